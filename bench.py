@@ -1,0 +1,185 @@
+"""Benchmark of the space-time BEM hot path on one MI355X.
+
+One step = the whole path of the method on one synthetic workload:
+assemble V_h, K_h, D_h and M_h^0 (FP64), form the right-hand side of eq.(4),
+solve with D_h-preconditioned GMRES in FP64, then solve again with FP32
+storage of V_h and D_h inside an FP64 iterative refinement.  Inputs are
+resident in HBM before the timed region.  Prints one JSON line.
+
+Default workload (the medium configuration): unit square, 256 boundary
+segments, 128 uniform time steps (N = 32768), alpha = 1, Omega_h 64^2 grid
+(8192 triangles), manufactured u = exp(k.x + |k|^2 t/alpha), k = (1, 0).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "entries/s (V_h,K_h,D_h) + precond. GMRES solve s to 1e-10, FP64 vs FP32-refined"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+# FP64 VALU operations per stored entry of each assembly kernel on the
+# medium workload, from the rocprofv3 FP64 instruction counters
+# (profiles/assembly_flops_medium.md); None until measured.
+FLOP_PER_ENTRY = {"V": None, "K": None, "D": None}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="medium")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="entries per operator for the oracle timing")
+    ap.add_argument("--tol", type=float, default=1e-12)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is a design "
+              "note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    import paper_1811_05224_amd as P
+    from paper_1811_05224_amd import _lib as L
+
+    wl = W.make(args.workload)
+    dev = torch.device("cuda:0")
+    ctx = P.Context.from_workload(wl, device=dev)
+    g = torch.as_tensor(wl.g, device=dev)
+    u0 = torch.as_tensor(wl.u0, device=dev)
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def step(record):
+        t = {}
+        e0, e1, e2, e3, e4, e5, e6, e7 = (ev() for _ in range(8))
+        e0.record(stream)
+        ctx.assemble(L.V)
+        e1.record(stream)
+        ctx.assemble(L.K)
+        e2.record(stream)
+        ctx.assemble(L.D)
+        e3.record(stream)
+        ctx.assemble(L.M0)
+        e4.record(stream)
+        f = ctx.rhs(g, u0)
+        e5.record(stream)
+        w64, i64 = ctx.solve(f, tol=args.tol, max_it=400)
+        e6.record(stream)
+        w32, i32 = ctx.solve(f, tol=args.tol, max_it=400, mode=L.FP32_IR, inner_tol=1e-5, max_outer=12,
+                             ir_tol=args.tol)
+        e7.record(stream)
+        torch.cuda.synchronize()
+        if record is not None:
+            record.append({"V": e0.elapsed_time(e1), "K": e1.elapsed_time(e2), "D": e2.elapsed_time(e3),
+                           "M0": e3.elapsed_time(e4), "rhs": e4.elapsed_time(e5), "solve64": e5.elapsed_time(e6),
+                           "solve32": e6.elapsed_time(e7), "i64": i64, "i32": i32})
+        return f, w64, w32
+
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        f, w64, w32 = step(rec)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+
+    entries = ctx.packed_entries            # per causal matrix
+    avg = {k: float(np.mean([r[k] for r in rec])) for k in ("V", "K", "D", "M0", "rhs", "solve64", "solve32")}
+    value = 3 * entries / (ms_per_step * 1e-3)
+
+    # GEMV rate on V_h (HBM-bound), HIP events on the launch stream
+    x = torch.randn(ctx.n, dtype=torch.float64, device=dev)
+    y = ctx.apply(L.V, x)
+    a, b = ev(), ev()
+    reps = 20
+    a.record(stream)
+    for _ in range(reps):
+        ctx.apply(L.V, x, out=y)
+    b.record(stream)
+    torch.cuda.synchronize()
+    gemv_ms = a.elapsed_time(b) / reps
+    gemv_gbs = entries * 8 / (gemv_ms * 1e-3) / 1e9
+
+    # accuracy: FP32-refined vs FP64 solution; both vs the exact flux projection
+    w64n, w32n = w64.cpu().numpy(), w32.cpu().numpy()
+    ir_vs_fp64 = float(np.linalg.norm(w32n - w64n) / np.linalg.norm(w64n))
+    disc64 = float(np.linalg.norm(w64n - wl.w_ref) / np.linalg.norm(wl.w_ref))
+
+    dominant = max(("V", "K", "D", "M0"), key=lambda k: avg[k])
+    if dominant != "M0" and FLOP_PER_ENTRY.get(dominant):
+        achieved = FLOP_PER_ENTRY[dominant] * entries / (avg[dominant] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "kernel": f"k_assemble<{dominant}>"}
+    else:
+        roof = {"bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
+                "traffic": None, "kernel": f"assembly of {dominant} (flop count not yet measured)"}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: N_Gamma={ctx.ng}, N_I={ctx.nt}, N={ctx.n}, M_Omega={ctx.nv}, "
+                               f"alpha={wl.alpha}, entries per causal matrix={entries}"},
+        "assembly_ms": {k: avg[k] for k in ("V", "K", "D", "M0")},
+        "assembly_entries_per_s": {k: entries / (avg[k] * 1e-3) for k in ("V", "K", "D")},
+        "rhs_ms": avg["rhs"],
+        "solve_s_fp64": avg["solve64"] * 1e-3, "solve_s_fp32_refined": avg["solve32"] * 1e-3,
+        "gmres_iters_fp64": rec[-1]["i64"].iters, "gmres_iters_fp32_inner_total": rec[-1]["i32"].iters,
+        "ir_outer_steps": rec[-1]["i32"].outer,
+        "true_relres_fp64": rec[-1]["i64"].true_relres, "true_relres_fp32_refined": rec[-1]["i32"].true_relres,
+        "fp32_refined_vs_fp64_rel_err": ir_vs_fp64, "discretisation_err_vs_exact_flux": disc64,
+        "gemv_V": {"ms": gemv_ms, "GB/s": gemv_gbs, "frac_hbm": gemv_gbs / HBM_PEAK_GBS},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(wl, nsamp):
+    """The oracle (long-double CPU code) on a bounded sample of the same
+    workload: random entries of V_h, K_h and D_h, all host cores."""
+    from oracle.oracle import Oracle
+    o = Oracle.from_workload(wl)
+    rng = np.random.default_rng(0)
+    ng, nt = wl.n_gamma, wl.n_t
+    n = nsamp or 3000
+    res = {}
+    total_e, total_s = 0, 0.0
+    for op, cnt in (("V", n), ("K", n), ("D", max(n // 10, 50))):
+        k = rng.integers(0, nt, cnt)
+        m = np.minimum(k, rng.integers(0, nt, cnt))
+        idx = np.stack([k, m, rng.integers(0, ng, cnt), rng.integers(0, ng, cnt)], 1)
+        t0 = time.perf_counter()
+        o.entries(op, idx)
+        dt = time.perf_counter() - t0
+        res[op] = cnt / dt
+        total_e += cnt
+        total_s += dt
+    # V, K, D weighted equally: entries of the three matrices per second
+    rate = 3.0 / sum(1.0 / res[op] for op in ("V", "K", "D"))
+    return {"value": rate, "unit": "entries/s", "cores": o.nthreads, "kind": "oracle",
+            "sample": f"{n} random V_h, {n} K_h, {max(n // 10, 50)} D_h entries of the same workload "
+                      f"({total_s:.1f} s); per-operator entries/s " + ", ".join(f"{k}={v:.0f}" for k, v in res.items())}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * stbem: space-time Galerkin boundary elements for the 2D heat equation on
+ * one AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * Method: Dohr, Merta, Of, Steinbach, Zapletal, "A parallel solver for a
+ * preconditioned space-time boundary element method for the heat equation"
+ * (arXiv:1811.05224).  Model problem eq.(1): alpha du/dt - Laplace u = 0 in
+ * Omega x (0,T), u = g on Gamma x (0,T), u(.,0) = u0.  The Neumann datum w
+ * solves the Galerkin system eq.(4)
+ *     V_h w = (1/2 M_h + K_h) g - M_h^0 u0
+ * with V_h (single layer, piecewise constants), K_h (double layer, trial
+ * functions continuous piecewise linear in space x constant in time), M_h
+ * (mass) and M_h^0 (initial potential on a triangulation of Omega).  GMRES is
+ * preconditioned with C_V^{-1} = Mt^{-1} D_h Mt^{-1} (Sec. 2, Theorem 1): D_h
+ * is the hypersingular operator on the dual mesh (integration-by-parts form)
+ * and Mt the lumped dual mass matrix (Sec. 4).
+ *
+ * Conventions
+ *   - Gamma_h: closed counter-clockwise polygon, segment i = [x_i, x_{i+1}],
+ *     outward normal (e_y, -e_x).  P1 node n is vertex x_n.  Dual node i is the
+ *     midpoint of segment i.
+ *   - Time elements tau_m = (t_m, t_{m+1}], m = 0..n_t-1, t_0 = 0.
+ *   - DOF order is time-major: l = m * n_bnd + i.  All vectors have
+ *     N = n_bnd * n_t entries (u0 has n_vtx entries) and are float64.
+ *   - V_h, K_h, D_h (and their alpha-derivatives) are causal: block (k, m) of
+ *     size n_bnd x n_bnd vanishes for m > k (Sec. 3, block lower triangular).
+ *     They are stored packed: block (k, m), k >= m, at element offset
+ *     (k (k+1)/2 + m) * n_bnd^2, row-major (row = test index i).
+ *   - M_h^0 is stored dense, row-major N x n_vtx.
+ *   - Pointers named *_dev are device pointers owned by the caller; host
+ *     inputs of stbem_create are copied.  `stream` is a hipStream_t (NULL =
+ *     the null stream); every call is stream-ordered unless stated.
+ *
+ * Errors: 0 on success, negative STBEM_E* on failure (nothing is changed),
+ * positive STBEM_WARN_* when a result was produced with a caveat.
+ * stbem_last_error() describes the last failure of a context.  No call
+ * throws or aborts.  A context is not thread-safe; use one per stream.
+ */
+#ifndef STBEM_H
+#define STBEM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stbem_ctx stbem_ctx;
+
+/* error codes */
+#define STBEM_OK 0
+#define STBEM_EINVAL (-1)         /* bad argument (null pointer, size, flag) */
+#define STBEM_EMESH (-2)          /* polygon not closed/CCW, zero-length segment, bad triangle */
+#define STBEM_EALPHA (-3)         /* alpha <= 0 or not finite */
+#define STBEM_ETIME (-4)          /* time nodes not strictly increasing from 0 */
+#define STBEM_ENOMEM (-5)         /* device allocation failed */
+#define STBEM_ENOTASSEMBLED (-6)  /* operator used before stbem_assemble */
+#define STBEM_EHIP (-7)           /* HIP runtime error (message in stbem_last_error) */
+#define STBEM_WARN_NOT_CONVERGED 1
+#define STBEM_WARN_IR_STAGNATION 2
+
+/* operators (bit mask for stbem_assemble, single value elsewhere) */
+#define STBEM_V 1u      /* single layer V_h                    (eq. 4) */
+#define STBEM_K 2u      /* double layer K_h                    (eq. 4) */
+#define STBEM_D 4u      /* hypersingular D_h on the dual mesh  (Sec. 2) */
+#define STBEM_M0 8u     /* initial potential M_h^0             (eq. 4) */
+#define STBEM_DV 16u    /* dV_h / d alpha */
+#define STBEM_DK 32u    /* dK_h / d alpha */
+#define STBEM_DM0 64u   /* dM_h^0 / d alpha */
+
+/* storage precision of V_h and D_h for the refinement solve */
+#define STBEM_FP64 0
+#define STBEM_FP32_IR 1
+
+typedef struct {
+    double alpha;              /* heat capacity constant, > 0              (eq. 1) */
+    int n_t;                   /* number of time elements                          */
+    const double* t_nodes;     /* host, n_t + 1 nodes, t_0 = 0 < t_1 < ... = T     */
+    int n_bnd;                 /* number of boundary segments (>= 3)               */
+    const double* bnd_xy;      /* host, 2 * n_bnd: CCW polygon vertices (x, y)      */
+    int n_vtx;                 /* vertices of Omega_h (0: no M_h^0)                */
+    const double* vtx_xy;      /* host, 2 * n_vtx                                  */
+    int n_tri;                 /* triangles of Omega_h                             */
+    const int* tri;            /* host, 3 * n_tri vertex indices, CCW              */
+} stbem_problem;
+
+/* Validate the problem, copy it to the device and build quadrature tables. */
+int stbem_create(const stbem_problem* prob, stbem_ctx** out);
+/* Free everything the context owns. Null is accepted. */
+int stbem_destroy(stbem_ctx* ctx);
+const char* stbem_last_error(const stbem_ctx* ctx);
+
+/* Device memory for the matrices: if set, the context obtains and returns
+ * its matrix storage through these callbacks (e.g. a framework's caching
+ * allocator); otherwise it uses hipMalloc/hipFree. */
+typedef void* (*stbem_alloc_fn)(size_t bytes, void* user);
+typedef void (*stbem_free_fn)(void* ptr, void* user);
+int stbem_set_allocator(stbem_ctx* ctx, stbem_alloc_fn alloc, stbem_free_fn release, void* user);
+
+/* Sizes: N, n_bnd, n_t, n_vtx, entries of one packed causal matrix. */
+int stbem_sizes(const stbem_ctx* ctx, long long* n, int* n_bnd, int* n_t, int* n_vtx, long long* packed_entries);
+
+/* Assemble the operators in `mask` (STBEM_V | ...) into context storage.
+ * Every entry is an exact-in-time (E1 closed form / Laguerre series) and
+ * fixed-rule-in-space Galerkin integral; blocks with tau_m after tau_k are
+ * never computed.  Re-assembling replaces the old storage. */
+int stbem_assemble(stbem_ctx* ctx, unsigned mask, void* stream);
+
+/* Device pointer and size in bytes of an assembled operator's storage
+ * (op is one of STBEM_V ... STBEM_DM0); owned by the context. */
+int stbem_matrix(stbem_ctx* ctx, unsigned op, const double** dev_ptr, size_t* bytes);
+
+/* y = A x (trans = 0) or y = A^T x (trans = 1) for an assembled operator
+ * (STBEM_V, STBEM_K, STBEM_D, STBEM_DV, STBEM_DK: N-vectors;
+ *  STBEM_M0, STBEM_DM0: x has n_vtx entries for trans = 0, N for trans = 1). */
+int stbem_apply(stbem_ctx* ctx, unsigned op, int trans, const double* x_dev, double* y_dev, void* stream);
+
+/* M_h g for g in X_h^{1,0} (trans = 0) or M_h^T x (trans = 1). */
+int stbem_mass(stbem_ctx* ctx, int trans, const double* x_dev, double* y_dev, void* stream);
+
+/* Preconditioner of Theorem 1 with the lumped mass of Sec. 4:
+ * z = Mt^{-1} D_h Mt^{-1} r (trans = 1: D_h^T). Needs STBEM_D. */
+int stbem_precondition(stbem_ctx* ctx, int trans, const double* r_dev, double* z_dev, void* stream);
+
+/* Right-hand side of eq.(4): f = (1/2 M_h + K_h) g - M_h^0 u0.
+ * Needs STBEM_K and STBEM_M0 (u0_dev may be NULL: u0 = 0, M_h^0 not needed). */
+int stbem_rhs(stbem_ctx* ctx, const double* g_dev, const double* u0_dev, double* f_dev, void* stream);
+
+/* FP32 copies for the refinement solve: V_h as a float pair hi + lo
+ * (hi = fl32(V), lo = fl32(V - hi)) and D_h as float.  Needs STBEM_V and
+ * STBEM_D; stbem_solve calls it on first use of STBEM_FP32_IR. */
+int stbem_prepare_ir(stbem_ctx* ctx, void* stream);
+
+typedef struct {
+    double tol;        /* stop when ||C (f - A w)|| <= tol ||C f|| (C: preconditioner) */
+    int max_it;        /* GMRES iterations (no restart); inner iterations for IR    */
+    int mode;          /* STBEM_FP64 or STBEM_FP32_IR                             */
+    int trans;         /* 1: solve V_h^T w = f (adjoint), preconditioned with D_h^T */
+    int precondition;  /* 0: plain GMRES                                          */
+    double inner_tol;  /* IR: relative tolerance of each inner FP32 solve         */
+    int max_outer;     /* IR: outer refinement steps                              */
+    double ir_tol;     /* IR: stop when ||f - V w|| <= ir_tol ||f|| (FP64 residual) */
+} stbem_solve_opts;
+
+typedef struct {
+    int iters;             /* GMRES iterations (IR: summed over inner solves)      */
+    int outer;             /* IR outer steps                                      */
+    double relres;         /* final preconditioned relative residual estimate     */
+    double true_relres;    /* ||f - V w|| / ||f|| computed in FP64 at the end     */
+} stbem_solve_info;
+
+/* Solve V_h w = f (or V_h^T w = f) with left-preconditioned GMRES, x0 = 0.
+ * Needs STBEM_V (and STBEM_D when preconditioned).  FP32_IR stores V_h and
+ * D_h in float32 for the inner solves and keeps the residual of the outer
+ * refinement, the Krylov basis and its orthogonalisation in float64.
+ * Synchronises the stream.  Returns STBEM_WARN_NOT_CONVERGED if tol was not
+ * reached (w holds the last iterate). */
+int stbem_solve(stbem_ctx* ctx, const double* f_dev, double* w_dev, const stbem_solve_opts* opts,
+                stbem_solve_info* info, void* stream);
+
+/* d J / d alpha contribution lambda^T (dK_h g - dM_h^0 u0 - dV_h w) for an
+ * adjoint state lambda (from a trans = 1 solve).  Needs STBEM_DV, STBEM_DK
+ * and, if u0_dev is not NULL, STBEM_DM0.  The scalar is written to
+ * out_dev[0] (device).  */
+int stbem_grad_alpha(stbem_ctx* ctx, const double* lambda_dev, const double* w_dev, const double* g_dev,
+                     const double* u0_dev, double* out_dev, void* stream);
+
+/* Sampled entries of V/K/D/dV/dK computed directly by the assembly kernels'
+ * device code (idx_dev: n quadruples (k, m, i, j) as int32; out_dev: n). */
+int stbem_entries(stbem_ctx* ctx, unsigned op, long long n, const int* idx_dev, double* out_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STBEM_H */

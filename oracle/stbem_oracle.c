@@ -15,7 +15,11 @@
  * Time integrals are exact: for a kernel kappa(t - tau) that vanishes for
  * t <= tau, int_{tau_k} int_{tau_m} kappa = F(t_{k+1}-t_m) - F(t_{k+1}-t_{m+1})
  *   - F(t_k - t_m) + F(t_k - t_{m+1}) with F the second antiderivative
- * (F = 0 for arguments <= 0; that is causality).  With a = alpha r^2 / 4:
+ * (F = 0 for arguments <= 0; that is causality).  This closed form is used
+ * for touching elements (k - m <= 1); for separated elements the same double
+ * integral is taken directly, as a Gauss rule in the lag t - tau against the
+ * trapezoid weight, which avoids the cancellation of the four-point
+ * difference.  With a = alpha r^2 / 4:
  *   F_V(d) = [(d + a) E1(a/d) - d e^{-a/d}] / (4 pi)     single layer
  *   F_K(d) =  d e^{-a/d} - a E1(a/d)   (times (x-y).n_y / (2 pi r^2))
  *   F_D(d) =  E1(a/d) / (4 pi)         first antiderivative, used with the
@@ -95,9 +99,48 @@ static R delta4(R (*F)(R, R), R a, const TB* b)
     return F(a, b->tk1 - b->tm0) - F(a, b->tk1 - b->tm1) - F(a, b->tk0 - b->tm0) + F(a, b->tk0 - b->tm1);
 }
 
+/* Separated time elements (tau_k after tau_m with a gap): the double time
+ * integral itself, int_{tau_k} int_{tau_m} kappa(t - tau) = int w(s) kappa(s) ds,
+ * w(s) = |tau_k intersected with (tau_m + s)| (a trapezoid), by Gauss-Legendre on
+ * the three linear pieces of w.  kappa is smooth there (s >= gap > 0), and
+ * unlike the four-point difference of antiderivatives nothing cancels.
+ * kind: 0 k, 1 a e^{-a/s}/s^2 (F_K''), 2 d/ds k, 3 d/dalpha k (times alpha),
+ *       4 (e^{-a/s}/s)' = E1(a/s)'' */
+static R kappa(int kind, R a, R s)
+{
+    R x = expl(-a / s);
+    switch (kind) {
+    case 0: return x / (4 * PI_L * s);
+    case 1: return a * x / (s * s);
+    case 2: return x * (a - s) / (4 * PI_L * s * s * s);
+    case 3: return -(a / s) * x / (4 * PI_L * s);
+    case 4: return x * (a - s) / (s * s * s);
+    }
+    return NAN;
+}
+
+#define TQ_N 20
+static R gl_x[33][32], gl_w[33][32];
+static R tquad(int kind, R a, const TB* b)
+{
+    R br[4] = {b->tk0 - b->tm1, b->tk0 - b->tm0, b->tk1 - b->tm1, b->tk1 - b->tm0};
+    for (int i = 1; i < 4; ++i)
+        for (int j = i; j > 0 && br[j] < br[j - 1]; --j) { R t = br[j]; br[j] = br[j - 1]; br[j - 1] = t; }
+    R sum = 0;
+    for (int p = 0; p < 3; ++p) {
+        R lo = br[p], hi = br[p + 1];
+        if (!(hi > lo)) continue;
+        for (int q = 0; q < TQ_N; ++q) {
+            R s = lo + (hi - lo) * gl_x[TQ_N][q];
+            R w = fminl(b->tk1, b->tm1 + s) - fmaxl(b->tk0, b->tm0 + s);
+            if (w > 0) sum += (hi - lo) * gl_w[TQ_N][q] * w * kappa(kind, a, s);
+        }
+    }
+    return sum;
+}
+
 /* ------------------------------------------------ Gauss-Legendre nodes */
-#define GL_MAX 32
-static R gl_x[GL_MAX + 1][GL_MAX], gl_w[GL_MAX + 1][GL_MAX];     /* on [0,1] */
+#define GL_MAX 32     /* gl_x, gl_w: [GL_MAX + 1][GL_MAX] nodes/weights on [0,1] */
 
 __attribute__((constructor)) static void gl_init(void)
 {
@@ -329,25 +372,26 @@ static void kern(const KC* c, R sP, R sQ, R dx, R dy, R* out)
 {
     R r2 = dx * dx + dy * dy;
     R a = c->pr->alpha * r2 / 4;
+    int sep = c->tb.d >= 2;      /* separated time elements: integrate in time */
     switch (c->op) {
     case OP_V:
-        out[0] = delta4(FV, a, &c->tb);
+        out[0] = sep ? tquad(0, a, &c->tb) : delta4(FV, a, &c->tb);
         break;
     case OP_DV:
-        out[0] = delta4(FdV, a, &c->tb) / c->pr->alpha;
+        out[0] = (sep ? tquad(3, a, &c->tb) : delta4(FdV, a, &c->tb)) / c->pr->alpha;
         break;
     case OP_K: {
-        R g = (dx * c->Q->nx + dy * c->Q->ny) / (2 * PI_L * r2) * delta4(FK, a, &c->tb);
+        R g = (dx * c->Q->nx + dy * c->Q->ny) / (2 * PI_L * r2) * (sep ? tquad(1, a, &c->tb) : delta4(FK, a, &c->tb));
         R l1 = sQ / c->Q->L;
         out[0] = g * (1 - l1); out[1] = g * l1;
         break; }
     case OP_DK: {
-        R g = -(dx * c->Q->nx + dy * c->Q->ny) / (8 * PI_L) * delta4(FE, a, &c->tb);
+        R g = -(dx * c->Q->nx + dy * c->Q->ny) / (8 * PI_L) * (sep ? tquad(4, a, &c->tb) : delta4(FE, a, &c->tb));
         R l1 = sQ / c->Q->L;
         out[0] = g * (1 - l1); out[1] = g * l1;
         break; }
     case OP_D: {
-        R fv = delta4(FV, a, &c->tb), fd = delta4(FD, a, &c->tb);
+        R fv = sep ? tquad(0, a, &c->tb) : delta4(FV, a, &c->tb), fd = sep ? tquad(2, a, &c->tb) : delta4(FD, a, &c->tb);
         R p1 = sP / c->P->L, q1 = sQ / c->Q->L;
         out[0] = fv;
         out[1] = fd * (1 - p1) * (1 - q1); out[2] = fd * (1 - p1) * q1;
@@ -753,12 +797,13 @@ double or_time_integral(const or_problem* h, int which, double r, int k, int m)
     const Prob* p = h->p;
     TB b = time_block(p, k, m);
     R a = p->alpha * (R)r * (R)r / 4;
+    int sep = b.d >= 2;
     switch (which) {
-    case 0: return (double)delta4(FV, a, &b);
-    case 1: return (double)delta4(FK, a, &b);
-    case 2: return (double)delta4(FD, a, &b);
-    case 3: return (double)(delta4(FdV, a, &b) / p->alpha);
-    case 4: return (double)delta4(FE, a, &b);
+    case 0: return (double)(sep ? tquad(0, a, &b) : delta4(FV, a, &b));
+    case 1: return (double)(sep ? tquad(1, a, &b) : delta4(FK, a, &b));
+    case 2: return (double)(sep ? tquad(2, a, &b) : delta4(FD, a, &b));
+    case 3: return (double)((sep ? tquad(3, a, &b) : delta4(FdV, a, &b)) / p->alpha);
+    case 4: return (double)(sep ? tquad(4, a, &b) : delta4(FE, a, &b));
     }
     return NAN;
 }

@@ -1,0 +1,1137 @@
+// stbem: HIP kernels for gfx950 and the host runtime behind include/stbem.h.
+//
+// Assembly (VALU-bound): one workgroup = one 16 x 16 tile of one causal
+// block (k, m), k >= m; the upper blocks are never launched.  The quadrature
+// tables and the time-block data (lags, series moments) live in LDS; each lane
+// computes one entry and the lanes of a row store consecutive doubles.
+// GEMV (HBM-bound): pass 1 computes one partial vector per stored block
+// (a wavefront per row for A x, a lane per column for A^T x), pass 2 adds the
+// partials of a block row (or column) in a fixed order, so results are
+// bitwise reproducible.  GMRES keeps the Krylov basis in HBM; the small
+// Hessenberg least-squares problem is solved on the host.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "stbem_m0.h"
+#include "stbem_tables.h"
+#include "../../include/stbem.h"
+
+using namespace stbem;
+
+// ============================================================== kernels
+namespace {
+
+constexpr int kTile = 16;
+constexpr int kWG = 256;
+
+__device__ __forceinline__ void block_of(long long b, int& k, int& m)
+{
+    // b = k (k + 1) / 2 + m, 0 <= m <= k
+    double s = sqrt(8.0 * (double)b + 1.0);
+    long long kk = (long long)((s - 1.0) * 0.5);
+    while (kk * (kk + 1) / 2 > b) --kk;
+    while ((kk + 1) * (kk + 2) / 2 <= b) ++kk;
+    k = (int)kk;
+    m = (int)(b - kk * (kk + 1) / 2);
+}
+
+enum Store { ST_F64 = 0, ST_F32 = 1, ST_HILO = 2 };
+
+template <int OP, int ST>
+__global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restrict__ Tg, Orders O,
+                                                  double lmax, long long nblk, int tiles_1d,
+                                                  double* __restrict__ out64, float* __restrict__ hi,
+                                                  float* __restrict__ lo)
+{
+    __shared__ Tables T;
+    __shared__ TimeBlock tb;
+    __shared__ int qf;
+    const int tid = threadIdx.x;
+    {
+        const double* src = reinterpret_cast<const double*>(Tg);
+        double* dst = reinterpret_cast<double*>(&T);
+        for (int e = tid; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
+    }
+    const long long tiles = (long long)tiles_1d * tiles_1d;
+    const long long b = blockIdx.x / tiles;
+    const int tile = (int)(blockIdx.x % tiles);
+    int k, m;
+    block_of(b, k, m);
+    if (tid == 0) {
+        time_block(g, k, m, tb);
+        qf = q_block(OP, lmax, block_min_lag(g.t, k, m), g.alpha);
+    }
+    __syncthreads();
+    const int i = (tile / tiles_1d) * kTile + tid / kTile;
+    const int j = (tile % tiles_1d) * kTile + tid % kTile;
+    if (i >= g.ng || j >= g.ng) return;
+    double v = entry<OP>(T, O, g, tb, qf, i, j);
+    const long long off = b * (long long)g.ng * g.ng + (long long)i * g.ng + j;
+    if (ST == ST_F64) out64[off] = v;
+    else {
+        float h = (float)v;
+        hi[off] = h;
+        if (ST == ST_HILO) lo[off] = (float)(v - (double)h);
+    }
+}
+
+template <int OP>
+__global__ __launch_bounds__(kWG) void k_entries(Geom g, const Tables* __restrict__ Tg, Orders O, double lmax,
+                                                 long long n, const int* __restrict__ idx, double* __restrict__ out)
+{
+    __shared__ Tables T;
+    {
+        const double* src = reinterpret_cast<const double*>(Tg);
+        double* dst = reinterpret_cast<double*>(&T);
+        for (int e = threadIdx.x; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
+    }
+    __syncthreads();
+    long long e = (long long)blockIdx.x * kWG + threadIdx.x;
+    if (e >= n) return;
+    int k = idx[4 * e], m = idx[4 * e + 1], i = idx[4 * e + 2], j = idx[4 * e + 3];
+    if (k < m) { out[e] = 0.0; return; }
+    TimeBlock tb;
+    time_block(g, k, m, tb);
+    int qf = q_block(OP, lmax, block_min_lag(g.t, k, m), g.alpha);
+    out[e] = entry<OP>(T, O, g, tb, qf, i, j);
+}
+
+template <bool DERIV>
+__global__ __launch_bounds__(kWG) void k_m0(Geom g, Mesh2 mesh, const Tables* __restrict__ Tg, const M0Tables* __restrict__ Dg,
+                                            M0Orders MO, int nchunk, double* __restrict__ out)
+{
+    __shared__ Tables T;
+    __shared__ M0Tables D;
+    {
+        const double* src = reinterpret_cast<const double*>(Tg);
+        double* dst = reinterpret_cast<double*>(&T);
+        for (int e = threadIdx.x; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
+        const double* s2 = reinterpret_cast<const double*>(Dg);
+        double* d2 = reinterpret_cast<double*>(&D);
+        for (int e = threadIdx.x; e < (int)(sizeof(M0Tables) / sizeof(double)); e += kWG) d2[e] = s2[e];
+    }
+    __syncthreads();
+    const long long row = blockIdx.x / nchunk;           // row = k * ng + i
+    const int j = (int)(blockIdx.x % nchunk) * kWG + threadIdx.x;
+    if (j >= mesh.nv) return;
+    const int k = (int)(row / g.ng), i = (int)(row % g.ng);
+    // k >= 1: smooth kernel on the time scale sqrt(4 t_k / alpha);
+    // k = 0: triangles away from the segment see a log kernel at distance >= 2 sizes
+    int qs = 8;
+    if (k > 0) {
+        qs = q_time(fmax(g.len[i], MO.omax), g.t[k], g.alpha) + 1;
+        qs = qs < 4 ? 4 : qs;
+    }
+    out[row * (long long)mesh.nv + j] = m0_entry<DERIV>(T, D, MO, g, mesh, k, i, j, qs, qs);
+}
+
+// ---------------------------------------------------------------- GEMV
+template <class T>
+__device__ __forceinline__ double ld(const T* p, long long o) { return (double)p[o]; }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// partial[b][i] = sum_j A_b[i][j] x_m[j]: 4 waves x 4 rows per workgroup
+template <class T>
+__global__ __launch_bounds__(kWG) void k_gemv_n_part(const T* __restrict__ A, const T* __restrict__ A2,
+                                                     const double* __restrict__ x, double* __restrict__ part,
+                                                     int ng, int rowchunks)
+{
+    const long long b = blockIdx.x / rowchunks;
+    const int rc = (int)(blockIdx.x % rowchunks);
+    int k, m;
+    block_of(b, k, m);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long base = b * (long long)ng * ng;
+    const double* xm = x + (long long)m * ng;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int i = rc * 16 + wave * 4 + rr;
+        if (i >= ng) break;
+        const long long ro = base + (long long)i * ng;
+        double s = 0.0;
+        for (int j = lane; j < ng; j += 64) {
+            double a = ld(A, ro + j);
+            if (A2) a += ld(A2, ro + j);
+            s += a * xm[j];
+        }
+        s = wave_sum(s);
+        if (lane == 0) part[b * ng + i] = s;
+    }
+}
+
+// partial[b][j] = sum_i A_b[i][j] x_k[i]: 64 columns x 4 row groups
+template <class T>
+__global__ __launch_bounds__(kWG) void k_gemv_t_part(const T* __restrict__ A, const T* __restrict__ A2,
+                                                     const double* __restrict__ x, double* __restrict__ part,
+                                                     int ng, int colchunks)
+{
+    __shared__ double red[4][64];
+    const long long b = blockIdx.x / colchunks;
+    const int cc = (int)(blockIdx.x % colchunks);
+    int k, m;
+    block_of(b, k, m);
+    const int grp = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j = cc * 64 + lane;
+    const long long base = b * (long long)ng * ng;
+    const double* xk = x + (long long)k * ng;
+    double s = 0.0;
+    if (j < ng)
+        for (int i = grp; i < ng; i += 4) {
+            double a = ld(A, base + (long long)i * ng + j);
+            if (A2) a += ld(A2, base + (long long)i * ng + j);
+            s += a * xk[i];
+        }
+    red[grp][lane] = s;
+    __syncthreads();
+    if (grp == 0 && j < ng) part[b * ng + j] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// FP32 storage, FP32 accumulation (inner solves of the refinement)
+__global__ __launch_bounds__(kWG) void k_gemv_n_part32(const float* __restrict__ A, const double* __restrict__ x,
+                                                       double* __restrict__ part, int ng, int rowchunks)
+{
+    const long long b = blockIdx.x / rowchunks;
+    const int rc = (int)(blockIdx.x % rowchunks);
+    int k, m;
+    block_of(b, k, m);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long base = b * (long long)ng * ng;
+    const double* xm = x + (long long)m * ng;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int i = rc * 16 + wave * 4 + rr;
+        if (i >= ng) break;
+        const long long ro = base + (long long)i * ng;
+        float s = 0.0f;
+        for (int j = lane; j < ng; j += 64) s += A[ro + j] * (float)xm[j];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (lane == 0) part[b * ng + i] = (double)s;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_gemv_t_part32(const float* __restrict__ A, const double* __restrict__ x,
+                                                       double* __restrict__ part, int ng, int colchunks)
+{
+    __shared__ float red[4][64];
+    const long long b = blockIdx.x / colchunks;
+    const int cc = (int)(blockIdx.x % colchunks);
+    int k, m;
+    block_of(b, k, m);
+    const int grp = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j = cc * 64 + lane;
+    const long long base = b * (long long)ng * ng;
+    const double* xk = x + (long long)k * ng;
+    float s = 0.0f;
+    if (j < ng)
+        for (int i = grp; i < ng; i += 4) s += A[base + (long long)i * ng + j] * (float)xk[i];
+    red[grp][lane] = s;
+    __syncthreads();
+    if (grp == 0 && j < ng) part[b * ng + j] = (double)(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
+}
+
+// y[k][i] = sum_{m<=k} part[b(k,m)][i]  (trans: y[m][j] = sum_{k>=m} part[b(k,m)][j])
+__global__ __launch_bounds__(kWG) void k_gemv_reduce(const double* __restrict__ part, double* __restrict__ y,
+                                                     int ng, int nt, int trans)
+{
+    long long e = (long long)blockIdx.x * kWG + threadIdx.x;
+    if (e >= (long long)ng * nt) return;
+    int blk = (int)(e / ng), i = (int)(e % ng);
+    double s = 0.0;
+    if (!trans) {
+        const long long b0 = (long long)blk * (blk + 1) / 2;
+        for (int m = 0; m <= blk; ++m) s += part[(b0 + m) * ng + i];
+    } else {
+        for (int k = blk; k < nt; ++k) s += part[((long long)k * (k + 1) / 2 + blk) * ng + i];
+    }
+    y[e] = s;
+}
+
+// dense row-major M (rows x cols): y = M x (a wavefront per row)
+__global__ __launch_bounds__(kWG) void k_dense_n(const double* __restrict__ M, const double* __restrict__ x,
+                                                 double* __restrict__ y, long long rows, int cols)
+{
+    const long long r = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= rows) return;
+    double s = 0.0;
+    for (int c = lane; c < cols; c += 64) s += M[r * cols + c] * x[c];
+    s = wave_sum(s);
+    if (lane == 0) y[r] = s;
+}
+
+// partials of y = M^T x over row chunks of 256
+__global__ __launch_bounds__(kWG) void k_dense_t_part(const double* __restrict__ M, const double* __restrict__ x,
+                                                      double* __restrict__ part, long long rows, int cols, int colchunks)
+{
+    const long long rc = blockIdx.x / colchunks;
+    const int c = (int)(blockIdx.x % colchunks) * kWG + threadIdx.x;
+    if (c >= cols) return;
+    double s = 0.0;
+    const long long r0 = rc * 256, r1 = r0 + 256 < rows ? r0 + 256 : rows;
+    for (long long r = r0; r < r1; ++r) s += M[r * cols + c] * x[r];
+    part[rc * cols + c] = s;
+}
+
+__global__ __launch_bounds__(kWG) void k_dense_t_reduce(const double* __restrict__ part, double* __restrict__ y,
+                                                        int nrc, int cols)
+{
+    const int c = blockIdx.x * kWG + threadIdx.x;
+    if (c >= cols) return;
+    double s = 0.0;
+    for (int r = 0; r < nrc; ++r) s += part[(long long)r * cols + c];
+    y[c] = s;
+}
+
+// ------------------------------------------------------- vector kernels
+// (M g)[(k,i)] = h_k L_i / 2 (g[(k,i)] + g[(k,i+1)]);
+// (M^T x)[(k,n)] = h_k / 2 (L_n x[(k,n)] + L_{n-1} x[(k,n-1)])
+__global__ __launch_bounds__(kWG) void k_mass(const double* __restrict__ t, const double* __restrict__ len,
+                                              const double* __restrict__ x, double* __restrict__ y, int ng, int nt,
+                                              int trans, double scale, const double* __restrict__ addto)
+{
+    long long e = (long long)blockIdx.x * kWG + threadIdx.x;
+    if (e >= (long long)ng * nt) return;
+    int k = (int)(e / ng), i = (int)(e % ng);
+    double h = t[k + 1] - t[k];
+    double v;
+    if (!trans) {
+        int ip = i + 1 == ng ? 0 : i + 1;
+        v = 0.5 * h * len[i] * (x[(long long)k * ng + i] + x[(long long)k * ng + ip]);
+    } else {
+        int im = i == 0 ? ng - 1 : i - 1;
+        v = 0.5 * h * (len[i] * x[(long long)k * ng + i] + len[im] * x[(long long)k * ng + im]);
+    }
+    y[e] = scale * v + (addto ? addto[e] : 0.0);
+}
+
+// y = a * x + b * y
+__global__ __launch_bounds__(kWG) void k_axpby(long long n, double a, const double* __restrict__ x, double b,
+                                               double* __restrict__ y)
+{
+    long long e = (long long)blockIdx.x * kWG + threadIdx.x;
+    if (e < n) y[e] = a * x[e] + (b == 0.0 ? 0.0 : b * y[e]);
+}
+
+// y = x / d
+__global__ __launch_bounds__(kWG) void k_div(long long n, const double* __restrict__ x, const double* __restrict__ d,
+                                             double* __restrict__ y)
+{
+    long long e = (long long)blockIdx.x * kWG + threadIdx.x;
+    if (e < n) y[e] = x[e] / d[e];
+}
+
+// partial dot products: part[q * nchunk + c] = sum over chunk c of Q_q . v
+constexpr int kDotChunk = 4096;
+__global__ __launch_bounds__(kWG) void k_dots_part(const double* __restrict__ Q, long long ldq,
+                                                   const double* __restrict__ v, long long n,
+                                                   double* __restrict__ part, int nchunk)
+{
+    __shared__ double red[kWG / 64];
+    const int c = blockIdx.x, q = blockIdx.y;
+    const double* qq = Q + (long long)q * ldq;
+    long long e0 = (long long)c * kDotChunk;
+    long long e1 = e0 + kDotChunk < n ? e0 + kDotChunk : n;
+    double s = 0.0;
+    for (long long e = e0 + threadIdx.x; e < e1; e += kWG) s += qq[e] * v[e];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(long long)q * nchunk + c] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ __launch_bounds__(kWG) void k_dots_reduce(const double* __restrict__ part, int nchunk, int nq,
+                                                     double* __restrict__ out)
+{
+    int q = blockIdx.x * kWG + threadIdx.x;
+    if (q >= nq) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunk; ++c) s += part[(long long)q * nchunk + c];
+    out[q] = s;
+}
+
+// v -= sum_q Q_q h_q
+__global__ __launch_bounds__(kWG) void k_basis_sub(const double* __restrict__ Q, long long ldq, int nq,
+                                                   const double* __restrict__ h, double* __restrict__ v, long long n)
+{
+    long long e = (long long)blockIdx.x * kWG + threadIdx.x;
+    if (e >= n) return;
+    double s = 0.0;
+    for (int q = 0; q < nq; ++q) s += Q[(long long)q * ldq + e] * h[q];
+    v[e] -= s;
+}
+
+// w = sum_q Q_q y_q (+ w if accumulate)
+__global__ __launch_bounds__(kWG) void k_basis_comb(const double* __restrict__ Q, long long ldq, int nq,
+                                                    const double* __restrict__ y, double* __restrict__ w, long long n,
+                                                    int accumulate)
+{
+    long long e = (long long)blockIdx.x * kWG + threadIdx.x;
+    if (e >= n) return;
+    double s = accumulate ? w[e] : 0.0;
+    for (int q = 0; q < nq; ++q) s += Q[(long long)q * ldq + e] * y[q];
+    w[e] = s;
+}
+
+// FP64 -> hi/lo FP32 split, FP64 -> FP32
+__global__ __launch_bounds__(kWG) void k_split(long long n, const double* __restrict__ a, float* __restrict__ hi,
+                                               float* __restrict__ lo)
+{
+    long long e = (long long)blockIdx.x * kWG + threadIdx.x;
+    if (e >= n) return;
+    double v = a[e];
+    float h = (float)v;
+    hi[e] = h;
+    if (lo) lo[e] = (float)(v - (double)h);
+}
+
+}  // namespace
+
+// ============================================================ host side
+struct stbem_ctx {
+    int ng = 0, nt = 0, nv = 0, ntri = 0;
+    long long n = 0, nblk = 0, packed = 0;
+    double alpha = 0, lmax = 0;
+    std::vector<double> t, vx, vy, ex, ey, len, ox, oy;
+    std::vector<int> tri, v2t_ptr, v2t;
+    // device copies
+    double *d_t = nullptr, *d_vx = nullptr, *d_vy = nullptr, *d_ex = nullptr, *d_ey = nullptr, *d_len = nullptr;
+    double *d_ox = nullptr, *d_oy = nullptr, *d_mt = nullptr;
+    int *d_tri = nullptr, *d_v2t_ptr = nullptr, *d_v2t = nullptr;
+    Tables* d_tab = nullptr;
+    M0Tables* d_m0tab = nullptr;
+    Orders ord;
+    M0Orders m0ord;
+    // operators
+    double* mat[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};   // V K D M0 DV DK DM0
+    size_t mat_bytes[7] = {0, 0, 0, 0, 0, 0, 0};
+    float *v_hi = nullptr, *v_lo = nullptr, *d_32 = nullptr;
+    // work
+    double* part = nullptr;     // nblk * ng
+    size_t part_bytes = 0;
+    stbem_alloc_fn alloc = nullptr;
+    stbem_free_fn release = nullptr;
+    void* user = nullptr;
+    std::string err;
+};
+
+namespace {
+
+int fail(stbem_ctx* c, int code, const char* fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(c, expr)                                                                         \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return fail((c), STBEM_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int op_slot(unsigned op)
+{
+    switch (op) {
+    case STBEM_V: return 0;
+    case STBEM_K: return 1;
+    case STBEM_D: return 2;
+    case STBEM_M0: return 3;
+    case STBEM_DV: return 4;
+    case STBEM_DK: return 5;
+    case STBEM_DM0: return 6;
+    }
+    return -1;
+}
+
+void* dev_alloc(stbem_ctx* c, size_t bytes)
+{
+    if (bytes == 0) bytes = 8;
+    if (c->alloc) return c->alloc(bytes, c->user);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+    return p;
+}
+
+void dev_free(stbem_ctx* c, void* p)
+{
+    if (!p) return;
+    if (c->release) c->release(p, c->user);
+    else (void)hipFree(p);
+}
+
+template <class T>
+int upload(stbem_ctx* c, T** dst, const std::vector<T>& src)
+{
+    size_t bytes = src.size() * sizeof(T);
+    if (hipMalloc((void**)dst, bytes ? bytes : 8) != hipSuccess) return fail(c, STBEM_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+    if (bytes) HIPCHK(c, hipMemcpy(*dst, src.data(), bytes, hipMemcpyHostToDevice));
+    return 0;
+}
+
+Geom geom(const stbem_ctx* c)
+{
+    Geom g;
+    g.ng = c->ng; g.nt = c->nt; g.alpha = c->alpha;
+    g.vx = c->d_vx; g.vy = c->d_vy; g.ex = c->d_ex; g.ey = c->d_ey; g.len = c->d_len; g.t = c->d_t;
+    return g;
+}
+
+Mesh2 mesh(const stbem_ctx* c)
+{
+    Mesh2 m;
+    m.nv = c->nv; m.ntri = c->ntri; m.ox = c->d_ox; m.oy = c->d_oy; m.tri = c->d_tri;
+    m.v2t_ptr = c->d_v2t_ptr; m.v2t = c->d_v2t;
+    return m;
+}
+
+inline unsigned grid1(long long n) { return (unsigned)((n + kWG - 1) / kWG); }
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int ensure_part(stbem_ctx* c)
+{
+    size_t need = (size_t)c->nblk * c->ng * sizeof(double);
+    size_t need_dense = 0;
+    if (c->nv > 0) need_dense = (size_t)((c->n + 255) / 256) * c->nv * sizeof(double);
+    if (need_dense > need) need = need_dense;
+    if (c->part && c->part_bytes >= need) return 0;
+    if (c->part) (void)hipFree(c->part);
+    c->part = nullptr;
+    if (hipMalloc((void**)&c->part, need) != hipSuccess) { (void)hipGetLastError(); return fail(c, STBEM_ENOMEM, "work buffer of %zu bytes", need); }
+    c->part_bytes = need;
+    return 0;
+}
+
+template <int OP>
+int launch_assemble(stbem_ctx* c, int store, double* o64, float* hi, float* lo, hipStream_t s)
+{
+    int t1 = (c->ng + kTile - 1) / kTile;
+    long long nwg = c->nblk * (long long)t1 * t1;
+    if (nwg > 0x7fffffffLL) return fail(c, STBEM_EINVAL, "problem too large for one launch");
+    Geom g = geom(c);
+    if (store == ST_F64)
+        hipLaunchKernelGGL((k_assemble<OP, ST_F64>), dim3((unsigned)nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, c->nblk, t1, o64, hi, lo);
+    else if (store == ST_F32)
+        hipLaunchKernelGGL((k_assemble<OP, ST_F32>), dim3((unsigned)nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, c->nblk, t1, o64, hi, lo);
+    else
+        hipLaunchKernelGGL((k_assemble<OP, ST_HILO>), dim3((unsigned)nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, c->nblk, t1, o64, hi, lo);
+    HIPCHK(c, hipGetLastError());
+    return 0;
+}
+
+int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
+{
+    int slot = op_slot(op);
+    size_t bytes = (op == STBEM_M0 || op == STBEM_DM0) ? (size_t)c->n * c->nv * sizeof(double)
+                                                      : (size_t)c->packed * sizeof(double);
+    if ((op == STBEM_M0 || op == STBEM_DM0) && c->nv == 0) return fail(c, STBEM_EINVAL, "no Omega mesh for M0");
+    if (c->mat[slot] && c->mat_bytes[slot] != bytes) { dev_free(c, c->mat[slot]); c->mat[slot] = nullptr; }
+    if (!c->mat[slot]) {
+        c->mat[slot] = (double*)dev_alloc(c, bytes);
+        if (!c->mat[slot]) return fail(c, STBEM_ENOMEM, "allocation of %zu bytes for operator %u failed", bytes, op);
+        c->mat_bytes[slot] = bytes;
+    }
+    double* o = c->mat[slot];
+    switch (op) {
+    case STBEM_V: return launch_assemble<OP_V>(c, ST_F64, o, nullptr, nullptr, s);
+    case STBEM_K: return launch_assemble<OP_K>(c, ST_F64, o, nullptr, nullptr, s);
+    case STBEM_D: return launch_assemble<OP_D>(c, ST_F64, o, nullptr, nullptr, s);
+    case STBEM_DV: return launch_assemble<OP_DV>(c, ST_F64, o, nullptr, nullptr, s);
+    case STBEM_DK: return launch_assemble<OP_DK>(c, ST_F64, o, nullptr, nullptr, s);
+    case STBEM_M0:
+    case STBEM_DM0: {
+        int nchunk = (c->nv + kWG - 1) / kWG;
+        long long nwg = c->n * nchunk;
+        if (nwg > 0x7fffffffLL) return fail(c, STBEM_EINVAL, "M0 too large for one launch");
+        if (op == STBEM_M0)
+            hipLaunchKernelGGL((k_m0<false>), dim3((unsigned)nwg), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, nchunk, o);
+        else
+            hipLaunchKernelGGL((k_m0<true>), dim3((unsigned)nwg), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, nchunk, o);
+        HIPCHK(c, hipGetLastError());
+        return 0;
+    }
+    }
+    return fail(c, STBEM_EINVAL, "unknown operator %u", op);
+}
+
+// y = A x for packed causal storage (FP64, or hi+lo FP32 pair, or FP32)
+int packed_apply(stbem_ctx* c, const double* A, const float* hi, const float* lo, const float* a32, int trans,
+                 const double* x, double* y, hipStream_t s)
+{
+    int rc = ensure_part(c);
+    if (rc) return rc;
+    if (!trans) {
+        int rowchunks = (c->ng + 15) / 16;
+        unsigned nwg = (unsigned)(c->nblk * rowchunks);
+        if (A) hipLaunchKernelGGL((k_gemv_n_part<double>), dim3(nwg), dim3(kWG), 0, s, A, (const double*)nullptr, x, c->part, c->ng, rowchunks);
+        else if (hi) hipLaunchKernelGGL((k_gemv_n_part<float>), dim3(nwg), dim3(kWG), 0, s, hi, lo, x, c->part, c->ng, rowchunks);
+        else hipLaunchKernelGGL(k_gemv_n_part32, dim3(nwg), dim3(kWG), 0, s, a32, x, c->part, c->ng, rowchunks);
+    } else {
+        int colchunks = (c->ng + 63) / 64;
+        unsigned nwg = (unsigned)(c->nblk * colchunks);
+        if (A) hipLaunchKernelGGL((k_gemv_t_part<double>), dim3(nwg), dim3(kWG), 0, s, A, (const double*)nullptr, x, c->part, c->ng, colchunks);
+        else if (hi) hipLaunchKernelGGL((k_gemv_t_part<float>), dim3(nwg), dim3(kWG), 0, s, hi, lo, x, c->part, c->ng, colchunks);
+        else hipLaunchKernelGGL(k_gemv_t_part32, dim3(nwg), dim3(kWG), 0, s, a32, x, c->part, c->ng, colchunks);
+    }
+    HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(k_gemv_reduce, dim3(grid1(c->n)), dim3(kWG), 0, s, c->part, y, c->ng, c->nt, trans);
+    HIPCHK(c, hipGetLastError());
+    return 0;
+}
+
+int dense_apply(stbem_ctx* c, const double* M, int trans, const double* x, double* y, hipStream_t s)
+{
+    if (!trans) {
+        hipLaunchKernelGGL(k_dense_n, dim3((unsigned)((c->n + 3) / 4)), dim3(kWG), 0, s, M, x, y, c->n, c->nv);
+    } else {
+        int rc = ensure_part(c);
+        if (rc) return rc;
+        int nrc = (int)((c->n + 255) / 256), colchunks = (c->nv + kWG - 1) / kWG;
+        hipLaunchKernelGGL(k_dense_t_part, dim3((unsigned)((long long)nrc * colchunks)), dim3(kWG), 0, s, M, x, c->part, c->n, c->nv, colchunks);
+        hipLaunchKernelGGL(k_dense_t_reduce, dim3((unsigned)colchunks), dim3(kWG), 0, s, c->part, y, nrc, c->nv);
+    }
+    HIPCHK(c, hipGetLastError());
+    return 0;
+}
+
+// dot products of the nq vectors Q_q (stride ldq) with v, into h_dev[0..nq)
+struct DotWork { double* part = nullptr; int nchunk = 0; };
+
+int dots(stbem_ctx* c, DotWork& w, const double* Q, long long ldq, int nq, const double* v, double* h_dev, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dots_part, dim3((unsigned)w.nchunk, (unsigned)nq), dim3(kWG), 0, s, Q, ldq, v, c->n, w.part, w.nchunk);
+    hipLaunchKernelGGL(k_dots_reduce, dim3((unsigned)((nq + kWG - 1) / kWG)), dim3(kWG), 0, s, w.part, w.nchunk, nq, h_dev);
+    HIPCHK(c, hipGetLastError());
+    return 0;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+const char* stbem_last_error(const stbem_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int stbem_create(const stbem_problem* p, stbem_ctx** out)
+{
+    if (!p || !out) return STBEM_EINVAL;
+    *out = nullptr;
+    if (!(p->alpha > 0) || !std::isfinite(p->alpha)) return STBEM_EALPHA;
+    if (p->n_t < 1 || !p->t_nodes) return STBEM_ETIME;
+    if (p->t_nodes[0] != 0.0) return STBEM_ETIME;
+    for (int i = 0; i < p->n_t; ++i)
+        if (!(p->t_nodes[i + 1] > p->t_nodes[i]) || !std::isfinite(p->t_nodes[i + 1])) return STBEM_ETIME;
+    if (p->n_bnd < 3 || !p->bnd_xy) return STBEM_EMESH;
+    if (p->n_vtx < 0 || p->n_tri < 0 || (p->n_vtx > 0 && (!p->vtx_xy || !p->tri || p->n_tri < 1))) return STBEM_EMESH;
+    stbem_ctx* c = new stbem_ctx();
+    c->ng = p->n_bnd; c->nt = p->n_t; c->nv = p->n_vtx; c->ntri = p->n_vtx > 0 ? p->n_tri : 0;
+    c->alpha = p->alpha;
+    c->n = (long long)c->ng * c->nt;
+    c->nblk = (long long)c->nt * (c->nt + 1) / 2;
+    c->packed = c->nblk * (long long)c->ng * c->ng;
+    c->t.assign(p->t_nodes, p->t_nodes + c->nt + 1);
+    double area2 = 0.0;
+    for (int i = 0; i < c->ng; ++i) {
+        double x = p->bnd_xy[2 * i], y = p->bnd_xy[2 * i + 1];
+        if (!std::isfinite(x) || !std::isfinite(y)) { delete c; return STBEM_EMESH; }
+        c->vx.push_back(x); c->vy.push_back(y);
+    }
+    for (int i = 0; i < c->ng; ++i) {
+        int j = (i + 1) % c->ng;
+        double dx = c->vx[j] - c->vx[i], dy = c->vy[j] - c->vy[i], L = std::sqrt(dx * dx + dy * dy);
+        if (!(L > 0)) { delete c; return STBEM_EMESH; }
+        c->len.push_back(L); c->ex.push_back(dx / L); c->ey.push_back(dy / L);
+        area2 += c->vx[i] * c->vy[j] - c->vx[j] * c->vy[i];
+        if (L > c->lmax) c->lmax = L;
+    }
+    if (!(area2 > 0)) { delete c; return STBEM_EMESH; }     // clockwise or degenerate
+    if (c->nv > 0) {
+        c->ox.resize(c->nv); c->oy.resize(c->nv);
+        for (int v = 0; v < c->nv; ++v) { c->ox[v] = p->vtx_xy[2 * v]; c->oy[v] = p->vtx_xy[2 * v + 1]; }
+        c->tri.assign(p->tri, p->tri + 3 * c->ntri);
+        c->v2t_ptr.assign(c->nv + 1, 0);
+        for (int e = 0; e < 3 * c->ntri; ++e) {
+            int v = c->tri[e];
+            if (v < 0 || v >= c->nv) { delete c; return STBEM_EMESH; }
+            c->v2t_ptr[v + 1]++;
+        }
+        for (int t = 0; t < c->ntri; ++t) {
+            const int* q = &c->tri[3 * t];
+            double det = (c->ox[q[1]] - c->ox[q[0]]) * (c->oy[q[2]] - c->oy[q[0]]) - (c->oy[q[1]] - c->oy[q[0]]) * (c->ox[q[2]] - c->ox[q[0]]);
+            if (!(det > 0)) { delete c; return STBEM_EMESH; }
+        }
+        for (int v = 0; v < c->nv; ++v) c->v2t_ptr[v + 1] += c->v2t_ptr[v];
+        c->v2t.assign(3 * c->ntri, 0);
+        std::vector<int> fill(c->nv, 0);
+        for (int e = 0; e < 3 * c->ntri; ++e) { int v = c->tri[e]; c->v2t[c->v2t_ptr[v] + fill[v]++] = e / 3; }
+    }
+    // lumped dual mass Mt[(m,i)] = h_m (L_{i-1} + 2 L_i + L_{i+1}) / 4  (row sums, Sec. 4)
+    std::vector<double> mt(c->n);
+    for (int m = 0; m < c->nt; ++m)
+        for (int i = 0; i < c->ng; ++i) {
+            int im = (i + c->ng - 1) % c->ng, ip = (i + 1) % c->ng;
+            mt[(long long)m * c->ng + i] = (c->t[m + 1] - c->t[m]) * (c->len[im] + 2 * c->len[i] + c->len[ip]) / 4;
+        }
+    int rc = 0;
+    if ((rc = upload(c, &c->d_t, c->t)) || (rc = upload(c, &c->d_vx, c->vx)) || (rc = upload(c, &c->d_vy, c->vy)) ||
+        (rc = upload(c, &c->d_ex, c->ex)) || (rc = upload(c, &c->d_ey, c->ey)) || (rc = upload(c, &c->d_len, c->len)) ||
+        (rc = upload(c, &c->d_mt, mt)) || (rc = upload(c, &c->d_ox, c->ox)) || (rc = upload(c, &c->d_oy, c->oy)) ||
+        (rc = upload(c, &c->d_tri, c->tri)) || (rc = upload(c, &c->d_v2t_ptr, c->v2t_ptr)) || (rc = upload(c, &c->d_v2t, c->v2t))) {
+        stbem_destroy(c);
+        return rc;
+    }
+    Tables T;
+    build_tables(T);
+    M0Tables D;
+    {
+        // tanh-sinh on [0,1]: x = (1 + tanh(pi/2 sinh t))/2, t = -3..3, step 1/8
+        const double hstep = 0.125;
+        int n = 0;
+        for (int q = -24; q <= 24; ++q) {
+            double tt = q * hstep, u = 0.5 * M_PI * std::sinh(tt), ch = std::cosh(u);
+            D.de_x[n] = 0.5 * (1.0 + std::tanh(u));
+            D.de_w[n] = hstep * 0.25 * M_PI * std::cosh(tt) / (ch * ch);
+            ++n;
+        }
+        D.nde = n;
+    }
+    if (hipMalloc((void**)&c->d_tab, sizeof(Tables)) != hipSuccess || hipMalloc((void**)&c->d_m0tab, sizeof(M0Tables)) != hipSuccess) {
+        stbem_destroy(c);
+        return STBEM_ENOMEM;
+    }
+    if (hipMemcpy(c->d_tab, &T, sizeof(Tables), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_m0tab, &D, sizeof(M0Tables), hipMemcpyHostToDevice) != hipSuccess) {
+        stbem_destroy(c);
+        return STBEM_EHIP;
+    }
+    c->ord = default_orders();
+    c->m0ord.qs_near = 12; c->m0ord.qt_near = 12; c->m0ord.near_ratio = 2.0;
+    c->m0ord.omax = 0.0;
+    for (int t = 0; t < c->ntri; ++t)
+        for (int e = 0; e < 3; ++e) {
+            int a = c->tri[3 * t + e], b = c->tri[3 * t + (e + 1) % 3];
+            double d = std::hypot(c->ox[a] - c->ox[b], c->oy[a] - c->oy[b]);
+            if (d > c->m0ord.omax) c->m0ord.omax = d;
+        }
+    *out = c;
+    return STBEM_OK;
+}
+
+int stbem_destroy(stbem_ctx* c)
+{
+    if (!c) return STBEM_OK;
+    for (int s = 0; s < 7; ++s) dev_free(c, c->mat[s]);
+    dev_free(c, c->v_hi); dev_free(c, c->v_lo); dev_free(c, c->d_32);
+    void* own[] = {c->d_t, c->d_vx, c->d_vy, c->d_ex, c->d_ey, c->d_len, c->d_ox, c->d_oy, c->d_mt,
+                   c->d_tri, c->d_v2t_ptr, c->d_v2t, c->d_tab, c->d_m0tab, c->part};
+    for (void* p : own) if (p) (void)hipFree(p);
+    delete c;
+    return STBEM_OK;
+}
+
+int stbem_set_allocator(stbem_ctx* c, stbem_alloc_fn alloc, stbem_free_fn release, void* user)
+{
+    if (!c || (!alloc) != (!release)) return STBEM_EINVAL;
+    for (int s = 0; s < 7; ++s)
+        if (c->mat[s]) return fail(c, STBEM_EINVAL, "set the allocator before assembling");
+    c->alloc = alloc; c->release = release; c->user = user;
+    return STBEM_OK;
+}
+
+int stbem_sizes(const stbem_ctx* c, long long* n, int* ng, int* nt, int* nv, long long* packed)
+{
+    if (!c) return STBEM_EINVAL;
+    if (n) *n = c->n;
+    if (ng) *ng = c->ng;
+    if (nt) *nt = c->nt;
+    if (nv) *nv = c->nv;
+    if (packed) *packed = c->packed;
+    return STBEM_OK;
+}
+
+int stbem_assemble(stbem_ctx* c, unsigned mask, void* stream)
+{
+    if (!c) return STBEM_EINVAL;
+    if (mask == 0 || (mask & ~127u)) return fail(c, STBEM_EINVAL, "bad operator mask %u", mask);
+    const unsigned ops[7] = {STBEM_V, STBEM_K, STBEM_D, STBEM_M0, STBEM_DV, STBEM_DK, STBEM_DM0};
+    for (unsigned op : ops)
+        if (mask & op) {
+            int rc = assemble_one(c, op, S(stream));
+            if (rc) return rc;
+        }
+    return STBEM_OK;
+}
+
+int stbem_matrix(stbem_ctx* c, unsigned op, const double** ptr, size_t* bytes)
+{
+    if (!c || !ptr) return STBEM_EINVAL;
+    int slot = op_slot(op);
+    if (slot < 0) return fail(c, STBEM_EINVAL, "unknown operator %u", op);
+    if (!c->mat[slot]) return fail(c, STBEM_ENOTASSEMBLED, "operator %u not assembled", op);
+    *ptr = c->mat[slot];
+    if (bytes) *bytes = c->mat_bytes[slot];
+    return STBEM_OK;
+}
+
+int stbem_apply(stbem_ctx* c, unsigned op, int trans, const double* x, double* y, void* stream)
+{
+    if (!c || !x || !y) return STBEM_EINVAL;
+    int slot = op_slot(op);
+    if (slot < 0) return fail(c, STBEM_EINVAL, "unknown operator %u", op);
+    if (!c->mat[slot]) return fail(c, STBEM_ENOTASSEMBLED, "operator %u not assembled", op);
+    if (op == STBEM_M0 || op == STBEM_DM0) return dense_apply(c, c->mat[slot], trans ? 1 : 0, x, y, S(stream));
+    return packed_apply(c, c->mat[slot], nullptr, nullptr, nullptr, trans ? 1 : 0, x, y, S(stream));
+}
+
+int stbem_mass(stbem_ctx* c, int trans, const double* x, double* y, void* stream)
+{
+    if (!c || !x || !y) return STBEM_EINVAL;
+    hipLaunchKernelGGL(k_mass, dim3(grid1(c->n)), dim3(kWG), 0, S(stream), c->d_t, c->d_len, x, y, c->ng, c->nt,
+                       trans ? 1 : 0, 1.0, (const double*)nullptr);
+    HIPCHK(c, hipGetLastError());
+    return STBEM_OK;
+}
+
+static int precondition_impl(stbem_ctx* c, int trans, const double* r, double* z, double* tmp, const float* d32,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_div, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, r, (const double*)c->d_mt, tmp);
+    HIPCHK(c, hipGetLastError());
+    int rc = d32 ? packed_apply(c, nullptr, nullptr, nullptr, d32, trans, tmp, z, s)
+                 : packed_apply(c, c->mat[2], nullptr, nullptr, nullptr, trans, tmp, z, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_div, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, (const double*)z, (const double*)c->d_mt, z);
+    HIPCHK(c, hipGetLastError());
+    return 0;
+}
+
+int stbem_precondition(stbem_ctx* c, int trans, const double* r, double* z, void* stream)
+{
+    if (!c || !r || !z) return STBEM_EINVAL;
+    if (!c->mat[2]) return fail(c, STBEM_ENOTASSEMBLED, "D_h not assembled");
+    double* tmp = (double*)dev_alloc(c, (size_t)c->n * sizeof(double));
+    if (!tmp) return fail(c, STBEM_ENOMEM, "temporary vector");
+    int rc = precondition_impl(c, trans ? 1 : 0, r, z, tmp, nullptr, S(stream));
+    (void)hipStreamSynchronize(S(stream));
+    dev_free(c, tmp);
+    return rc;
+}
+
+int stbem_rhs(stbem_ctx* c, const double* g, const double* u0, double* f, void* stream)
+{
+    if (!c || !g || !f) return STBEM_EINVAL;
+    if (!c->mat[1]) return fail(c, STBEM_ENOTASSEMBLED, "K_h not assembled");
+    if (u0 && !c->mat[3]) return fail(c, STBEM_ENOTASSEMBLED, "M_h^0 not assembled");
+    hipStream_t s = S(stream);
+    double* tmp = (double*)dev_alloc(c, (size_t)c->n * sizeof(double));
+    if (!tmp) return fail(c, STBEM_ENOMEM, "temporary vector");
+    int rc = 0;
+    // f = K g;  f = 1/2 M g + f;  f -= M0 u0
+    if ((rc = packed_apply(c, c->mat[1], nullptr, nullptr, nullptr, 0, g, f, s))) goto done;
+    hipLaunchKernelGGL(k_mass, dim3(grid1(c->n)), dim3(kWG), 0, s, c->d_t, c->d_len, g, tmp, c->ng, c->nt, 0, 0.5,
+                       (const double*)f);
+    if (hipGetLastError() != hipSuccess) { rc = fail(c, STBEM_EHIP, "mass kernel"); goto done; }
+    if (u0) {
+        if ((rc = dense_apply(c, c->mat[3], 0, u0, f, s))) goto done;
+        hipLaunchKernelGGL(k_axpby, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, 1.0, (const double*)tmp, -1.0, f);
+    } else {
+        hipLaunchKernelGGL(k_axpby, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, 1.0, (const double*)tmp, 0.0, f);
+    }
+    if (hipGetLastError() != hipSuccess) { rc = fail(c, STBEM_EHIP, "axpby kernel"); goto done; }
+done:
+    (void)hipStreamSynchronize(s);
+    dev_free(c, tmp);
+    return rc;
+}
+
+// ----------------------------------------------------------------- GMRES
+namespace {
+
+struct SolveOp {
+    stbem_ctx* c;
+    int trans, precond;
+    const double* A; const float *hi, *lo, *a32;     // system matrix storage
+    const float* d32;                                // FP32 D (else FP64 D)
+    double* tmp;
+};
+
+int op_apply(const SolveOp& o, const double* x, double* y, hipStream_t s)
+{
+    // y = C A x   (C = Mt^-1 D Mt^-1 or identity)
+    stbem_ctx* c = o.c;
+    if (!o.precond) return packed_apply(c, o.A, o.hi, o.lo, o.a32, o.trans, x, y, s);
+    int rc = packed_apply(c, o.A, o.hi, o.lo, o.a32, o.trans, x, o.tmp + c->n, s);
+    if (rc) return rc;
+    return precondition_impl(c, o.trans, o.tmp + c->n, y, o.tmp, o.d32, s);
+}
+
+int op_precond(const SolveOp& o, const double* r, double* z, hipStream_t s)
+{
+    stbem_ctx* c = o.c;
+    if (!o.precond) {
+        HIPCHK(c, hipMemcpyAsync(z, r, (size_t)c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        return 0;
+    }
+    return precondition_impl(c, o.trans, r, z, o.tmp, o.d32, s);
+}
+
+// left-preconditioned GMRES, x0 = 0, CGS2 orthogonalisation in FP64
+int gmres(const SolveOp& o, const double* f, double* w, double tol, int maxit, int* iters, double* relres, hipStream_t s)
+{
+    stbem_ctx* c = o.c;
+    const long long n = c->n;
+    const long long ldq = n;
+    double* Q = (double*)dev_alloc(c, (size_t)(maxit + 1) * n * sizeof(double));
+    DotWork dw;
+    dw.nchunk = (int)((n + kDotChunk - 1) / kDotChunk);
+    dw.part = (double*)dev_alloc(c, (size_t)(maxit + 1) * dw.nchunk * sizeof(double));
+    double* hdev = (double*)dev_alloc(c, (size_t)(maxit + 2) * 2 * sizeof(double));
+    double* v = (double*)dev_alloc(c, (size_t)n * sizeof(double));
+    if (!Q || !dw.part || !hdev || !v) {
+        dev_free(c, Q); dev_free(c, dw.part); dev_free(c, hdev); dev_free(c, v);
+        return fail(c, STBEM_ENOMEM, "GMRES workspace (%d vectors of %lld)", maxit + 1, n);
+    }
+    std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), gv(maxit + 1, 0.0), hh(maxit + 2);
+    int rc = 0, j = 0;
+    double beta = 0.0;
+    *iters = 0; *relres = 0.0;
+    // r0 = C f
+    if ((rc = op_precond(o, f, Q, s))) goto out;
+    if ((rc = dots(c, dw, Q, ldq, 1, Q, hdev, s))) goto out;
+    HIPCHK(c, hipMemcpyAsync(hh.data(), hdev, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    beta = std::sqrt(hh[0]);
+    if (beta == 0.0) {
+        HIPCHK(c, hipMemsetAsync(w, 0, (size_t)n * sizeof(double), s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        goto out;
+    }
+    hipLaunchKernelGGL(k_axpby, dim3(grid1(n)), dim3(kWG), 0, s, n, 1.0 / beta, (const double*)Q, 0.0, Q);
+    gv[0] = beta;
+    for (j = 0; j < maxit; ++j) {
+        double* qj1 = Q + (long long)(j + 1) * ldq;
+        if ((rc = op_apply(o, Q + (long long)j * ldq, v, s))) goto out;
+        // classical Gram-Schmidt, twice
+        for (int pass = 0; pass < 2; ++pass) {
+            if ((rc = dots(c, dw, Q, ldq, j + 1, v, hdev, s))) goto out;
+            hipLaunchKernelGGL(k_basis_sub, dim3(grid1(n)), dim3(kWG), 0, s, (const double*)Q, ldq, j + 1, (const double*)hdev, v, n);
+            HIPCHK(c, hipMemcpyAsync(hh.data(), hdev, (size_t)(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            for (int i = 0; i <= j; ++i) H[(size_t)j * (maxit + 1) + i] += hh[i];
+        }
+        if ((rc = dots(c, dw, v, ldq, 1, v, hdev, s))) goto out;
+        HIPCHK(c, hipMemcpyAsync(hh.data(), hdev, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        {
+            double hn = std::sqrt(hh[0]);
+            double* col = &H[(size_t)j * (maxit + 1)];
+            col[j + 1] = hn;
+            if (hn > 0.0)
+                hipLaunchKernelGGL(k_axpby, dim3(grid1(n)), dim3(kWG), 0, s, n, 1.0 / hn, (const double*)v, 0.0, qj1);
+            for (int i = 0; i < j; ++i) {
+                double a = col[i], b = col[i + 1];
+                col[i] = cs[i] * a + sn[i] * b;
+                col[i + 1] = -sn[i] * a + cs[i] * b;
+            }
+            double a = col[j], b = col[j + 1], r = std::hypot(a, b);
+            cs[j] = a / r; sn[j] = b / r;
+            col[j] = r; col[j + 1] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            *relres = std::fabs(gv[j + 1]) / beta;
+            if (std::fabs(gv[j + 1]) <= tol * beta || hn == 0.0) { ++j; break; }
+        }
+    }
+    if (j > maxit) j = maxit;
+    {
+        // back substitution on the host, combination on the device
+        std::vector<double> y(j);
+        for (int i = j - 1; i >= 0; --i) {
+            double sacc = gv[i];
+            for (int l = i + 1; l < j; ++l) sacc -= H[(size_t)l * (maxit + 1) + i] * y[l];
+            y[i] = sacc / H[(size_t)i * (maxit + 1) + i];
+        }
+        HIPCHK(c, hipMemcpyAsync(hdev, y.data(), (size_t)j * sizeof(double), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_basis_comb, dim3(grid1(n)), dim3(kWG), 0, s, (const double*)Q, ldq, j, (const double*)hdev, w, n, 0);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
+    *iters = j;
+out:
+    dev_free(c, Q); dev_free(c, dw.part); dev_free(c, hdev); dev_free(c, v);
+    return rc;
+}
+
+int true_relres(stbem_ctx* c, const SolveOp& o64, const double* f, const double* w, double* r, double* res, hipStream_t s)
+{
+    // r = f - A w in FP64 storage (or hi+lo), returns ||r|| / ||f||
+    int rc = packed_apply(c, o64.A, o64.hi, o64.lo, nullptr, o64.trans, w, r, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_axpby, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, 1.0, f, -1.0, r);
+    DotWork dw;
+    dw.nchunk = (int)((c->n + kDotChunk - 1) / kDotChunk);
+    dw.part = (double*)dev_alloc(c, (size_t)2 * dw.nchunk * sizeof(double));
+    double* hd = (double*)dev_alloc(c, 2 * sizeof(double));
+    if (!dw.part || !hd) { dev_free(c, dw.part); dev_free(c, hd); return fail(c, STBEM_ENOMEM, "norms"); }
+    double hh[2];
+    if ((rc = dots(c, dw, r, c->n, 1, r, hd, s)) || (rc = dots(c, dw, f, c->n, 1, f, hd + 1, s))) {
+        dev_free(c, dw.part); dev_free(c, hd); return rc;
+    }
+    (void)hipMemcpyAsync(hh, hd, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    (void)hipStreamSynchronize(s);
+    dev_free(c, dw.part); dev_free(c, hd);
+    *res = hh[1] > 0 ? std::sqrt(hh[0] / hh[1]) : 0.0;
+    return 0;
+}
+
+}  // namespace
+
+int stbem_prepare_ir(stbem_ctx* c, void* stream)
+{
+    if (!c) return STBEM_EINVAL;
+    if (!c->mat[0] || !c->mat[2]) return fail(c, STBEM_ENOTASSEMBLED, "FP32 storage needs V_h and D_h");
+    hipStream_t s = S(stream);
+    size_t fb = (size_t)c->packed * sizeof(float);
+    if (!c->v_hi) c->v_hi = (float*)dev_alloc(c, fb);
+    if (!c->v_lo) c->v_lo = (float*)dev_alloc(c, fb);
+    if (!c->d_32) c->d_32 = (float*)dev_alloc(c, fb);
+    if (!c->v_hi || !c->v_lo || !c->d_32) return fail(c, STBEM_ENOMEM, "FP32 storage (3 x %zu bytes)", fb);
+    hipLaunchKernelGGL(k_split, dim3(grid1(c->packed)), dim3(kWG), 0, s, c->packed, (const double*)c->mat[0], c->v_hi, c->v_lo);
+    hipLaunchKernelGGL(k_split, dim3(grid1(c->packed)), dim3(kWG), 0, s, c->packed, (const double*)c->mat[2], c->d_32, (float*)nullptr);
+    HIPCHK(c, hipGetLastError());
+    return STBEM_OK;
+}
+
+int stbem_solve(stbem_ctx* c, const double* f, double* w, const stbem_solve_opts* opts, stbem_solve_info* info, void* stream)
+{
+    if (!c || !f || !w || !opts) return STBEM_EINVAL;
+    if (!c->mat[0]) return fail(c, STBEM_ENOTASSEMBLED, "V_h not assembled");
+    if (opts->precondition && !c->mat[2]) return fail(c, STBEM_ENOTASSEMBLED, "D_h not assembled");
+    if (opts->max_it < 1 || !(opts->tol > 0)) return fail(c, STBEM_EINVAL, "bad tolerance or iteration limit");
+    hipStream_t s = S(stream);
+    stbem_solve_info inf = {0, 0, 0.0, 0.0};
+    double* tmp = (double*)dev_alloc(c, (size_t)3 * c->n * sizeof(double));
+    if (!tmp) return fail(c, STBEM_ENOMEM, "solver vectors");
+    int rc = 0;
+    SolveOp o64 = {c, opts->trans ? 1 : 0, opts->precondition ? 1 : 0, c->mat[0], nullptr, nullptr, nullptr, nullptr, tmp};
+    if (opts->mode == STBEM_FP64) {
+        int it = 0;
+        double rr = 0.0;
+        rc = gmres(o64, f, w, opts->tol, opts->max_it, &it, &rr, s);
+        inf.iters = it; inf.relres = rr;
+        if (!rc) rc = true_relres(c, o64, f, w, tmp + 2 * c->n, &inf.true_relres, s);
+        if (!rc && rr > opts->tol) rc = STBEM_WARN_NOT_CONVERGED;
+    } else if (opts->mode == STBEM_FP32_IR) {
+        if (!c->v_hi || !c->d_32) {
+            if ((rc = stbem_prepare_ir(c, stream))) { dev_free(c, tmp); return rc; }
+        }
+        // outer: r = f - V w with V = hi + lo (FP64 accumulation); inner:
+        // GMRES on FP32 V_hi and FP32 D; w += correction
+        SolveOp ohl = {c, o64.trans, 0, nullptr, c->v_hi, c->v_lo, nullptr, nullptr, tmp};
+        SolveOp o32 = {c, o64.trans, opts->precondition ? 1 : 0, nullptr, nullptr, nullptr, c->v_hi, c->d_32, tmp};
+        double* r = (double*)dev_alloc(c, (size_t)2 * c->n * sizeof(double));
+        if (!r) { dev_free(c, tmp); return fail(c, STBEM_ENOMEM, "IR vectors"); }
+        double* corr = r + c->n;
+        HIPCHK(c, hipMemsetAsync(w, 0, (size_t)c->n * sizeof(double), s));
+        double prev = 1e300, res = 0.0;
+        int outer = 0;
+        for (;;) {
+            if ((rc = true_relres(c, ohl, f, w, r, &res, s))) break;
+            if (res <= opts->ir_tol) break;
+            if (outer >= opts->max_outer) { rc = STBEM_WARN_NOT_CONVERGED; break; }
+            if (res > 0.5 * prev) { rc = STBEM_WARN_IR_STAGNATION; break; }
+            prev = res;
+            int it = 0;
+            double rr = 0.0;
+            if ((rc = gmres(o32, r, corr, opts->inner_tol, opts->max_it, &it, &rr, s))) break;
+            inf.iters += it;
+            inf.relres = rr;
+            hipLaunchKernelGGL(k_axpby, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, 1.0, (const double*)corr, 1.0, w);
+            ++outer;
+        }
+        inf.outer = outer;
+        int rc2 = true_relres(c, o64, f, w, r, &inf.true_relres, s);
+        if (!rc && rc2) rc = rc2;
+        dev_free(c, r);
+    } else {
+        dev_free(c, tmp);
+        return fail(c, STBEM_EINVAL, "unknown solve mode %d", opts->mode);
+    }
+    (void)hipStreamSynchronize(s);
+    dev_free(c, tmp);
+    if (info) *info = inf;
+    return rc;
+}
+
+int stbem_grad_alpha(stbem_ctx* c, const double* lam, const double* w, const double* g, const double* u0,
+                     double* out, void* stream)
+{
+    if (!c || !lam || !w || !g || !out) return STBEM_EINVAL;
+    if (!c->mat[4] || !c->mat[5] || (u0 && !c->mat[6])) return fail(c, STBEM_ENOTASSEMBLED, "alpha-derivative operators not assembled");
+    hipStream_t s = S(stream);
+    double* t = (double*)dev_alloc(c, (size_t)2 * c->n * sizeof(double));
+    if (!t) return fail(c, STBEM_ENOMEM, "temporaries");
+    int rc = 0;
+    // t = dK g - dV w - dM0 u0
+    if ((rc = packed_apply(c, c->mat[5], nullptr, nullptr, nullptr, 0, g, t, s))) goto done;
+    if ((rc = packed_apply(c, c->mat[4], nullptr, nullptr, nullptr, 0, w, t + c->n, s))) goto done;
+    hipLaunchKernelGGL(k_axpby, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, -1.0, (const double*)(t + c->n), 1.0, t);
+    if (u0) {
+        if ((rc = dense_apply(c, c->mat[6], 0, u0, t + c->n, s))) goto done;
+        hipLaunchKernelGGL(k_axpby, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, -1.0, (const double*)(t + c->n), 1.0, t);
+    }
+    {
+        DotWork dw;
+        dw.nchunk = (int)((c->n + kDotChunk - 1) / kDotChunk);
+        dw.part = (double*)dev_alloc(c, (size_t)dw.nchunk * sizeof(double));
+        if (!dw.part) { rc = fail(c, STBEM_ENOMEM, "dot"); goto done; }
+        rc = dots(c, dw, lam, c->n, 1, t, out, s);
+        (void)hipStreamSynchronize(s);
+        dev_free(c, dw.part);
+    }
+done:
+    (void)hipStreamSynchronize(s);
+    dev_free(c, t);
+    return rc;
+}
+
+int stbem_entries(stbem_ctx* c, unsigned op, long long n, const int* idx, double* out, void* stream)
+{
+    if (!c || (n > 0 && (!idx || !out))) return STBEM_EINVAL;
+    if (n == 0) return STBEM_OK;
+    hipStream_t s = S(stream);
+    unsigned nwg = grid1(n);
+    Geom g = geom(c);
+    switch (op) {
+    case STBEM_V: hipLaunchKernelGGL(k_entries<OP_V>, dim3(nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, n, idx, out); break;
+    case STBEM_K: hipLaunchKernelGGL(k_entries<OP_K>, dim3(nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, n, idx, out); break;
+    case STBEM_D: hipLaunchKernelGGL(k_entries<OP_D>, dim3(nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, n, idx, out); break;
+    case STBEM_DV: hipLaunchKernelGGL(k_entries<OP_DV>, dim3(nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, n, idx, out); break;
+    case STBEM_DK: hipLaunchKernelGGL(k_entries<OP_DK>, dim3(nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, n, idx, out); break;
+    default: return fail(c, STBEM_EINVAL, "stbem_entries supports V, K, D, dV, dK");
+    }
+    HIPCHK(c, hipGetLastError());
+    return STBEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,225 @@
+// Initial potential M_h^0 of eq.(4) (arXiv:1811.05224, Sec. 1):
+//   M0[(k,i), j] = int_{gamma_i} int_Omega phi_j(y) G_k(|x - y|) dy ds_x,
+//   G_k(r) = int_{tau_k} U*(r, t) dt = alpha/(4 pi) [E1(a/t_{k+1}) - E1(a/t_k)],
+// a = alpha r^2 / 4, E1(a/0) = 0.  phi_j is the P1 hat of vertex j of Omega_h.
+// The alpha-derivative is (1/(4 pi)) [E1 - E1 - e^{-a/t_{k+1}} + e^{-a/t_k}].
+//
+// For k >= 1, G_k is smooth (its ln r parts cancel): tensor Gauss on the
+// segment times a collapsed Gauss rule on the triangle.  For k = 0 it has the
+// singularity -(alpha/2pi) ln r; near the segment the kernel is split as
+// S(r^2) - (alpha/2pi) ln r (S smooth), the S part uses the tensor rule and
+// the ln part uses the closed-form logarithmic potential of a linear density
+// on the triangle, integrated along the segment by a tanh-sinh rule on the
+// pieces between the projections of the triangle vertices.
+#pragma once
+#include "stbem_math.h"
+
+namespace stbem {
+
+constexpr int kMaxDE = 64;
+
+struct M0Tables {
+    int nde;
+    double de_x[kMaxDE], de_w[kMaxDE];     // tanh-sinh on [0,1]
+};
+
+struct Mesh2 {
+    int nv, ntri;
+    const double *ox, *oy;                 // Omega vertices
+    const int* tri;                        // 3 * ntri, CCW
+    const int *v2t_ptr, *v2t;              // vertex -> triangles
+};
+
+// G_k (or its alpha-derivative) at r^2
+template <bool DERIV>
+SDEV double m0_kernel(const Geom& g, int k, double r2)
+{
+    double a = 0.25 * g.alpha * r2;
+    double t1 = g.t[k + 1], t0 = g.t[k];
+    double z1 = a / t1;
+    if (k == 0) {
+        double E = e1(z1);
+        return DERIV ? (E - exp(-z1)) * kInv4Pi : g.alpha * kInv4Pi * E;
+    }
+    double z0 = a / t0, dE;
+    if (z0 <= 2.0) dE = log(t1 / t0) + ein(z1) - ein(z0);    // no ln a cancellation
+    else dE = e1(z1) - e1(z0);
+    if (DERIV) return (dE - exp(-z1) + exp(-z0)) * kInv4Pi;
+    return g.alpha * kInv4Pi * dE;
+}
+
+// smooth part S of G_0 = S - B ln r with B = alpha/(2 pi) (resp. 1/(2 pi))
+template <bool DERIV>
+SDEV double m0_smooth0(const Geom& g, double r2, double lnr)
+{
+    double a = 0.25 * g.alpha * r2, t1 = g.t[1], z = a / t1;
+    double Ez;   // E1(z) + 2 ln r
+    if (z <= 2.0) Ez = -kEuler - log(0.25 * g.alpha / t1) + ein(z);
+    else Ez = e1(z) + 2.0 * lnr;
+    return DERIV ? (Ez - exp(-z)) * kInv4Pi : g.alpha * kInv4Pi * Ez;
+}
+
+struct Tri {
+    double ax, ay, bx, by, cx, cy;
+    double gx, gy, g0;      // phi_j(y) = g0 + gx y_x + gy y_y
+};
+
+SDEV Tri load_tri(const Mesh2& m, int t, int j)
+{
+    Tri T;
+    int v0 = m.tri[3 * t], v1 = m.tri[3 * t + 1], v2 = m.tri[3 * t + 2];
+    T.ax = m.ox[v0]; T.ay = m.oy[v0]; T.bx = m.ox[v1]; T.by = m.oy[v1]; T.cx = m.ox[v2]; T.cy = m.oy[v2];
+    // hat of vertex j: phi(y) = cross(C' - B', y - B') / cross(B - A, C - A)
+    double px, py, qx, qy;   // B', C': the two other vertices in CCW order after j
+    if (j == v0) { px = T.bx; py = T.by; qx = T.cx; qy = T.cy; }
+    else if (j == v1) { px = T.cx; py = T.cy; qx = T.ax; qy = T.ay; }
+    else { px = T.ax; py = T.ay; qx = T.bx; qy = T.by; }
+    double det = (T.bx - T.ax) * (T.cy - T.ay) - (T.by - T.ay) * (T.cx - T.ax);
+    T.gx = -(qy - py) / det;
+    T.gy = (qx - px) / det;
+    T.g0 = ((qx - px) * (-py) - (qy - py) * (-px)) / det;
+    return T;
+}
+
+// regular rule: qs Gauss points on the segment, qt x qt collapsed Gauss on
+// the triangle; f(r2) * phi_j
+template <class F>
+SDEV double m0_regular(const Tables& T, const Piece& S, const Tri& tr, int qs, int qt, F f)
+{
+    double e1x = tr.bx - tr.ax, e1y = tr.by - tr.ay, e2x = tr.cx - tr.ax, e2y = tr.cy - tr.ay;
+    double area2 = fabs(e1x * e2y - e1y * e2x);
+    double acc = 0.0;
+    for (int a = 0; a < qt; ++a) {
+        double u = T.gl_x[qt][a], wu = T.gl_w[qt][a] * (1.0 - u);
+        for (int b = 0; b < qt; ++b) {
+            double v = T.gl_x[qt][b] * (1.0 - u), w = wu * T.gl_w[qt][b] * area2;
+            double yx = tr.ax + u * e1x + v * e2x, yy = tr.ay + u * e1y + v * e2y;
+            double phi = tr.g0 + tr.gx * yx + tr.gy * yy;
+            double inner = 0.0;
+            for (int c = 0; c < qs; ++c) {
+                double s = S.len * T.gl_x[qs][c];
+                double dx = S.ax + s * S.ex - yx, dy = S.ay + s * S.ey - yy;
+                inner += T.gl_w[qs][c] * f(dx * dx + dy * dy);
+            }
+            acc += w * phi * inner;
+        }
+    }
+    return acc * S.len;
+}
+
+// u ln(u^2 + d^2) - 2u + 2 d atan(u/d), and (1/2)[(u^2+d^2) ln(u^2+d^2) - u^2]
+SDEV double logU(double u, double d)
+{
+    double q = u * u + d * d;
+    double l = q > 0.0 ? u * log(q) : 0.0;
+    return l - 2.0 * u + (d > 0.0 ? 2.0 * d * atan(u / d) : 0.0);
+}
+SDEV double logW(double u, double d)
+{
+    double q = u * u + d * d;
+    return 0.5 * ((q > 0.0 ? q * log(q) : 0.0) - u * u);
+}
+
+// int_omega phi_j(y) ln|x - y| dy in closed form: sum over the CCW edges
+// (p, p + E) of the signed sub-triangles (x, p, p + E) in polar form
+SDEV double log_potential(const Tri& tr, double x, double y)
+{
+    const double vx[3] = {tr.ax, tr.bx, tr.cx}, vy[3] = {tr.ay, tr.by, tr.cy};
+    double phx = tr.g0 + tr.gx * x + tr.gy * y;
+    double acc = 0.0;
+    for (int e = 0; e < 3; ++e) {
+        int f = e == 2 ? 0 : e + 1;
+        double Px = vx[e] - x, Py = vy[e] - y, Ex = vx[f] - vx[e], Ey = vy[f] - vy[e];
+        double J = Px * Ey - Py * Ex;
+        double E2 = Ex * Ex + Ey * Ey;
+        if (fabs(J) <= 1e-14 * E2) continue;
+        double tau0 = -(Px * Ex + Py * Ey) / E2;
+        double del = fabs(J) / E2;
+        double dU = logU(1.0 - tau0, del) - logU(-tau0, del);
+        double dW = logW(1.0 - tau0, del) - logW(-tau0, del);
+        double lE = log(E2);
+        double I0 = 0.5 * lE + 0.5 * dU;
+        double I1 = 0.25 * lE + 0.5 * (dW + tau0 * dU);
+        double g0 = tr.gx * Px + tr.gy * Py, g1 = tr.gx * Ex + tr.gy * Ey;
+        acc += J * (-0.25 * phx - (g0 + 0.5 * g1) / 9.0 + (0.5 * phx + g0 / 3.0) * I0 + g1 * I1 / 3.0);
+    }
+    return acc;
+}
+
+// int_{gamma_i} log_potential ds: tanh-sinh on the pieces of the segment
+// between the projections of the triangle vertices
+SDEV double seg_log_potential(const M0Tables& D, const Piece& S, const Tri& tr)
+{
+    double cuts[5];
+    int nc = 0;
+    cuts[nc++] = 0.0;
+    const double vx[3] = {tr.ax, tr.bx, tr.cx}, vy[3] = {tr.ay, tr.by, tr.cy};
+    for (int v = 0; v < 3; ++v) {
+        double s = (vx[v] - S.ax) * S.ex + (vy[v] - S.ay) * S.ey;
+        if (s > 1e-12 * S.len && s < S.len * (1.0 - 1e-12)) cuts[nc++] = s;
+    }
+    cuts[nc++] = S.len;
+    for (int a = 1; a < nc; ++a)
+        for (int b = a; b > 0 && cuts[b] < cuts[b - 1]; --b) { double t = cuts[b]; cuts[b] = cuts[b - 1]; cuts[b - 1] = t; }
+    double acc = 0.0;
+    for (int p = 0; p + 1 < nc; ++p) {
+        double s0 = cuts[p], h = cuts[p + 1] - cuts[p];
+        if (h <= 0.0) continue;
+        double part = 0.0;
+        for (int q = 0; q < D.nde; ++q) {
+            double s = s0 + h * D.de_x[q];
+            part += D.de_w[q] * log_potential(tr, S.ax + s * S.ex, S.ay + s * S.ey);
+        }
+        acc += h * part;
+    }
+    return acc;
+}
+
+SDEV double seg_tri_dist(const Piece& S, const Tri& tr)
+{
+    // distance between the segment and the triangle's vertices/edges
+    const double vx[3] = {tr.ax, tr.bx, tr.cx}, vy[3] = {tr.ay, tr.by, tr.cy};
+    double d2 = 1e300;
+    for (int e = 0; e < 3; ++e) {
+        d2 = fmin(d2, pt_seg_d2(vx[e], vy[e], S));
+        int f = e == 2 ? 0 : e + 1;
+        Piece Ed;
+        Ed.ax = vx[e]; Ed.ay = vy[e];
+        double ex = vx[f] - vx[e], ey = vy[f] - vy[e], L = sqrt(ex * ex + ey * ey);
+        Ed.ex = ex / L; Ed.ey = ey / L; Ed.len = L;
+        d2 = fmin(d2, pt_seg_d2(S.ax, S.ay, Ed));
+        d2 = fmin(d2, pt_seg_d2(S.ax + S.len * S.ex, S.ay + S.len * S.ey, Ed));
+    }
+    return sqrt(d2);
+}
+
+struct M0Orders { int qs_near, qt_near; double near_ratio, omax; };
+
+// one entry M0[(k,i), j] (or its alpha-derivative)
+template <bool DERIV>
+SDEV double m0_entry(const Tables& T, const M0Tables& D, const M0Orders& MO, const Geom& g,
+                     const Mesh2& m, int k, int i, int j, int qs, int qt)
+{
+    Piece S = seg_piece(g, i);
+    double acc = 0.0;
+    for (int p = m.v2t_ptr[j]; p < m.v2t_ptr[j + 1]; ++p) {
+        Tri tr = load_tri(m, m.v2t[p], j);
+        if (k == 0) {
+            double dx1 = tr.bx - tr.ax, dy1 = tr.by - tr.ay, dx2 = tr.cx - tr.ax, dy2 = tr.cy - tr.ay;
+            double diam = sqrt(fmax(fmax(dx1 * dx1 + dy1 * dy1, dx2 * dx2 + dy2 * dy2),
+                                    (dx2 - dx1) * (dx2 - dx1) + (dy2 - dy1) * (dy2 - dy1)));
+            double size = fmax(diam, S.len);
+            if (seg_tri_dist(S, tr) < MO.near_ratio * size) {
+                double sm = m0_regular(T, S, tr, MO.qs_near, MO.qt_near,
+                                       [&](double r2) { return m0_smooth0<DERIV>(g, r2, 0.5 * log(r2)); });
+                double B = DERIV ? kInv2Pi : g.alpha * kInv2Pi;
+                acc += sm - B * seg_log_potential(D, S, tr);
+                continue;
+            }
+        }
+        acc += m0_regular(T, S, tr, qs, qt, [&](double r2) { return m0_kernel<DERIV>(g, k, r2); });
+    }
+    return acc;
+}
+
+}  // namespace stbem

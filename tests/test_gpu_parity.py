@@ -1,0 +1,148 @@
+"""GPU path (libstbem.so through the C ABI) against the CPU oracle.
+
+Entries: |A_gpu - A_ref| <= tol * max(|A_ref|, 1e-8 * max over the block of
+|A_ref|), tol = 1e-12 (D_h: 2e-12, see the cancellation note in the design
+notes).  Solutions: relative l2 error <= 1e-10 against the oracle's direct
+block forward substitution on the oracle's own matrices.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.oracle import Oracle, packed_apply, packed_index
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"V": 1e-12, "K": 1e-12, "D": 2e-12, "dV": 1e-12, "dK": 1e-12}
+
+
+def _ctx(wl, mask):
+    import paper_1811_05224_amd as P
+    from paper_1811_05224_amd import _lib as L
+    c = P.Context.from_workload(wl)
+    c.assemble(mask)
+    return c, L
+
+
+def block_err(gpu, ref):
+    """floor-rule relative error per entry of packed [nb, ng, ng] arrays"""
+    mx = np.abs(ref).reshape(ref.shape[0], -1).max(axis=1)[:, None, None]
+    return np.abs(gpu - ref) / np.maximum(np.abs(ref), 1e-8 * mx + 1e-300)
+
+
+@pytest.fixture(scope="module")
+def small():
+    # 20 segments: two 16-wide tiles per block side, the second one ragged
+    wl = W.make("custom", n_side=5, n_t=4, n_omega=3, alpha=1.3, k=(0.4, -0.3))
+    o = Oracle.from_workload(wl)
+    import paper_1811_05224_amd as P
+    from paper_1811_05224_amd import _lib as L
+    c = P.Context.from_workload(wl)
+    c.assemble(L.V | L.K | L.D | L.M0 | L.DV | L.DK | L.DM0)
+    return wl, o, c, L
+
+
+@pytest.mark.parametrize("op", ["V", "K", "D", "dV", "dK"])
+def test_assembly_small_all_entries(small, op):
+    wl, o, c, L = small
+    code = {"V": L.V, "K": L.K, "D": L.D, "dV": L.DV, "dK": L.DK}[op]
+    gpu = c.packed(code).cpu().numpy()
+    ref = o.packed(op)
+    e = block_err(gpu, ref)
+    print(op, "max floor-rule error", e.max())
+    assert e.max() <= TOL[op]
+
+
+@pytest.mark.parametrize("deriv", [False, True])
+def test_m0_small_all_entries(small, deriv):
+    wl, o, c, L = small
+    gpu = c.matrix(L.DM0 if deriv else L.M0).cpu().numpy().reshape(c.n, c.nv)
+    ref = o.m0(deriv)
+    mx = np.abs(ref).max(axis=1, keepdims=True)
+    e = np.abs(gpu - ref) / np.maximum(np.abs(ref), 1e-8 * mx)
+    print("M0 max error", e.max())
+    assert e.max() <= 1e-12
+
+
+def test_sampled_entries_kernel_matches_storage(small):
+    wl, o, c, L = small
+    rng = np.random.default_rng(3)
+    idx = np.stack([rng.integers(0, c.nt, 64), rng.integers(0, c.nt, 64), rng.integers(0, c.ng, 64), rng.integers(0, c.ng, 64)], 1)
+    idx[:, 1] = np.minimum(idx[:, 0], idx[:, 1])
+    for code in (L.V, L.K, L.D):
+        a = c.entries(code, idx).cpu().numpy()
+        P = c.packed(code).cpu().numpy()
+        b = np.array([P[packed_index(k, m), i, j] for k, m, i, j in idx])
+        assert np.array_equal(a, b)
+
+
+def test_gemv_matches_numpy_and_is_deterministic(small):
+    wl, o, c, L = small
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(c.n)
+    for code in (L.V, L.K, L.D):
+        P = c.packed(code).cpu().numpy()
+        for trans in (False, True):
+            y1 = c.apply(code, x, trans=trans).cpu().numpy()
+            y2 = c.apply(code, x, trans=trans).cpu().numpy()
+            ref = packed_apply(P, x, c.nt, c.ng, trans=trans)
+            assert np.array_equal(y1, y2)
+            assert np.abs(y1 - ref).max() <= 1e-14 * np.abs(P).max() * np.abs(x).sum() ** 0.5 * c.n ** 0.5
+    M0 = c.matrix(L.M0).cpu().numpy().reshape(c.n, c.nv)
+    u = rng.standard_normal(c.nv)
+    np.testing.assert_allclose(c.apply(L.M0, u).cpu().numpy(), M0 @ u, rtol=1e-13, atol=1e-16)
+    np.testing.assert_allclose(c.apply(L.M0, x, trans=True).cpu().numpy(), M0.T @ x, rtol=1e-13, atol=1e-16)
+
+
+def test_rhs_and_solves_small(small):
+    wl, o, c, L = small
+    V, K, D, M0 = o.packed("V"), o.packed("K"), o.packed("D"), o.m0()
+    f_ref = o.rhs(K, M0, wl.g, wl.u0)
+    f = c.rhs(wl.g, wl.u0).cpu().numpy()
+    assert np.linalg.norm(f - f_ref) / np.linalg.norm(f_ref) < 1e-12
+    w_ref = o.solve_direct(V, f_ref)
+    for mode in (L.FP64, L.FP32_IR):
+        w, info = c.solve(f_ref, tol=1e-13, max_it=200, mode=mode, ir_tol=1e-13)
+        err = np.linalg.norm(w.cpu().numpy() - w_ref) / np.linalg.norm(w_ref)
+        print("mode", mode, "iters", info.iters, "outer", info.outer, "err", err, "true relres", info.true_relres)
+        assert err < 1e-10
+        assert info.status == 0
+    # adjoint solve: V^T lam = f
+    lam, info = c.solve(f_ref, tol=1e-13, max_it=200, trans=True)
+    lam_ref = o.solve_direct(V, f_ref) if False else None
+    import scipy.linalg as sla
+    A = o.dense(V)
+    lam_ref = sla.solve(A.T, f_ref)
+    assert np.linalg.norm(lam.cpu().numpy() - lam_ref) / np.linalg.norm(lam_ref) < 1e-10
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    wl = W.make("tiny")
+    o = Oracle.from_workload(wl)
+    import paper_1811_05224_amd as P
+    from paper_1811_05224_amd import _lib as L
+    c = P.Context.from_workload(wl)
+    c.assemble(L.V | L.K | L.D | L.M0)
+    return wl, o, c, L
+
+
+@pytest.mark.parametrize("op", ["V", "K", "D"])
+def test_tiny_all_entries(tiny, op):
+    wl, o, c, L = tiny
+    code = {"V": L.V, "K": L.K, "D": L.D}[op]
+    e = block_err(c.packed(code).cpu().numpy(), o.packed(op))
+    print(op, "tiny max floor-rule error", e.max())
+    assert e.max() <= TOL[op]
+
+
+def test_tiny_solution(tiny):
+    wl, o, c, L = tiny
+    V, K, M0 = o.packed("V"), o.packed("K"), o.m0()
+    f_ref = o.rhs(K, M0, wl.g, wl.u0)
+    w_ref = o.solve_direct(V, f_ref)
+    f = c.rhs(wl.g, wl.u0)
+    w, info = c.solve(f, tol=1e-13, max_it=200)
+    err = np.linalg.norm(w.cpu().numpy() - w_ref) / np.linalg.norm(w_ref)
+    print("tiny solve iters", info.iters, "err vs oracle", err)
+    assert err < 1e-10
