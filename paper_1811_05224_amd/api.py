@@ -41,6 +41,7 @@ class Context:
         if not torch.cuda.is_available():
             raise StbemError("no HIP device: this library runs only on the GPU")
         self.lib = L.load()
+        self.alpha_value = float(alpha)
         self.device = torch.device(device)
         torch.cuda.set_device(self.device)
         t = np.ascontiguousarray(t_nodes, dtype=np.float64)

@@ -69,6 +69,7 @@ __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restri
         qf = q_block(OP, lmax, block_min_lag(g.t, k, m), g.alpha);
     }
     __syncthreads();
+    if (tb.ser && (OP == OP_D || ((OP == OP_V || OP == OP_K) && qf <= 8))) return;   // dedicated far kernels
     const int i = (tile / tiles_1d) * kTile + tid / kTile;
     const int j = (tile % tiles_1d) * kTile + tid % kTile;
     if (i >= g.ng || j >= g.ng) return;
@@ -80,6 +81,218 @@ __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restri
         hi[off] = h;
         if (ST == ST_HILO) lo[off] = (float)(v - (double)h);
     }
+}
+
+// V_h and K_h on separated time elements (series), Gauss order Q fixed at
+// compile time so the Q x Q node pairs of a segment pair unroll into Q
+// independent series recurrences per step (instruction-level parallelism).
+template <int Q, bool NEED_V>
+__device__ __forceinline__ void far_pair(const Tables& T, const TimeBlock& tb, double al,
+                                         const double* P, const double* Qs, double nqx, double nqy,
+                                         double& m0, double& m1)
+{
+    // P, Qs: ax ay ex ey len; V: m0 = int int Delta F_V; K: shape moments of the
+    // double-layer kernel (x-y).n_Q/(2 pi r^2) Delta F_K (a/r^2 = alpha/4)
+    m0 = 0.0; m1 = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        const double sP = P[4] * T.gl_x[Q][a];
+        const double xx = P[0] + sP * P[2], xy = P[1] + sP * P[3];
+        double z[Q], l0[Q], l1[Q], acc[Q], cum[Q], dn[Q];
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            const double sQ = Qs[4] * T.gl_x[Q][c];
+            const double dx = xx - (Qs[0] + sQ * Qs[2]), dy = xy - (Qs[1] + sQ * Qs[3]);
+            z[c] = 0.25 * al * (dx * dx + dy * dy) * tb.inv_dc;
+            dn[c] = dx * nqx + dy * nqy;
+            l0[c] = 1.0; l1[c] = 1.0 - z[c]; acc[c] = tb.c[0]; cum[c] = 1.0;
+        }
+        for (int n = 1; n < tb.nterm; ++n) {
+            const int j = 2 * n - 1;
+            const double cn = tb.c[n], r1 = tb.rinv[j + 1], r2 = tb.rinv[j + 2];
+#pragma unroll
+            for (int c = 0; c < Q; ++c) {
+                const double x2 = ((2.0 * j + 1.0 - z[c]) * l1[c] - j * l0[c]) * r1;
+                const double x3 = ((2.0 * j + 3.0 - z[c]) * x2 - (j + 1.0) * l1[c]) * r2;
+                if (NEED_V) acc[c] += cn * x2;
+                else { cum[c] += l1[c] + x2; acc[c] += cn * cum[c]; }
+                l0[c] = x2; l1[c] = x3;
+            }
+        }
+        const double wP = P[4] * T.gl_w[Q][a];
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            const double e = exp(-z[c]);
+            if (NEED_V) {
+                m0 += wP * Qs[4] * T.gl_w[Q][c] * e * acc[c];
+            } else {
+                const double v = wP * Qs[4] * T.gl_w[Q][c] * dn[c] * e * acc[c];
+                m0 += v * (1.0 - T.gl_x[Q][c]);
+                m1 += v * T.gl_x[Q][c];
+            }
+        }
+    }
+    if (NEED_V) m0 *= tb.inv_dc * kInv4Pi;
+    else { const double f = al * 0.125 / kPi * tb.inv_dc * tb.inv_dc; m0 *= f; m1 *= f; }
+}
+
+template <int OP>
+__global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __restrict__ Tg, double lmax,
+                                                        int tiles_i, int tiles_j, double* __restrict__ out64)
+{
+    __shared__ Tables T;
+    __shared__ TimeBlock tb;
+    __shared__ int qf;
+    const int tid = threadIdx.x;
+    const long long tiles = (long long)tiles_i * tiles_j;
+    const long long b = blockIdx.x / tiles;
+    const int tile = (int)(blockIdx.x % tiles);
+    int k, m;
+    block_of(b, k, m);
+    if (k - m < 2) return;
+    if (tid == 0) {
+        time_block(g, k, m, tb);
+        qf = q_block(OP, lmax, block_min_lag(g.t, k, m), g.alpha);
+    }
+    {
+        const double* src = reinterpret_cast<const double*>(Tg);
+        double* dst = reinterpret_cast<double*>(&T);
+        for (int e = tid; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
+    }
+    __syncthreads();
+    if (!tb.ser || qf > 8) return;         // closed-form fallback or high order: generic kernel
+    const int ty = tid / kTile, tx = tid % kTile;
+    const int i = (tile / tiles_j) * kTile + ty;
+    // V: column j = J0 + tx.  K: the tile covers segments J0-1 .. J0+14 and
+    // writes the 15 hats J0 .. J0+14 (hat j = rising part on j-1 + falling on j)
+    const int J0 = (tile % tiles_j) * (OP == OP_K ? kTile - 1 : kTile);
+    int jseg = OP == OP_K ? J0 - 1 + tx : J0 + tx;
+    jseg = jseg < 0 ? jseg + g.ng : (jseg >= g.ng ? jseg - g.ng : jseg);
+    double m0 = 0.0, m1 = 0.0;
+    const bool live = i < g.ng && (OP == OP_K || jseg < g.ng) && (OP == OP_K || J0 + tx < g.ng);
+    if (live) {
+        const double P[5] = {g.vx[i], g.vy[i], g.ex[i], g.ey[i], g.len[i]};
+        const double Qs[5] = {g.vx[jseg], g.vy[jseg], g.ex[jseg], g.ey[jseg], g.len[jseg]};
+        const double nqx = g.ey[jseg], nqy = -g.ex[jseg];
+        const bool V = OP == OP_V;
+        switch (qf) {
+        case 3: V ? far_pair<3, true>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1) : far_pair<3, false>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1); break;
+        case 4: V ? far_pair<4, true>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1) : far_pair<4, false>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1); break;
+        case 5: V ? far_pair<5, true>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1) : far_pair<5, false>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1); break;
+        case 6: V ? far_pair<6, true>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1) : far_pair<6, false>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1); break;
+        case 7: V ? far_pair<7, true>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1) : far_pair<7, false>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1); break;
+        default: V ? far_pair<8, true>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1) : far_pair<8, false>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1); break;
+        }
+    }
+    const long long rowoff = b * (long long)g.ng * g.ng + (long long)i * g.ng;
+    if (OP == OP_V) {
+        if (live) out64[rowoff + J0 + tx] = m0;
+    } else {
+        // lanes of one tile row are consecutive: the rising moment of segment
+        // j - 1 sits in the lane to the left
+        const double left = __shfl_up(m1, 1, kTile);
+        const int j = J0 + tx - 1;
+        if (tx >= 1 && i < g.ng && j < g.ng) out64[rowoff + j] = left + m0;
+    }
+}
+
+// D_h on separated time elements (series), one 16 x 16 tile of dual
+// functions per workgroup.  The 2*16+2 half-segment pieces that carry the
+// tile's rows (and columns) are paired once: each pair gets its four shape
+// moments  int_P int_Q l_a(x) l_b(y) kappa(x, y),  l_0 = 1 - s/L, l_1 = s/L,
+// with the raw hypersingular kernel kappa = alpha n_P.n_Q dF_D - t_P^T Hess(F_V) t_Q
+// (smooth here); every entry then combines 4 x 4 pairs from LDS.
+constexpr int kDP = 2 * kTile + 2;     // pieces per tile side
+
+__global__ __launch_bounds__(kWG) void k_assemble_dfar(Geom g, const Tables* __restrict__ Tg, double lmax,
+                                                       int tiles_1d, double* __restrict__ out64,
+                                                       float* __restrict__ out32)
+{
+    __shared__ Tables T;
+    __shared__ TimeBlock tb;
+    __shared__ int qf;
+    __shared__ double mom[kDP][kDP][4];
+    __shared__ double pc[2][kDP][7];       // ax ay ex ey len nx ny
+    const int tid = threadIdx.x;
+    const long long tiles = (long long)tiles_1d * tiles_1d;
+    const long long b = blockIdx.x / tiles;
+    const int tile = (int)(blockIdx.x % tiles);
+    int k, m;
+    block_of(b, k, m);
+    if (k - m < 2) return;                 // touching elements: generic kernel
+    if (tid == 0) {
+        time_block(g, k, m, tb);
+        qf = q_block(OP_D, lmax, block_min_lag(g.t, k, m), g.alpha);
+    }
+    {
+        const double* src = reinterpret_cast<const double*>(Tg);
+        double* dst = reinterpret_cast<double*>(&T);
+        for (int e = tid; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
+    }
+    const int I0 = (tile / tiles_1d) * kTile, J0 = (tile % tiles_1d) * kTile;
+    const int np = 2 * g.ng;
+    if (tid < 2 * kDP) {
+        int side = tid / kDP, u = tid % kDP;
+        int base = side ? J0 : I0;
+        int h = ((2 * base - 1 + u) % np + np) % np;
+        Piece P = half_piece(g, h);
+        double* q = pc[side][u];
+        q[0] = P.ax; q[1] = P.ay; q[2] = P.ex; q[3] = P.ey; q[4] = P.len; q[5] = P.nx; q[6] = P.ny;
+    }
+    __syncthreads();
+    if (!tb.ser) {                          // closed-form fallback block: generic path
+        return;
+    }
+    const int q = qf;
+    const double al = g.alpha;
+    for (int e = tid; e < kDP * kDP; e += kWG) {
+        const int u = e / kDP, v = e % kDP;
+        const double* P = pc[0][u];
+        const double* Q = pc[1][v];
+        const double cn = al * (P[5] * Q[5] + P[6] * Q[6]);
+        const double tt = P[2] * Q[2] + P[3] * Q[3];
+        double m00 = 0, m01 = 0, m10 = 0, m11 = 0;
+        for (int a = 0; a < q; ++a) {
+            const double xa = T.gl_x[q][a];
+            const double sP = P[4] * xa, wP = P[4] * T.gl_w[q][a];
+            const double xx = P[0] + sP * P[2], xy = P[1] + sP * P[3];
+            double r0 = 0, r1 = 0;
+            for (int c = 0; c < q; ++c) {
+                const double xc = T.gl_x[q][c];
+                const double sQ = Q[4] * xc;
+                const double dx = xx - (Q[0] + sQ * Q[2]), dy = xy - (Q[1] + sQ * Q[3]);
+                const double r2 = dx * dx + dy * dy;
+                SeriesVals sv = series<false, false, true, true>(tb, 0.25 * al * r2);
+                const double zt = (dx * P[2] + dy * P[3]) * (dx * Q[2] + dy * Q[3]);
+                const double kap = cn * sv.dd - (0.25 * al * al * sv.vaa * zt + 0.5 * al * sv.va * tt);
+                const double w = Q[4] * T.gl_w[q][c] * kap;
+                r0 += w * (1.0 - xc);
+                r1 += w * xc;
+            }
+            m00 += wP * (1.0 - xa) * r0; m01 += wP * (1.0 - xa) * r1;
+            m10 += wP * xa * r0;         m11 += wP * xa * r1;
+        }
+        mom[u][v][0] = m00; mom[u][v][1] = m01; mom[u][v][2] = m10; mom[u][v][3] = m11;
+    }
+    __syncthreads();
+    const int i = I0 + tid / kTile, j = J0 + tid % kTile;
+    if (i >= g.ng || j >= g.ng) return;
+    DualSupport si = dual_support(g, i), sj = dual_support(g, j);
+    const int ui = 2 * (i - I0), vj = 2 * (j - J0);
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const double a0 = si.v0[u], a1 = si.v0[u] + si.slope[u] * pc[0][ui + u][4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double b0 = sj.v0[v], b1 = sj.v0[v] + sj.slope[v] * pc[1][vj + v][4];
+            const double* M = mom[ui + u][vj + v];
+            acc += a0 * (b0 * M[0] + b1 * M[1]) + a1 * (b0 * M[2] + b1 * M[3]);
+        }
+    }
+    const long long off = b * (long long)g.ng * g.ng + (long long)i * g.ng + j;
+    if (out64) out64[off] = acc;
+    else out32[off] = (float)acc;
 }
 
 template <int OP>
@@ -105,7 +318,7 @@ __global__ __launch_bounds__(kWG) void k_entries(Geom g, const Tables* __restric
 
 template <bool DERIV>
 __global__ __launch_bounds__(kWG) void k_m0(Geom g, Mesh2 mesh, const Tables* __restrict__ Tg, const M0Tables* __restrict__ Dg,
-                                            M0Orders MO, int nchunk, double* __restrict__ out)
+                                            M0Orders MO, M0Poly PP, int nchunk, double* __restrict__ out)
 {
     __shared__ Tables T;
     __shared__ M0Tables D;
@@ -129,7 +342,7 @@ __global__ __launch_bounds__(kWG) void k_m0(Geom g, Mesh2 mesh, const Tables* __
         qs = q_time(fmax(g.len[i], MO.omax), g.t[k], g.alpha) + 1;
         qs = qs < 4 ? 4 : qs;
     }
-    out[row * (long long)mesh.nv + j] = m0_entry<DERIV>(T, D, MO, g, mesh, k, i, j, qs, qs);
+    out[row * (long long)mesh.nv + j] = m0_entry<DERIV>(T, D, MO, g, mesh, k, i, j, qs, qs, PP);
 }
 
 // ---------------------------------------------------------------- GEMV
@@ -241,6 +454,105 @@ __global__ __launch_bounds__(kWG) void k_gemv_t_part32(const float* __restrict__
     red[grp][lane] = s;
     __syncthreads();
     if (grp == 0 && j < ng) part[b * ng + j] = (double)(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
+}
+
+// Vectorised block products: VW consecutive entries per lane load.
+// T: storage type; ACC: accumulation type; HILO: A + A2 (float pair).
+template <class T, int VW>
+struct VecLd {
+    typedef T type __attribute__((ext_vector_type(VW)));
+};
+
+template <class T, int VW, class ACC, bool HILO>
+__global__ __launch_bounds__(kWG) void k_gemv_n_vec(const T* __restrict__ A, const T* __restrict__ A2,
+                                                    const double* __restrict__ x, double* __restrict__ part,
+                                                    int ng, int rowchunks)
+{
+    typedef typename VecLd<T, VW>::type VT;
+    const long long b = blockIdx.x / rowchunks;
+    const int rc = (int)(blockIdx.x % rowchunks);
+    int k, m;
+    block_of(b, k, m);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long base = b * (long long)ng * ng;
+    const double* xm = x + (long long)m * ng;
+    const int span = 64 * VW;
+    ACC s[4] = {0, 0, 0, 0};
+    for (int c = lane * VW; c < ng; c += span) {
+        ACC xv[VW];
+#pragma unroll
+        for (int q = 0; q < VW; ++q) xv[q] = (ACC)xm[c + q];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int i = rc * 16 + wave * 4 + rr;
+            if (i < ng) {
+                const long long o = base + (long long)i * ng + c;
+                VT a = *reinterpret_cast<const VT*>(A + o);
+                if (HILO) {
+                    VT a2 = *reinterpret_cast<const VT*>(A2 + o);
+#pragma unroll
+                    for (int q = 0; q < VW; ++q) s[rr] += ((ACC)a[q] + (ACC)a2[q]) * xv[q];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < VW; ++q) s[rr] += (ACC)a[q] * xv[q];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        ACC v = s[rr];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        const int i = rc * 16 + wave * 4 + rr;
+        if (lane == 0 && i < ng) part[b * ng + i] = (double)v;
+    }
+}
+
+template <class T, int VW, class ACC, bool HILO>
+__global__ __launch_bounds__(kWG) void k_gemv_t_vec(const T* __restrict__ A, const T* __restrict__ A2,
+                                                    const double* __restrict__ x, double* __restrict__ part,
+                                                    int ng, int colchunks)
+{
+    typedef typename VecLd<T, VW>::type VT;
+    __shared__ ACC red[4][64 * VW];
+    const long long b = blockIdx.x / colchunks;
+    const int cc = (int)(blockIdx.x % colchunks);
+    int k, m;
+    block_of(b, k, m);
+    const int grp = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j0 = cc * 64 * VW + lane * VW;
+    const long long base = b * (long long)ng * ng;
+    const double* xk = x + (long long)k * ng;
+    ACC s[VW];
+#pragma unroll
+    for (int q = 0; q < VW; ++q) s[q] = 0;
+    if (j0 < ng) {
+#pragma unroll 4
+        for (int i = grp; i < ng; i += 4) {
+            const long long o = base + (long long)i * ng + j0;
+            const ACC xi = (ACC)xk[i];
+            VT a = *reinterpret_cast<const VT*>(A + o);
+            if (HILO) {
+                VT a2 = *reinterpret_cast<const VT*>(A2 + o);
+#pragma unroll
+                for (int q = 0; q < VW; ++q) s[q] += ((ACC)a[q] + (ACC)a2[q]) * xi;
+            } else {
+#pragma unroll
+                for (int q = 0; q < VW; ++q) s[q] += (ACC)a[q] * xi;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < VW; ++q) red[grp][lane * VW + q] = s[q];
+    __syncthreads();
+    if (grp == 0 && j0 < ng) {
+#pragma unroll
+        for (int q = 0; q < VW; ++q) {
+            const int c = lane * VW + q;
+            part[b * ng + j0 + q] = (double)(((red[0][c] + red[1][c]) + red[2][c]) + red[3][c]);
+        }
+    }
 }
 
 // y[k][i] = sum_{m<=k} part[b(k,m)][i]  (trans: y[m][j] = sum_{k>=m} part[b(k,m)][j])
@@ -410,6 +722,8 @@ struct stbem_ctx {
     // device copies
     double *d_t = nullptr, *d_vx = nullptr, *d_vy = nullptr, *d_ex = nullptr, *d_ey = nullptr, *d_len = nullptr;
     double *d_ox = nullptr, *d_oy = nullptr, *d_mt = nullptr;
+    double *d_m0c = nullptr, *d_m0cd = nullptr;
+    int* d_m0n = nullptr;
     int *d_tri = nullptr, *d_v2t_ptr = nullptr, *d_v2t = nullptr;
     Tables* d_tab = nullptr;
     M0Tables* d_m0tab = nullptr;
@@ -496,6 +810,13 @@ Geom geom(const stbem_ctx* c)
     return g;
 }
 
+M0Poly m0poly(const stbem_ctx* c)
+{
+    M0Poly p;
+    p.c = c->d_m0c; p.cd = c->d_m0cd; p.n = c->d_m0n;
+    return p;
+}
+
 Mesh2 mesh(const stbem_ctx* c)
 {
     Mesh2 m;
@@ -553,9 +874,32 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
     }
     double* o = c->mat[slot];
     switch (op) {
-    case STBEM_V: return launch_assemble<OP_V>(c, ST_F64, o, nullptr, nullptr, s);
-    case STBEM_K: return launch_assemble<OP_K>(c, ST_F64, o, nullptr, nullptr, s);
-    case STBEM_D: return launch_assemble<OP_D>(c, ST_F64, o, nullptr, nullptr, s);
+    case STBEM_V:
+    case STBEM_K: {
+        int rc = op == STBEM_V ? launch_assemble<OP_V>(c, ST_F64, o, nullptr, nullptr, s)
+                               : launch_assemble<OP_K>(c, ST_F64, o, nullptr, nullptr, s);
+        if (rc) return rc;
+        int ti = (c->ng + kTile - 1) / kTile;
+        int tj = op == STBEM_V ? ti : (c->ng + kTile - 2) / (kTile - 1);
+        long long nwg = c->nblk * (long long)ti * tj;
+        if (nwg > 0x7fffffffLL) return fail(c, STBEM_EINVAL, "problem too large for one launch");
+        if (op == STBEM_V)
+            hipLaunchKernelGGL(k_assemble_vkfar<OP_V>, dim3((unsigned)nwg), dim3(kWG), 0, s, geom(c), c->d_tab, c->lmax, ti, tj, o);
+        else
+            hipLaunchKernelGGL(k_assemble_vkfar<OP_K>, dim3((unsigned)nwg), dim3(kWG), 0, s, geom(c), c->d_tab, c->lmax, ti, tj, o);
+        HIPCHK(c, hipGetLastError());
+        return 0;
+    }
+    case STBEM_D: {
+        int rc = launch_assemble<OP_D>(c, ST_F64, o, nullptr, nullptr, s);
+        if (rc) return rc;
+        int t1 = (c->ng + kTile - 1) / kTile;
+        long long nwg = c->nblk * (long long)t1 * t1;
+        hipLaunchKernelGGL(k_assemble_dfar, dim3((unsigned)nwg), dim3(kWG), 0, s, geom(c), c->d_tab, c->lmax, t1, o,
+                           (float*)nullptr);
+        HIPCHK(c, hipGetLastError());
+        return 0;
+    }
     case STBEM_DV: return launch_assemble<OP_DV>(c, ST_F64, o, nullptr, nullptr, s);
     case STBEM_DK: return launch_assemble<OP_DK>(c, ST_F64, o, nullptr, nullptr, s);
     case STBEM_M0:
@@ -564,9 +908,9 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
         long long nwg = c->n * nchunk;
         if (nwg > 0x7fffffffLL) return fail(c, STBEM_EINVAL, "M0 too large for one launch");
         if (op == STBEM_M0)
-            hipLaunchKernelGGL((k_m0<false>), dim3((unsigned)nwg), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, nchunk, o);
+            hipLaunchKernelGGL((k_m0<false>), dim3((unsigned)nwg), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), nchunk, o);
         else
-            hipLaunchKernelGGL((k_m0<true>), dim3((unsigned)nwg), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, nchunk, o);
+            hipLaunchKernelGGL((k_m0<true>), dim3((unsigned)nwg), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), nchunk, o);
         HIPCHK(c, hipGetLastError());
         return 0;
     }
@@ -580,18 +924,44 @@ int packed_apply(stbem_ctx* c, const double* A, const float* hi, const float* lo
 {
     int rc = ensure_part(c);
     if (rc) return rc;
+    const int ng = c->ng;
+    // vector width: the row length must be a multiple of 64 * VW
+    const int vw64 = (ng % 128 == 0) ? 2 : 1;
+    const int vw32 = (ng % 256 == 0) ? 4 : (ng % 128 == 0 ? 2 : 1);
     if (!trans) {
-        int rowchunks = (c->ng + 15) / 16;
-        unsigned nwg = (unsigned)(c->nblk * rowchunks);
-        if (A) hipLaunchKernelGGL((k_gemv_n_part<double>), dim3(nwg), dim3(kWG), 0, s, A, (const double*)nullptr, x, c->part, c->ng, rowchunks);
-        else if (hi) hipLaunchKernelGGL((k_gemv_n_part<float>), dim3(nwg), dim3(kWG), 0, s, hi, lo, x, c->part, c->ng, rowchunks);
-        else hipLaunchKernelGGL(k_gemv_n_part32, dim3(nwg), dim3(kWG), 0, s, a32, x, c->part, c->ng, rowchunks);
+        int rowchunks = (ng + 15) / 16;
+        dim3 gr((unsigned)(c->nblk * rowchunks)), bl(kWG);
+        if (A) {
+            if (vw64 == 2) hipLaunchKernelGGL((k_gemv_n_vec<double, 2, double, false>), gr, bl, 0, s, A, (const double*)nullptr, x, c->part, ng, rowchunks);
+            else hipLaunchKernelGGL((k_gemv_n_vec<double, 1, double, false>), gr, bl, 0, s, A, (const double*)nullptr, x, c->part, ng, rowchunks);
+        } else if (hi) {
+            if (vw32 == 4) hipLaunchKernelGGL((k_gemv_n_vec<float, 4, double, true>), gr, bl, 0, s, hi, lo, x, c->part, ng, rowchunks);
+            else if (vw32 == 2) hipLaunchKernelGGL((k_gemv_n_vec<float, 2, double, true>), gr, bl, 0, s, hi, lo, x, c->part, ng, rowchunks);
+            else hipLaunchKernelGGL((k_gemv_n_vec<float, 1, double, true>), gr, bl, 0, s, hi, lo, x, c->part, ng, rowchunks);
+        } else {
+            if (vw32 == 4) hipLaunchKernelGGL((k_gemv_n_vec<float, 4, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, c->part, ng, rowchunks);
+            else if (vw32 == 2) hipLaunchKernelGGL((k_gemv_n_vec<float, 2, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, c->part, ng, rowchunks);
+            else hipLaunchKernelGGL((k_gemv_n_vec<float, 1, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, c->part, ng, rowchunks);
+        }
     } else {
-        int colchunks = (c->ng + 63) / 64;
-        unsigned nwg = (unsigned)(c->nblk * colchunks);
-        if (A) hipLaunchKernelGGL((k_gemv_t_part<double>), dim3(nwg), dim3(kWG), 0, s, A, (const double*)nullptr, x, c->part, c->ng, colchunks);
-        else if (hi) hipLaunchKernelGGL((k_gemv_t_part<float>), dim3(nwg), dim3(kWG), 0, s, hi, lo, x, c->part, c->ng, colchunks);
-        else hipLaunchKernelGGL(k_gemv_t_part32, dim3(nwg), dim3(kWG), 0, s, a32, x, c->part, c->ng, colchunks);
+        if (A) {
+            int cc = (ng + 64 * vw64 - 1) / (64 * vw64);
+            dim3 gr((unsigned)(c->nblk * cc)), bl(kWG);
+            if (vw64 == 2) hipLaunchKernelGGL((k_gemv_t_vec<double, 2, double, false>), gr, bl, 0, s, A, (const double*)nullptr, x, c->part, ng, cc);
+            else hipLaunchKernelGGL((k_gemv_t_vec<double, 1, double, false>), gr, bl, 0, s, A, (const double*)nullptr, x, c->part, ng, cc);
+        } else {
+            int cc = (ng + 64 * vw32 - 1) / (64 * vw32);
+            dim3 gr((unsigned)(c->nblk * cc)), bl(kWG);
+            if (hi) {
+                if (vw32 == 4) hipLaunchKernelGGL((k_gemv_t_vec<float, 4, double, true>), gr, bl, 0, s, hi, lo, x, c->part, ng, cc);
+                else if (vw32 == 2) hipLaunchKernelGGL((k_gemv_t_vec<float, 2, double, true>), gr, bl, 0, s, hi, lo, x, c->part, ng, cc);
+                else hipLaunchKernelGGL((k_gemv_t_vec<float, 1, double, true>), gr, bl, 0, s, hi, lo, x, c->part, ng, cc);
+            } else {
+                if (vw32 == 4) hipLaunchKernelGGL((k_gemv_t_vec<float, 4, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, c->part, ng, cc);
+                else if (vw32 == 2) hipLaunchKernelGGL((k_gemv_t_vec<float, 2, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, c->part, ng, cc);
+                else hipLaunchKernelGGL((k_gemv_t_vec<float, 1, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, c->part, ng, cc);
+            }
+        }
     }
     HIPCHK(c, hipGetLastError());
     hipLaunchKernelGGL(k_gemv_reduce, dim3(grid1(c->n)), dim3(kWG), 0, s, c->part, y, c->ng, c->nt, trans);
@@ -725,7 +1095,7 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
         return STBEM_EHIP;
     }
     c->ord = default_orders();
-    c->m0ord.qs_near = 12; c->m0ord.qt_near = 12; c->m0ord.near_ratio = 2.0;
+    c->m0ord.qs_near = 12; c->m0ord.qt_near = 12; c->m0ord.near_ratio = 0.5;
     c->m0ord.omax = 0.0;
     for (int t = 0; t < c->ntri; ++t)
         for (int e = 0; e < 3; ++e) {
@@ -733,6 +1103,46 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
             double d = std::hypot(c->ox[a] - c->ox[b], c->oy[a] - c->oy[b]);
             if (d > c->m0ord.omax) c->m0ord.omax = d;
         }
+    {
+        // M0 rows k >= 1: power series of ln(t1/t0) + Ein(a/t1) - Ein(a/t0) in
+        // a = alpha r^2 / 4, usable when a/t0 <= 2 for every pair (r <= R,
+        // the diameter of the bounding box of Gamma_h and Omega_h)
+        double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+        for (int v = 0; v < c->ng; ++v) { xmin = std::fmin(xmin, c->vx[v]); xmax = std::fmax(xmax, c->vx[v]); ymin = std::fmin(ymin, c->vy[v]); ymax = std::fmax(ymax, c->vy[v]); }
+        for (int v = 0; v < c->nv; ++v) { xmin = std::fmin(xmin, c->ox[v]); xmax = std::fmax(xmax, c->ox[v]); ymin = std::fmin(ymin, c->oy[v]); ymax = std::fmax(ymax, c->oy[v]); }
+        double R2 = (xmax - xmin) * (xmax - xmin) + (ymax - ymin) * (ymax - ymin);
+        double amax = 0.25 * c->alpha * R2;
+        std::vector<double> cf((size_t)c->nt * kPolyMax, 0.0), cfd((size_t)c->nt * kPolyMax, 0.0);
+        std::vector<int> nn(c->nt, 0);
+        for (int k = 1; k < c->nt; ++k) {
+            long double t0 = c->t[k], t1 = c->t[k + 1], h = (long double)c->t[k + 1] - (long double)c->t[k];
+            if (amax / (double)t0 > 2.0) continue;
+            double* co = &cf[(size_t)k * kPolyMax];
+            double* cd = &cfd[(size_t)k * kPolyMax];
+            co[0] = cd[0] = (double)logl(t1 / t0);
+            long double fact = 1, sum = 0, pw1 = 1, pw0 = 1;   // sum = sum_j t1^j t0^(n-1-j)
+            int n = 1;
+            bool conv = false;
+            for (; n < kPolyMax; ++n) {
+                // t1^-n - t0^-n = -h * S_n / (t0 t1)^n,  S_n = sum_{j<n} t1^j t0^{n-1-j}
+                sum = sum * t0 + pw1;           // S_n = t0 S_{n-1} + t1^{n-1}
+                pw1 *= t1; pw0 *= t0;
+                fact *= n;
+                long double en = -h * sum / (pw1 * pw0) / fact;  // (t1^-n - t0^-n)/n!
+                long double sg = (n & 1) ? 1.0L : -1.0L;       // (-1)^{n+1}
+                co[n] = (double)(sg * en / n);
+                cd[n] = (double)(sg * en * (1.0L / n + 1.0L));
+                long double tail = powl(amax / t0, n) / fact;
+                if (tail < 1e-18L * fabsl((long double)co[0]) && n > 2) { ++n; conv = true; break; }
+            }
+            nn[k] = conv ? n : 0;      // not converged: the E1 path is used
+        }
+        int rc2 = 0;
+        if ((rc2 = upload(c, &c->d_m0c, cf)) || (rc2 = upload(c, &c->d_m0cd, cfd)) || (rc2 = upload(c, &c->d_m0n, nn))) {
+            stbem_destroy(c);
+            return rc2;
+        }
+    }
     *out = c;
     return STBEM_OK;
 }
@@ -742,7 +1152,7 @@ int stbem_destroy(stbem_ctx* c)
     if (!c) return STBEM_OK;
     for (int s = 0; s < 7; ++s) dev_free(c, c->mat[s]);
     dev_free(c, c->v_hi); dev_free(c, c->v_lo); dev_free(c, c->d_32);
-    void* own[] = {c->d_t, c->d_vx, c->d_vy, c->d_ex, c->d_ey, c->d_len, c->d_ox, c->d_oy, c->d_mt,
+    void* own[] = {c->d_t, c->d_vx, c->d_vy, c->d_ex, c->d_ey, c->d_len, c->d_ox, c->d_oy, c->d_mt, c->d_m0c, c->d_m0cd, c->d_m0n,
                    c->d_tri, c->d_v2t_ptr, c->d_v2t, c->d_tab, c->d_m0tab, c->part};
     for (void* p : own) if (p) (void)hipFree(p);
     delete c;

@@ -195,13 +195,37 @@ SDEV double seg_tri_dist(const Piece& S, const Tri& tr)
 
 struct M0Orders { int qs_near, qt_near; double near_ratio, omax; };
 
+// For k >= 1, with z = a/t, E1(a/t_{k+1}) - E1(a/t_k) = ln(t_{k+1}/t_k)
+// + Ein(a/t_{k+1}) - Ein(a/t_k) is a power series in a; when a/t_k stays
+// <= 2 over the whole geometry it is evaluated from precomputed
+// coefficients (row-wise table, Horner).  DERIV adds -(e^{-a/t_{k+1}} - e^{-a/t_k}).
+constexpr int kPolyMax = 30;
+struct M0Poly { const double* c; const double* cd; const int* n; };   // [nt][kPolyMax], [nt]
+
+SDEV double m0_poly(const double* c, int n, double a)
+{
+    double p = c[n - 1];
+    for (int q = n - 2; q >= 0; --q) p = p * a + c[q];
+    return p;
+}
+
 // one entry M0[(k,i), j] (or its alpha-derivative)
 template <bool DERIV>
 SDEV double m0_entry(const Tables& T, const M0Tables& D, const M0Orders& MO, const Geom& g,
-                     const Mesh2& m, int k, int i, int j, int qs, int qt)
+                     const Mesh2& m, int k, int i, int j, int qs, int qt, const M0Poly& PP)
 {
     Piece S = seg_piece(g, i);
     double acc = 0.0;
+    if (k > 0 && PP.n[k] > 0) {
+        const double* c = (DERIV ? PP.cd : PP.c) + (long long)k * kPolyMax;
+        const int n = PP.n[k];
+        const double scale = (DERIV ? 1.0 : g.alpha) * kInv4Pi, q4 = 0.25 * g.alpha;
+        for (int p = m.v2t_ptr[j]; p < m.v2t_ptr[j + 1]; ++p) {
+            Tri tr = load_tri(m, m.v2t[p], j);
+            acc += m0_regular(T, S, tr, qs, qt, [&](double r2) { return m0_poly(c, n, q4 * r2); });
+        }
+        return scale * acc;
+    }
     for (int p = m.v2t_ptr[j]; p < m.v2t_ptr[j + 1]; ++p) {
         Tri tr = load_tri(m, m.v2t[p], j);
         if (k == 0) {
@@ -209,13 +233,21 @@ SDEV double m0_entry(const Tables& T, const M0Tables& D, const M0Orders& MO, con
             double diam = sqrt(fmax(fmax(dx1 * dx1 + dy1 * dy1, dx2 * dx2 + dy2 * dy2),
                                     (dx2 - dx1) * (dx2 - dx1) + (dy2 - dy1) * (dy2 - dy1)));
             double size = fmax(diam, S.len);
-            if (seg_tri_dist(S, tr) < MO.near_ratio * size) {
+            double eta = seg_tri_dist(S, tr) / size;
+            if (eta < MO.near_ratio) {
+                // touching or close: exact split S(r^2) - B ln r
                 double sm = m0_regular(T, S, tr, MO.qs_near, MO.qt_near,
                                        [&](double r2) { return m0_smooth0<DERIV>(g, r2, 0.5 * log(r2)); });
                 double B = DERIV ? kInv2Pi : g.alpha * kInv2Pi;
                 acc += sm - B * seg_log_potential(D, S, tr);
                 continue;
             }
+            // the log singularity sits at relative distance eta: Gauss order
+            // for a branch point at that distance (error ~ rho(eta)^(-2q))
+            int qn = eta >= 2.0 ? 8 : (eta >= 1.0 ? 12 : kMaxGL);
+            int q0s = qs > qn ? qs : qn, q0t = qt > qn ? qt : qn;
+            acc += m0_regular(T, S, tr, q0s, q0t, [&](double r2) { return m0_kernel<DERIV>(g, k, r2); });
+            continue;
         }
         acc += m0_regular(T, S, tr, qs, qt, [&](double r2) { return m0_kernel<DERIV>(g, k, r2); });
     }

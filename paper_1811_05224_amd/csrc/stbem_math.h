@@ -31,6 +31,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "e1_cheb_table.h"
+
 #define SDEV __host__ __device__ __forceinline__
 
 namespace stbem {
@@ -84,17 +86,27 @@ SDEV double ein(double z)
     return sum;
 }
 
-// E1(z) for z > 0: -gamma - ln z + Ein(z) for z <= 2; otherwise the
-// continued fraction e^{-z}/(z+1 - 1^2/(z+3 - 2^2/(z+5 - ...))) evaluated
-// from the tail, with a depth that gives full double precision for z > 2.
+// E1(z) for z > 0: -gamma - ln z + Ein(z) for z <= 2; on [2, 64) e^{-z}
+// times a Chebyshev expansion of e^z E1(z) per octave (generated with
+// mpmath, relative error < 2.5e-16); beyond, the continued fraction
+// e^{-z}/(z+1 - 1^2/(z+3 - 2^2/(z+5 - ...))) evaluated from the tail.
 SDEV double e1(double z)
 {
     if (z <= 2.0) return -kEuler - log(z) + ein(z);
     if (z > 740.0) return 0.0;
-    int nt = 4 + (int)(110.0 / z);
-    if (nt > 60) nt = 60;
+    if (z < 64.0) {
+        int o = z < 4.0 ? 0 : z < 8.0 ? 1 : z < 16.0 ? 2 : z < 32.0 ? 3 : 4;
+        double lo = (double)(2 << o), x = (z - 1.5 * lo) / (0.5 * lo);
+        const double* co = kE1Cheb[o];
+        double b1 = 0.0, b2 = 0.0;
+        for (int n = kE1ChebN[o] - 1; n >= 1; --n) {
+            double t = 2.0 * x * b1 - b2 + co[n];
+            b2 = b1; b1 = t;
+        }
+        return exp(-z) * (x * b1 - b2 + co[0]);
+    }
     double tail = 0.0;
-    for (int n = nt; n >= 1; --n) tail = (double)n * n / (z + 2.0 * n + 1.0 - tail);
+    for (int n = 6; n >= 1; --n) tail = (double)n * n / (z + 2.0 * n + 1.0 - tail);
     return exp(-z) / (z + 1.0 - tail);
 }
 
@@ -120,6 +132,7 @@ struct TimeBlock {
     int ndel;
     double dc, inv_dc;    // centre distance (separated)
     double c[kMaxTerms];  // mu_2n / dc^2n
+    double rinv[2 * kMaxTerms + 2];   // 1/n for the Laguerre recurrence
 };
 
 // Build the time block (k, m), k >= m, from the node array.
@@ -154,6 +167,8 @@ SDEV void time_block(const Geom& g, int k, int m, TimeBlock& tb)
             return;
         }
         tb.ser = 1;
+        tb.rinv[0] = 0.0;
+        for (int r = 1; r < 2 * kMaxTerms + 2; ++r) tb.rinv[r] = 1.0 / r;
         // mu_2n/dc^2n = 2 dc^2 [p^{2n+2} - q^{2n+2}] / ((2n+1)(2n+2))
         double p2 = p * p, q2 = q * q, pp = p2, qq = q2;
         int n = 0;
@@ -183,8 +198,8 @@ SDEV SeriesVals series(const TimeBlock& tb, double a)
     double sv = tb.c[0], sk = tb.c[0], sd = tb.c[0] * l1, s2 = tb.c[0];
     for (int n = 1; n < tb.nterm; ++n) {
         int j = 2 * n - 1;                  // advance to L_{2n}, L_{2n+1}
-        double l2 = ((2.0 * j + 1.0 - z) * l1 - j * l0) / (j + 1.0);
-        double l3 = ((2.0 * j + 3.0 - z) * l2 - (j + 1.0) * l1) / (j + 2.0);
+        double l2 = ((2.0 * j + 1.0 - z) * l1 - j * l0) * tb.rinv[j + 1];
+        double l3 = ((2.0 * j + 3.0 - z) * l2 - (j + 1.0) * l1) * tb.rinv[j + 2];
         double c1o = c1 + l1;               // L^(1)_{2n-1}
         if (NEED_H) c2 += c1o;              // L^(2)_{2n-1}
         c1 = c1o + l2;                      // L^(1)_{2n}

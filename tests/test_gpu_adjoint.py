@@ -1,0 +1,92 @@
+"""Adjoint gradients of J = 1/2 ||w_h(alpha, g) - w_obs||^2 through
+HeatFluxSolve (torch.autograd.Function over the C ABI): against the oracle's
+gradient (its own dV/dalpha, dK/dalpha, dM0/dalpha and dense adjoint solve)
+and against central differences with step 1e-6."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.oracle import Oracle, packed_apply
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(wl, alpha):
+    import paper_1811_05224_amd as P
+    from paper_1811_05224_amd import _lib as L
+    c = P.Context(alpha, wl.t_nodes, wl.bnd_xy, wl.vtx_xy, wl.tri)
+    c.assemble(L.V | L.K | L.D | L.M0 | L.DV | L.DK | L.DM0)
+    return c, L
+
+
+def _J(c, g, u0, w_obs, opts):
+    import torch
+    import paper_1811_05224_amd as P
+    gt = torch.as_tensor(g, device=c.device).requires_grad_(True)
+    at = torch.tensor(c.alpha_value, dtype=torch.float64, device=c.device, requires_grad=True)
+    w = P.HeatFluxSolve.apply(gt, at, c, torch.as_tensor(u0, device=c.device), opts)
+    J = 0.5 * ((w - torch.as_tensor(w_obs, device=c.device)) ** 2).sum()
+    return J, gt, at
+
+
+OPTS = dict(tol=1e-13, max_it=300)
+
+
+def test_gradient_vs_oracle_small():
+    wl = W.make("custom", n_side=3, n_t=4, n_omega=3, alpha=1.2, k=(0.7, 0.1))
+    rng = np.random.default_rng(7)
+    w_obs = wl.w_ref + 1e-3 * rng.standard_normal(wl.n)
+    c, L = _setup(wl, wl.alpha)
+    J, gt, at = _J(c, wl.g, wl.u0, w_obs, OPTS)
+    J.backward()
+    gg, ga = gt.grad.cpu().numpy(), float(at.grad)
+    # oracle gradient
+    o = Oracle.from_workload(wl)
+    V, K, M0 = o.packed("V"), o.packed("K"), o.m0()
+    dV, dK, dM0 = o.packed("dV"), o.packed("dK"), o.m0(deriv=True)
+    f = o.rhs(K, M0, wl.g, wl.u0)
+    w = o.solve_direct(V, f)
+    A = o.dense(V)
+    lam = np.linalg.solve(A.T, w - w_obs)
+    ref_g = 0.5 * o.mass_matrix().T @ lam + packed_apply(K, lam, o.nt, o.ng, trans=True)
+    ref_a = lam @ (packed_apply(dK, wl.g, o.nt, o.ng) - dM0 @ wl.u0 - packed_apply(dV, w, o.nt, o.ng))
+    print("grad_alpha gpu", ga, "oracle", ref_a)
+    assert np.linalg.norm(gg - ref_g) / np.linalg.norm(ref_g) < 1e-10
+    assert abs(ga - ref_a) / abs(ref_a) < 1e-9
+
+
+def test_gradient_vs_central_differences_diff_workload():
+    """Differentiation workload: 128 segments x 128 steps (N = 16384), data
+    from alpha* = 1.5, noise sigma = 1e-3, J at alpha = 1; FP64 and FP32-refined."""
+    import torch
+    from paper_1811_05224_amd import _lib as L
+    wl = W.make("diff")
+    w_obs = wl.w_ref + wl.extra["sigma"] * wl.extra["noise"]
+    alpha, h = 1.0, 1e-6
+    c, L = _setup(wl, alpha)
+    for mode in (L.FP64, L.FP32_IR):
+        opts = dict(tol=1e-12, max_it=300, mode=mode, ir_tol=1e-13)
+        J, gt, at = _J(c, wl.g, wl.u0, w_obs, opts)
+        J.backward()
+        ga = float(at.grad)
+        gg = gt.grad.cpu().numpy()
+        # directional central difference in g (J is quadratic in g)
+        d = np.random.default_rng(1).standard_normal(wl.n)
+        eps = 1e-6
+        Jp = float(_J(c, wl.g + eps * d, wl.u0, w_obs, opts)[0])
+        Jm = float(_J(c, wl.g - eps * d, wl.u0, w_obs, opts)[0])
+        fd_g = (Jp - Jm) / (2 * eps)
+        print("mode", mode, "directional dJ/dg: adjoint", gg @ d, "FD", fd_g)
+        assert abs(gg @ d - fd_g) <= 1e-6 * abs(fd_g)
+        if mode == L.FP64:
+            Jvals = []
+            for a in (alpha + h, alpha - h):
+                ca, _ = _setup(wl, a)
+                Jvals.append(float(_J(ca, wl.g, wl.u0, w_obs, opts)[0]))
+                ca.close()
+            fd_a = (Jvals[0] - Jvals[1]) / (2 * h)
+            print("dJ/dalpha: adjoint", ga, "FD", fd_a)
+            assert abs(ga - fd_a) <= 1e-6 * abs(fd_a)
+        ga64 = ga if mode == L.FP64 else ga64
+    print("FP32-refined vs FP64 dJ/dalpha rel diff", abs(ga - ga64) / abs(ga64))
+    assert abs(ga - ga64) <= 1e-8 * abs(ga64)
