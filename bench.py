@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="entries per operator for the oracle timing")
     ap.add_argument("--tol", type=float, default=1e-12)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device-to-device copy (scale for the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -58,6 +60,12 @@ def main():
 
     wl = W.make(args.workload)
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = P.Context.from_workload(wl, device=dev)
     g = torch.as_tensor(wl.g, device=dev)
     u0 = torch.as_tensor(wl.u0, device=dev)

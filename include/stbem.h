@@ -106,6 +106,12 @@ int stbem_sizes(const stbem_ctx* ctx, long long* n, int* n_bnd, int* n_t, int* n
  * never computed.  Re-assembling replaces the old storage. */
 int stbem_assemble(stbem_ctx* ctx, unsigned mask, void* stream);
 
+/* Free the storage of the operators in `mask` (and the FP32 copies when
+ * STBEM_V or STBEM_D is released), e.g. K_h and M_h^0 once the right-hand
+ * side is formed.  Synchronisation is the caller's: no kernel may still use
+ * that storage. */
+int stbem_release(stbem_ctx* ctx, unsigned mask);
+
 /* Device pointer and size in bytes of an assembled operator's storage
  * (op is one of STBEM_V ... STBEM_DM0); owned by the context. */
 int stbem_matrix(stbem_ctx* ctx, unsigned op, const double** dev_ptr, size_t* bytes);

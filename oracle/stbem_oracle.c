@@ -9,7 +9,9 @@
  * What it computes (all in x87 long double, slowly and plainly):
  *   U*(z,s) = alpha/(4 pi s) exp(-alpha|z|^2/(4s))            (Sec. 1)
  *   V_h, K_h, M_h^0 of eq.(4)                                   (Sec. 1)
- *   D_h on the dual mesh, integration-by-parts form             (Sec. 2, Thm 1)
+ *   D_h on the dual mesh: integration-by-parts form on touching time
+ *   elements, the raw kernel -d_nx d_ny k (its definition, D = -d_n W)
+ *   on separated ones, where it is smooth                      (Sec. 2, Thm 1)
  *   and the alpha-derivatives of V_h, K_h, M_h^0.
  *
  * Time integrals are exact: for a kernel kappa(t - tau) that vanishes for
@@ -119,6 +121,14 @@ static R kappa(int kind, R a, R s)
     return NAN;
 }
 
+/* raw hypersingular kernel -d_nx d_ny k (Sec. 2: D = -d_n W):
+ * k(s) [ (alpha^2/(4 s^2)) (z.n_x)(z.n_y) - (alpha/(2 s)) n_x.n_y ] */
+static R kappa_raw(R alpha, R a, R s, R zx, R zy, R nn)
+{
+    R k = expl(-a / s) / (4 * PI_L * s);
+    return k * (alpha * alpha / (4 * s * s) * zx * zy - alpha / (2 * s) * nn);
+}
+
 #define TQ_N 20
 static R gl_x[33][32], gl_w[33][32];
 static R tquad(int kind, R a, const TB* b)
@@ -134,6 +144,24 @@ static R tquad(int kind, R a, const TB* b)
             R s = lo + (hi - lo) * gl_x[TQ_N][q];
             R w = fminl(b->tk1, b->tm1 + s) - fmaxl(b->tk0, b->tm0 + s);
             if (w > 0) sum += (hi - lo) * gl_w[TQ_N][q] * w * kappa(kind, a, s);
+        }
+    }
+    return sum;
+}
+
+static R tquad_raw(R alpha, R a, R zx, R zy, R nn, const TB* b)
+{
+    R br[4] = {b->tk0 - b->tm1, b->tk0 - b->tm0, b->tk1 - b->tm1, b->tk1 - b->tm0};
+    for (int i = 1; i < 4; ++i)
+        for (int j = i; j > 0 && br[j] < br[j - 1]; --j) { R t = br[j]; br[j] = br[j - 1]; br[j - 1] = t; }
+    R sum = 0;
+    for (int p = 0; p < 3; ++p) {
+        R lo = br[p], hi = br[p + 1];
+        if (!(hi > lo)) continue;
+        for (int q = 0; q < TQ_N; ++q) {
+            R s = lo + (hi - lo) * gl_x[TQ_N][q];
+            R w = fminl(b->tk1, b->tm1 + s) - fmaxl(b->tk0, b->tm0 + s);
+            if (w > 0) sum += (hi - lo) * gl_w[TQ_N][q] * w * kappa_raw(alpha, a, s, zx, zy, nn);
         }
     }
     return sum;
@@ -391,8 +419,20 @@ static void kern(const KC* c, R sP, R sQ, R dx, R dy, R* out)
         out[0] = g * (1 - l1); out[1] = g * l1;
         break; }
     case OP_D: {
-        R fv = sep ? tquad(0, a, &c->tb) : delta4(FV, a, &c->tb), fd = sep ? tquad(2, a, &c->tb) : delta4(FD, a, &c->tb);
         R p1 = sP / c->P->L, q1 = sQ / c->Q->L;
+        if (sep) {
+            /* separated time elements: the kernel is smooth, D is taken from
+             * its definition, the raw kernel; out[0] (curl part) unused and
+             * out[1..4] already carry alpha n.n */
+            R zx = dx * c->P->nx + dy * c->P->ny, zy = dx * c->Q->nx + dy * c->Q->ny;
+            R nn = c->P->nx * c->Q->nx + c->P->ny * c->Q->ny;
+            R raw = tquad_raw(c->pr->alpha, a, zx, zy, nn, &c->tb);
+            out[0] = 0;
+            out[1] = raw * (1 - p1) * (1 - q1); out[2] = raw * (1 - p1) * q1;
+            out[3] = raw * p1 * (1 - q1);       out[4] = raw * p1 * q1;
+            break;
+        }
+        R fv = delta4(FV, a, &c->tb), fd = delta4(FD, a, &c->tb);
         out[0] = fv;
         out[1] = fd * (1 - p1) * (1 - q1); out[2] = fd * (1 - p1) * q1;
         out[3] = fd * p1 * (1 - q1);       out[4] = fd * p1 * q1;
@@ -522,7 +562,7 @@ static R entry(const Prob* p, int op, int k, int m, int i, int j)
                 Piece P = half_piece(p, pi[u]), Q = half_piece(p, pj[v]);
                 c.P = &P; c.Q = &Q;
                 pair_integral(&c, out);
-                R nn = P.nx * Q.nx + P.ny * Q.ny;
+                R nn = c.tb.d >= 2 ? 1.0L / p->alpha : P.nx * Q.nx + P.ny * Q.ny;   /* raw form carries alpha n.n */
                 acc += da[u] * db[v] * out[0]
                      + p->alpha * nn * (a0[u] * b0[v] * out[1] + a0[u] * b1[v] * out[2]
                                       + a1[u] * b0[v] * out[3] + a1[u] * b1[v] * out[4]);

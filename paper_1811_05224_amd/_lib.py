@@ -52,6 +52,7 @@ def load():
         "stbem_set_allocator": (ctypes.c_int, [vp, ALLOC_FN, FREE_FN, vp]),
         "stbem_sizes": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_longlong), ip, ip, ip, ctypes.POINTER(ctypes.c_longlong)]),
         "stbem_assemble": (ctypes.c_int, [vp, ctypes.c_uint, vp]),
+        "stbem_release": (ctypes.c_int, [vp, ctypes.c_uint]),
         "stbem_matrix": (ctypes.c_int, [vp, ctypes.c_uint, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]),
         "stbem_apply": (ctypes.c_int, [vp, ctypes.c_uint, ctypes.c_int, vp, vp, vp]),
         "stbem_mass": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
@@ -70,5 +71,5 @@ def load():
 
 
 EXPORTED = ["stbem_create", "stbem_destroy", "stbem_last_error", "stbem_set_allocator", "stbem_sizes",
-            "stbem_assemble", "stbem_matrix", "stbem_apply", "stbem_mass", "stbem_precondition", "stbem_rhs",
+            "stbem_assemble", "stbem_release", "stbem_matrix", "stbem_apply", "stbem_mass", "stbem_precondition", "stbem_rhs",
             "stbem_prepare_ir", "stbem_solve", "stbem_grad_alpha", "stbem_entries"]

@@ -112,6 +112,10 @@ class Context:
     def assemble(self, mask):
         self._check(self.lib.stbem_assemble(self._h, int(mask), self._stream()), "stbem_assemble")
 
+    def release(self, mask):
+        torch.cuda.current_stream().synchronize()
+        self._check(self.lib.stbem_release(self._h, int(mask)), "stbem_release")
+
     def matrix(self, op):
         """The operator's storage as a float64 tensor (packed blocks or dense M0)."""
         p, nb = ctypes.c_void_p(), ctypes.c_size_t()

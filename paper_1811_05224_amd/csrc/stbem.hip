@@ -46,7 +46,7 @@ enum Store { ST_F64 = 0, ST_F32 = 1, ST_HILO = 2 };
 
 template <int OP, int ST>
 __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restrict__ Tg, Orders O,
-                                                  double lmax, long long nblk, int tiles_1d,
+                                                  double lmax, const int* __restrict__ blist, int tiles_1d,
                                                   double* __restrict__ out64, float* __restrict__ hi,
                                                   float* __restrict__ lo)
 {
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restri
         for (int e = tid; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
     }
     const long long tiles = (long long)tiles_1d * tiles_1d;
-    const long long b = blockIdx.x / tiles;
+    const long long b = blist[blockIdx.x / tiles];
     const int tile = (int)(blockIdx.x % tiles);
     int k, m;
     block_of(b, k, m);
@@ -69,7 +69,6 @@ __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restri
         qf = q_block(OP, lmax, block_min_lag(g.t, k, m), g.alpha);
     }
     __syncthreads();
-    if (tb.ser && (OP == OP_D || ((OP == OP_V || OP == OP_K) && qf <= 8))) return;   // dedicated far kernels
     const int i = (tile / tiles_1d) * kTile + tid / kTile;
     const int j = (tile % tiles_1d) * kTile + tid % kTile;
     if (i >= g.ng || j >= g.ng) return;
@@ -94,7 +93,7 @@ __device__ __forceinline__ void far_pair(const Tables& T, const TimeBlock& tb, d
     // P, Qs: ax ay ex ey len; V: m0 = int int Delta F_V; K: shape moments of the
     // double-layer kernel (x-y).n_Q/(2 pi r^2) Delta F_K (a/r^2 = alpha/4)
     m0 = 0.0; m1 = 0.0;
-#pragma unroll
+#pragma unroll 1
     for (int a = 0; a < Q; ++a) {
         const double sP = P[4] * T.gl_x[Q][a];
         const double xx = P[0] + sP * P[2], xy = P[1] + sP * P[3];
@@ -136,31 +135,26 @@ __device__ __forceinline__ void far_pair(const Tables& T, const TimeBlock& tb, d
     else { const double f = al * 0.125 / kPi * tb.inv_dc * tb.inv_dc; m0 *= f; m1 *= f; }
 }
 
-template <int OP>
-__global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __restrict__ Tg, double lmax,
-                                                        int tiles_i, int tiles_j, double* __restrict__ out64)
+template <int OP, int Q>
+__global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __restrict__ Tg,
+                                                        const int* __restrict__ blist, int tiles_i, int tiles_j,
+                                                        double* __restrict__ out64)
 {
     __shared__ Tables T;
     __shared__ TimeBlock tb;
-    __shared__ int qf;
     const int tid = threadIdx.x;
     const long long tiles = (long long)tiles_i * tiles_j;
-    const long long b = blockIdx.x / tiles;
+    const long long b = blist[blockIdx.x / tiles];
     const int tile = (int)(blockIdx.x % tiles);
     int k, m;
     block_of(b, k, m);
-    if (k - m < 2) return;
-    if (tid == 0) {
-        time_block(g, k, m, tb);
-        qf = q_block(OP, lmax, block_min_lag(g.t, k, m), g.alpha);
-    }
+    if (tid == 0) time_block(g, k, m, tb);
     {
         const double* src = reinterpret_cast<const double*>(Tg);
         double* dst = reinterpret_cast<double*>(&T);
         for (int e = tid; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
     }
     __syncthreads();
-    if (!tb.ser || qf > 8) return;         // closed-form fallback or high order: generic kernel
     const int ty = tid / kTile, tx = tid % kTile;
     const int i = (tile / tiles_j) * kTile + ty;
     // V: column j = J0 + tx.  K: the tile covers segments J0-1 .. J0+14 and
@@ -169,20 +163,11 @@ __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __
     int jseg = OP == OP_K ? J0 - 1 + tx : J0 + tx;
     jseg = jseg < 0 ? jseg + g.ng : (jseg >= g.ng ? jseg - g.ng : jseg);
     double m0 = 0.0, m1 = 0.0;
-    const bool live = i < g.ng && (OP == OP_K || jseg < g.ng) && (OP == OP_K || J0 + tx < g.ng);
+    const bool live = i < g.ng && (OP == OP_K || J0 + tx < g.ng);
     if (live) {
         const double P[5] = {g.vx[i], g.vy[i], g.ex[i], g.ey[i], g.len[i]};
         const double Qs[5] = {g.vx[jseg], g.vy[jseg], g.ex[jseg], g.ey[jseg], g.len[jseg]};
-        const double nqx = g.ey[jseg], nqy = -g.ex[jseg];
-        const bool V = OP == OP_V;
-        switch (qf) {
-        case 3: V ? far_pair<3, true>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1) : far_pair<3, false>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1); break;
-        case 4: V ? far_pair<4, true>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1) : far_pair<4, false>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1); break;
-        case 5: V ? far_pair<5, true>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1) : far_pair<5, false>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1); break;
-        case 6: V ? far_pair<6, true>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1) : far_pair<6, false>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1); break;
-        case 7: V ? far_pair<7, true>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1) : far_pair<7, false>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1); break;
-        default: V ? far_pair<8, true>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1) : far_pair<8, false>(T, tb, g.alpha, P, Qs, nqx, nqy, m0, m1); break;
-        }
+        far_pair<Q, OP == OP_V>(T, tb, g.alpha, P, Qs, g.ey[jseg], -g.ex[jseg], m0, m1);
     }
     const long long rowoff = b * (long long)g.ng * g.ng + (long long)i * g.ng;
     if (OP == OP_V) {
@@ -204,26 +189,84 @@ __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __
 // (smooth here); every entry then combines 4 x 4 pairs from LDS.
 constexpr int kDP = 2 * kTile + 2;     // pieces per tile side
 
+// four shape moments of the raw hypersingular kernel for one piece pair,
+// Q x Q Gauss nodes, the Q series of a row of nodes advanced together
+template <int Q>
+__device__ __forceinline__ void far_dpair(const Tables& T, const TimeBlock& tb, double al,
+                                          const double* P, const double* Qs, double* mom)
+{
+    const double cn = al * (P[5] * Qs[5] + P[6] * Qs[6]);
+    const double tt = P[2] * Qs[2] + P[3] * Qs[3];
+    double m00 = 0, m01 = 0, m10 = 0, m11 = 0;
+#pragma unroll 1
+    for (int a = 0; a < Q; ++a) {
+        const double xa = T.gl_x[Q][a];
+        const double sP = P[4] * xa, wP = P[4] * T.gl_w[Q][a];
+        const double xx = P[0] + sP * P[2], xy = P[1] + sP * P[3];
+        double z[Q], l0[Q], l1[Q], c1[Q], c2[Q], sd[Q], sk[Q], s2[Q], zt[Q];
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            const double sQ = Qs[4] * T.gl_x[Q][c];
+            const double dx = xx - (Qs[0] + sQ * Qs[2]), dy = xy - (Qs[1] + sQ * Qs[3]);
+            z[c] = 0.25 * al * (dx * dx + dy * dy) * tb.inv_dc;
+            zt[c] = (dx * P[2] + dy * P[3]) * (dx * Qs[2] + dy * Qs[3]);
+            l0[c] = 1.0; l1[c] = 1.0 - z[c]; c1[c] = 1.0; c2[c] = 1.0;
+            sd[c] = tb.c[0] * l1[c]; sk[c] = tb.c[0]; s2[c] = tb.c[0];
+        }
+        for (int n = 1; n < tb.nterm; ++n) {
+            const int j = 2 * n - 1;
+            const double cn_ = tb.c[n], r1 = tb.rinv[j + 1], r2 = tb.rinv[j + 2], f3 = 2.0 * n + 1.0;
+#pragma unroll
+            for (int c = 0; c < Q; ++c) {
+                const double x2 = ((2.0 * j + 1.0 - z[c]) * l1[c] - j * l0[c]) * r1;
+                const double x3 = ((2.0 * j + 3.0 - z[c]) * x2 - (j + 1.0) * l1[c]) * r2;
+                const double c1o = c1[c] + l1[c];
+                c2[c] += c1o;
+                c1[c] = c1o + x2;
+                c2[c] += c1[c];
+                sk[c] += cn_ * c1[c];
+                sd[c] += cn_ * f3 * x3;
+                s2[c] += cn_ * c2[c];
+                l0[c] = x2; l1[c] = x3;
+            }
+        }
+        double r0 = 0, r1s = 0;
+        const double i1 = tb.inv_dc, i2 = i1 * i1;
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            const double e = exp(-z[c]);
+            const double dd = -e * i2 * kInv4Pi * sd[c];
+            const double va = -e * i2 * kInv4Pi * sk[c];
+            const double vaa = e * i2 * i1 * kInv4Pi * s2[c];
+            const double kap = cn * dd - (0.25 * al * al * vaa * zt[c] + 0.5 * al * va * tt);
+            const double xc = T.gl_x[Q][c];
+            const double w = Qs[4] * T.gl_w[Q][c] * kap;
+            r0 += w * (1.0 - xc);
+            r1s += w * xc;
+        }
+        m00 += wP * (1.0 - xa) * r0; m01 += wP * (1.0 - xa) * r1s;
+        m10 += wP * xa * r0;         m11 += wP * xa * r1s;
+    }
+    mom[0] = m00; mom[1] = m01; mom[2] = m10; mom[3] = m11;
+}
+
+
+template <int Q>
 __global__ __launch_bounds__(kWG) void k_assemble_dfar(Geom g, const Tables* __restrict__ Tg, double lmax,
-                                                       int tiles_1d, double* __restrict__ out64,
-                                                       float* __restrict__ out32)
+                                                       const int* __restrict__ blist, int tiles_1d,
+                                                       double* __restrict__ out64, float* __restrict__ out32)
 {
     __shared__ Tables T;
     __shared__ TimeBlock tb;
-    __shared__ int qf;
     __shared__ double mom[kDP][kDP][4];
     __shared__ double pc[2][kDP][7];       // ax ay ex ey len nx ny
     const int tid = threadIdx.x;
     const long long tiles = (long long)tiles_1d * tiles_1d;
-    const long long b = blockIdx.x / tiles;
+    const long long b = blist[blockIdx.x / tiles];
     const int tile = (int)(blockIdx.x % tiles);
     int k, m;
     block_of(b, k, m);
-    if (k - m < 2) return;                 // touching elements: generic kernel
-    if (tid == 0) {
-        time_block(g, k, m, tb);
-        qf = q_block(OP_D, lmax, block_min_lag(g.t, k, m), g.alpha);
-    }
+    if (tid == 0) time_block(g, k, m, tb);
     {
         const double* src = reinterpret_cast<const double*>(Tg);
         double* dst = reinterpret_cast<double*>(&T);
@@ -240,39 +283,9 @@ __global__ __launch_bounds__(kWG) void k_assemble_dfar(Geom g, const Tables* __r
         q[0] = P.ax; q[1] = P.ay; q[2] = P.ex; q[3] = P.ey; q[4] = P.len; q[5] = P.nx; q[6] = P.ny;
     }
     __syncthreads();
-    if (!tb.ser) {                          // closed-form fallback block: generic path
-        return;
-    }
-    const int q = qf;
-    const double al = g.alpha;
     for (int e = tid; e < kDP * kDP; e += kWG) {
         const int u = e / kDP, v = e % kDP;
-        const double* P = pc[0][u];
-        const double* Q = pc[1][v];
-        const double cn = al * (P[5] * Q[5] + P[6] * Q[6]);
-        const double tt = P[2] * Q[2] + P[3] * Q[3];
-        double m00 = 0, m01 = 0, m10 = 0, m11 = 0;
-        for (int a = 0; a < q; ++a) {
-            const double xa = T.gl_x[q][a];
-            const double sP = P[4] * xa, wP = P[4] * T.gl_w[q][a];
-            const double xx = P[0] + sP * P[2], xy = P[1] + sP * P[3];
-            double r0 = 0, r1 = 0;
-            for (int c = 0; c < q; ++c) {
-                const double xc = T.gl_x[q][c];
-                const double sQ = Q[4] * xc;
-                const double dx = xx - (Q[0] + sQ * Q[2]), dy = xy - (Q[1] + sQ * Q[3]);
-                const double r2 = dx * dx + dy * dy;
-                SeriesVals sv = series<false, false, true, true>(tb, 0.25 * al * r2);
-                const double zt = (dx * P[2] + dy * P[3]) * (dx * Q[2] + dy * Q[3]);
-                const double kap = cn * sv.dd - (0.25 * al * al * sv.vaa * zt + 0.5 * al * sv.va * tt);
-                const double w = Q[4] * T.gl_w[q][c] * kap;
-                r0 += w * (1.0 - xc);
-                r1 += w * xc;
-            }
-            m00 += wP * (1.0 - xa) * r0; m01 += wP * (1.0 - xa) * r1;
-            m10 += wP * xa * r0;         m11 += wP * xa * r1;
-        }
-        mom[u][v][0] = m00; mom[u][v][1] = m01; mom[u][v][2] = m10; mom[u][v][3] = m11;
+        far_dpair<Q>(T, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v]);
     }
     __syncthreads();
     const int i = I0 + tid / kTile, j = J0 + tid % kTile;
@@ -316,9 +329,13 @@ __global__ __launch_bounds__(kWG) void k_entries(Geom g, const Tables* __restric
     out[e] = entry<OP>(T, O, g, tb, qf, i, j);
 }
 
-template <bool DERIV>
-__global__ __launch_bounds__(kWG) void k_m0(Geom g, Mesh2 mesh, const Tables* __restrict__ Tg, const M0Tables* __restrict__ Dg,
-                                            M0Orders MO, M0Poly PP, int nchunk, double* __restrict__ out)
+// M_h^0, pass 1: the three barycentric moments of every (row, triangle) pair
+// of a chunk of rows into scratch[row - row0][t][v].
+template <bool DERIV, bool FIRST>
+__global__ __launch_bounds__(kWG) void k_m0_tri(Geom g, Mesh2 mesh, const Tables* __restrict__ Tg,
+                                                const M0Tables* __restrict__ Dg, M0Orders MO, M0Poly PP,
+                                                long long row0, long long lrow0, int nchunk,
+                                                double* __restrict__ scratch)
 {
     __shared__ Tables T;
     __shared__ M0Tables D;
@@ -331,18 +348,35 @@ __global__ __launch_bounds__(kWG) void k_m0(Geom g, Mesh2 mesh, const Tables* __
         for (int e = threadIdx.x; e < (int)(sizeof(M0Tables) / sizeof(double)); e += kWG) d2[e] = s2[e];
     }
     __syncthreads();
-    const long long row = blockIdx.x / nchunk;           // row = k * ng + i
-    const int j = (int)(blockIdx.x % nchunk) * kWG + threadIdx.x;
-    if (j >= mesh.nv) return;
+    const long long lrow = lrow0 + blockIdx.x / nchunk;       // row within the chunk
+    const int t = (int)(blockIdx.x % nchunk) * kWG + threadIdx.x;
+    if (t >= mesh.ntri) return;
+    const long long row = row0 + lrow;          // row = k * ng + i
     const int k = (int)(row / g.ng), i = (int)(row % g.ng);
-    // k >= 1: smooth kernel on the time scale sqrt(4 t_k / alpha);
-    // k = 0: triangles away from the segment see a log kernel at distance >= 2 sizes
+    // k >= 1: the kernel varies on the time scale sqrt(4 t_k / alpha)
     int qs = 8;
     if (k > 0) {
         qs = q_time(fmax(g.len[i], MO.omax), g.t[k], g.alpha) + 1;
         qs = qs < 4 ? 4 : qs;
     }
-    out[row * (long long)mesh.nv + j] = m0_entry<DERIV>(T, D, MO, g, mesh, k, i, j, qs, qs, PP);
+    double mom[3];
+    m0_tri_moments<DERIV, FIRST>(T, D, MO, g, mesh, PP, k, i, t, qs, mom);
+    double* o = scratch + (lrow * mesh.ntri + t) * 3;
+    o[0] = mom[0]; o[1] = mom[1]; o[2] = mom[2];
+}
+
+// pass 2: M0[row][j] = sum over the triangles of vertex j (fixed order)
+__global__ __launch_bounds__(kWG) void k_m0_gather(Mesh2 mesh, const int* __restrict__ v2t_loc, long long row0,
+                                                   int nchunk, const double* __restrict__ scratch,
+                                                   double* __restrict__ out)
+{
+    const long long lrow = blockIdx.x / nchunk;
+    const int j = (int)(blockIdx.x % nchunk) * kWG + threadIdx.x;
+    if (j >= mesh.nv) return;
+    const double* sr = scratch + lrow * mesh.ntri * 3;
+    double acc = 0.0;
+    for (int p = mesh.v2t_ptr[j]; p < mesh.v2t_ptr[j + 1]; ++p) acc += sr[mesh.v2t[p] * 3 + v2t_loc[p]];
+    out[(row0 + lrow) * mesh.nv + j] = acc;
 }
 
 // ---------------------------------------------------------------- GEMV
@@ -718,12 +752,12 @@ struct stbem_ctx {
     long long n = 0, nblk = 0, packed = 0;
     double alpha = 0, lmax = 0;
     std::vector<double> t, vx, vy, ex, ey, len, ox, oy;
-    std::vector<int> tri, v2t_ptr, v2t;
+    std::vector<int> tri, v2t_ptr, v2t, v2t_loc;
     // device copies
     double *d_t = nullptr, *d_vx = nullptr, *d_vy = nullptr, *d_ex = nullptr, *d_ey = nullptr, *d_len = nullptr;
     double *d_ox = nullptr, *d_oy = nullptr, *d_mt = nullptr;
-    double *d_m0c = nullptr, *d_m0cd = nullptr;
-    int* d_m0n = nullptr;
+    double *d_m0c = nullptr, *d_m0cd = nullptr, *d_m0amax = nullptr;
+    int *d_m0n = nullptr, *d_v2t_loc = nullptr;
     int *d_tri = nullptr, *d_v2t_ptr = nullptr, *d_v2t = nullptr;
     Tables* d_tab = nullptr;
     M0Tables* d_m0tab = nullptr;
@@ -733,6 +767,10 @@ struct stbem_ctx {
     double* mat[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};   // V K D M0 DV DK DM0
     size_t mat_bytes[7] = {0, 0, 0, 0, 0, 0, 0};
     float *v_hi = nullptr, *v_lo = nullptr, *d_32 = nullptr;
+    // block lists per operator slot: [generic | far Q=3..8 (V, K) or tile kernel (D)]
+    int* d_blist[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int nlist_gen[7] = {0, 0, 0, 0, 0, 0, 0};
+    int nlist_far[7][9] = {};
     // work
     double* part = nullptr;     // nblk * ng
     size_t part_bytes = 0;
@@ -813,7 +851,7 @@ Geom geom(const stbem_ctx* c)
 M0Poly m0poly(const stbem_ctx* c)
 {
     M0Poly p;
-    p.c = c->d_m0c; p.cd = c->d_m0cd; p.n = c->d_m0n;
+    p.c = c->d_m0c; p.cd = c->d_m0cd; p.n = c->d_m0n; p.amax = c->d_m0amax;
     return p;
 }
 
@@ -846,17 +884,74 @@ int ensure_part(stbem_ctx* c)
 template <int OP>
 int launch_assemble(stbem_ctx* c, int store, double* o64, float* hi, float* lo, hipStream_t s)
 {
+    const int slot = OP == OP_V ? 0 : OP == OP_K ? 1 : OP == OP_D ? 2 : OP == OP_DV ? 4 : 5;
     int t1 = (c->ng + kTile - 1) / kTile;
-    long long nwg = c->nblk * (long long)t1 * t1;
+    long long nwg = c->nlist_gen[slot] * (long long)t1 * t1;
+    if (nwg == 0) return 0;
     if (nwg > 0x7fffffffLL) return fail(c, STBEM_EINVAL, "problem too large for one launch");
     Geom g = geom(c);
+    const int* bl = c->d_blist[slot];
     if (store == ST_F64)
-        hipLaunchKernelGGL((k_assemble<OP, ST_F64>), dim3((unsigned)nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, c->nblk, t1, o64, hi, lo);
+        hipLaunchKernelGGL((k_assemble<OP, ST_F64>), dim3((unsigned)nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64, hi, lo);
     else if (store == ST_F32)
-        hipLaunchKernelGGL((k_assemble<OP, ST_F32>), dim3((unsigned)nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, c->nblk, t1, o64, hi, lo);
+        hipLaunchKernelGGL((k_assemble<OP, ST_F32>), dim3((unsigned)nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64, hi, lo);
     else
-        hipLaunchKernelGGL((k_assemble<OP, ST_HILO>), dim3((unsigned)nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, c->nblk, t1, o64, hi, lo);
+        hipLaunchKernelGGL((k_assemble<OP, ST_HILO>), dim3((unsigned)nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64, hi, lo);
     HIPCHK(c, hipGetLastError());
+    return 0;
+}
+
+template <int OP, int Q>
+void launch_vkfar(stbem_ctx* c, int slot, const int* bl, int cnt, double* o, hipStream_t s)
+{
+    int ti = (c->ng + kTile - 1) / kTile;
+    int tj = OP == OP_V ? ti : (c->ng + kTile - 2) / (kTile - 1);
+    long long nwg = (long long)cnt * ti * tj;
+    if (nwg > 0) hipLaunchKernelGGL((k_assemble_vkfar<OP, Q>), dim3((unsigned)nwg), dim3(kWG), 0, s, geom(c), c->d_tab, bl, ti, tj, o);
+}
+
+template <int OP>
+int launch_far(stbem_ctx* c, int slot, double* o, hipStream_t s)
+{
+    const int* bl = c->d_blist[slot] + c->nlist_gen[slot];
+    int off = 0;
+    launch_vkfar<OP, 3>(c, slot, bl + off, c->nlist_far[slot][3], o, s); off += c->nlist_far[slot][3];
+    launch_vkfar<OP, 4>(c, slot, bl + off, c->nlist_far[slot][4], o, s); off += c->nlist_far[slot][4];
+    launch_vkfar<OP, 5>(c, slot, bl + off, c->nlist_far[slot][5], o, s); off += c->nlist_far[slot][5];
+    launch_vkfar<OP, 6>(c, slot, bl + off, c->nlist_far[slot][6], o, s); off += c->nlist_far[slot][6];
+    launch_vkfar<OP, 7>(c, slot, bl + off, c->nlist_far[slot][7], o, s); off += c->nlist_far[slot][7];
+    launch_vkfar<OP, 8>(c, slot, bl + off, c->nlist_far[slot][8], o, s);
+    HIPCHK(c, hipGetLastError());
+    return 0;
+}
+
+// Block lists: the generic kernel takes touching blocks, closed-form
+// fallbacks and orders above 8; the far kernels take the rest.
+int build_block_lists(stbem_ctx* c)
+{
+    Geom g;
+    g.ng = c->ng; g.nt = c->nt; g.alpha = c->alpha; g.t = c->t.data();
+    g.vx = c->vx.data(); g.vy = c->vy.data(); g.ex = c->ex.data(); g.ey = c->ey.data(); g.len = c->len.data();
+    const int ops[5] = {OP_V, OP_K, OP_D, OP_DV, OP_DK}, slots[5] = {0, 1, 2, 4, 5};
+    TimeBlock tb;
+    for (int e = 0; e < 5; ++e) {
+        const int op = ops[e], slot = slots[e];
+        std::vector<int> gen, far[9];
+        for (int k = 0; k < c->nt; ++k)
+            for (int m = 0; m <= k; ++m) {
+                int b = (int)((long long)k * (k + 1) / 2 + m);
+                time_block(g, k, m, tb);
+                int q = q_block(op, c->lmax, block_min_lag(g.t, k, m), g.alpha);
+                if (!tb.ser || op == OP_DV || op == OP_DK) gen.push_back(b);
+                else if (q >= 3 && q <= 8) far[q].push_back(b);
+                else gen.push_back(b);
+            }
+        std::vector<int> all(gen);
+        for (int q = 0; q < 9; ++q) { all.insert(all.end(), far[q].begin(), far[q].end()); c->nlist_far[slot][q] = (int)far[q].size(); }
+        c->nlist_gen[slot] = (int)gen.size();
+        int rc = upload(c, &c->d_blist[slot], all);
+        if (rc) return rc;
+    }
     return 0;
 }
 
@@ -879,24 +974,28 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
         int rc = op == STBEM_V ? launch_assemble<OP_V>(c, ST_F64, o, nullptr, nullptr, s)
                                : launch_assemble<OP_K>(c, ST_F64, o, nullptr, nullptr, s);
         if (rc) return rc;
-        int ti = (c->ng + kTile - 1) / kTile;
-        int tj = op == STBEM_V ? ti : (c->ng + kTile - 2) / (kTile - 1);
-        long long nwg = c->nblk * (long long)ti * tj;
-        if (nwg > 0x7fffffffLL) return fail(c, STBEM_EINVAL, "problem too large for one launch");
-        if (op == STBEM_V)
-            hipLaunchKernelGGL(k_assemble_vkfar<OP_V>, dim3((unsigned)nwg), dim3(kWG), 0, s, geom(c), c->d_tab, c->lmax, ti, tj, o);
-        else
-            hipLaunchKernelGGL(k_assemble_vkfar<OP_K>, dim3((unsigned)nwg), dim3(kWG), 0, s, geom(c), c->d_tab, c->lmax, ti, tj, o);
-        HIPCHK(c, hipGetLastError());
-        return 0;
+        return op == STBEM_V ? launch_far<OP_V>(c, 0, o, s) : launch_far<OP_K>(c, 1, o, s);
     }
     case STBEM_D: {
         int rc = launch_assemble<OP_D>(c, ST_F64, o, nullptr, nullptr, s);
         if (rc) return rc;
         int t1 = (c->ng + kTile - 1) / kTile;
-        long long nwg = c->nblk * (long long)t1 * t1;
-        hipLaunchKernelGGL(k_assemble_dfar, dim3((unsigned)nwg), dim3(kWG), 0, s, geom(c), c->d_tab, c->lmax, t1, o,
-                           (float*)nullptr);
+        const int* bl = c->d_blist[2] + c->nlist_gen[2];
+        for (int q = 3; q <= 8; ++q) {
+            long long nwg = (long long)c->nlist_far[2][q] * t1 * t1;
+            if (nwg > 0) {
+                dim3 gr((unsigned)nwg), blk(kWG);
+                switch (q) {
+                case 3: hipLaunchKernelGGL(k_assemble_dfar<3>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, bl, t1, o, (float*)nullptr); break;
+                case 4: hipLaunchKernelGGL(k_assemble_dfar<4>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, bl, t1, o, (float*)nullptr); break;
+                case 5: hipLaunchKernelGGL(k_assemble_dfar<5>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, bl, t1, o, (float*)nullptr); break;
+                case 6: hipLaunchKernelGGL(k_assemble_dfar<6>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, bl, t1, o, (float*)nullptr); break;
+                case 7: hipLaunchKernelGGL(k_assemble_dfar<7>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, bl, t1, o, (float*)nullptr); break;
+                default: hipLaunchKernelGGL(k_assemble_dfar<8>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, bl, t1, o, (float*)nullptr); break;
+                }
+            }
+            bl += c->nlist_far[2][q];
+        }
         HIPCHK(c, hipGetLastError());
         return 0;
     }
@@ -904,15 +1003,37 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
     case STBEM_DK: return launch_assemble<OP_DK>(c, ST_F64, o, nullptr, nullptr, s);
     case STBEM_M0:
     case STBEM_DM0: {
-        int nchunk = (c->nv + kWG - 1) / kWG;
-        long long nwg = c->n * nchunk;
-        if (nwg > 0x7fffffffLL) return fail(c, STBEM_EINVAL, "M0 too large for one launch");
-        if (op == STBEM_M0)
-            hipLaunchKernelGGL((k_m0<false>), dim3((unsigned)nwg), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), nchunk, o);
-        else
-            hipLaunchKernelGGL((k_m0<true>), dim3((unsigned)nwg), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), nchunk, o);
-        HIPCHK(c, hipGetLastError());
-        return 0;
+        // rows in chunks whose moment scratch stays below 1 GiB
+        long long per_row = (long long)c->ntri * 3 * (long long)sizeof(double);
+        long long rows = (1LL << 30) / (per_row > 0 ? per_row : 1);
+        rows = rows < 1 ? 1 : (rows > c->n ? c->n : rows);
+        double* scratch = (double*)dev_alloc(c, (size_t)(rows * per_row));
+        if (!scratch) return fail(c, STBEM_ENOMEM, "M0 scratch of %lld bytes", rows * per_row);
+        int tchunk = (c->ntri + kWG - 1) / kWG, vchunk = (c->nv + kWG - 1) / kWG;
+        int rc = 0;
+        for (long long r0 = 0; r0 < c->n && !rc; r0 += rows) {
+            long long nr = c->n - r0 < rows ? c->n - r0 : rows;
+            // rows r0 .. r0+nr: those of the first time element (row < ng) take
+            // the kernel with the singular rules, the others the regular one
+            long long nf = r0 < c->ng ? std::min<long long>(nr, c->ng - r0) : 0, nl = nr - nf;
+            if (nf > 0) {
+                if (op == STBEM_M0)
+                    hipLaunchKernelGGL((k_m0_tri<false, true>), dim3((unsigned)(nf * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), r0, 0LL, tchunk, scratch);
+                else
+                    hipLaunchKernelGGL((k_m0_tri<true, true>), dim3((unsigned)(nf * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), r0, 0LL, tchunk, scratch);
+            }
+            if (nl > 0) {
+                if (op == STBEM_M0)
+                    hipLaunchKernelGGL((k_m0_tri<false, false>), dim3((unsigned)(nl * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), r0, nf, tchunk, scratch);
+                else
+                    hipLaunchKernelGGL((k_m0_tri<true, false>), dim3((unsigned)(nl * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), r0, nf, tchunk, scratch);
+            }
+            hipLaunchKernelGGL(k_m0_gather, dim3((unsigned)(nr * vchunk)), dim3(kWG), 0, s, mesh(c), (const int*)c->d_v2t_loc, r0, vchunk, (const double*)scratch, o);
+            if (hipGetLastError() != hipSuccess) rc = fail(c, STBEM_EHIP, "M0 kernels");
+        }
+        (void)hipStreamSynchronize(s);
+        dev_free(c, scratch);
+        return rc;
     }
     }
     return fail(c, STBEM_EINVAL, "unknown operator %u", op);
@@ -1052,8 +1173,13 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
         }
         for (int v = 0; v < c->nv; ++v) c->v2t_ptr[v + 1] += c->v2t_ptr[v];
         c->v2t.assign(3 * c->ntri, 0);
+        c->v2t_loc.assign(3 * c->ntri, 0);
         std::vector<int> fill(c->nv, 0);
-        for (int e = 0; e < 3 * c->ntri; ++e) { int v = c->tri[e]; c->v2t[c->v2t_ptr[v] + fill[v]++] = e / 3; }
+        for (int e = 0; e < 3 * c->ntri; ++e) {
+            int v = c->tri[e], p = c->v2t_ptr[v] + fill[v]++;
+            c->v2t[p] = e / 3;
+            c->v2t_loc[p] = e % 3;
+        }
     }
     // lumped dual mass Mt[(m,i)] = h_m (L_{i-1} + 2 L_i + L_{i+1}) / 4  (row sums, Sec. 4)
     std::vector<double> mt(c->n);
@@ -1066,7 +1192,8 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
     if ((rc = upload(c, &c->d_t, c->t)) || (rc = upload(c, &c->d_vx, c->vx)) || (rc = upload(c, &c->d_vy, c->vy)) ||
         (rc = upload(c, &c->d_ex, c->ex)) || (rc = upload(c, &c->d_ey, c->ey)) || (rc = upload(c, &c->d_len, c->len)) ||
         (rc = upload(c, &c->d_mt, mt)) || (rc = upload(c, &c->d_ox, c->ox)) || (rc = upload(c, &c->d_oy, c->oy)) ||
-        (rc = upload(c, &c->d_tri, c->tri)) || (rc = upload(c, &c->d_v2t_ptr, c->v2t_ptr)) || (rc = upload(c, &c->d_v2t, c->v2t))) {
+        (rc = upload(c, &c->d_tri, c->tri)) || (rc = upload(c, &c->d_v2t_ptr, c->v2t_ptr)) || (rc = upload(c, &c->d_v2t, c->v2t)) ||
+        (rc = upload(c, &c->d_v2t_loc, c->v2t_loc))) {
         stbem_destroy(c);
         return rc;
     }
@@ -1095,6 +1222,7 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
         return STBEM_EHIP;
     }
     c->ord = default_orders();
+    if ((rc = build_block_lists(c))) { stbem_destroy(c); return rc; }
     c->m0ord.qs_near = 12; c->m0ord.qt_near = 12; c->m0ord.near_ratio = 0.5;
     c->m0ord.omax = 0.0;
     for (int t = 0; t < c->ntri; ++t)
@@ -1114,9 +1242,11 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
         double amax = 0.25 * c->alpha * R2;
         std::vector<double> cf((size_t)c->nt * kPolyMax, 0.0), cfd((size_t)c->nt * kPolyMax, 0.0);
         std::vector<int> nn(c->nt, 0);
+        std::vector<double> am(c->nt, 0.0);
         for (int k = 1; k < c->nt; ++k) {
             long double t0 = c->t[k], t1 = c->t[k + 1], h = (long double)c->t[k + 1] - (long double)c->t[k];
-            if (amax / (double)t0 > 2.0) continue;
+            double amk = std::fmin(2.0 * c->t[k], amax);   // the series is used for a <= amk
+            am[k] = amk;
             double* co = &cf[(size_t)k * kPolyMax];
             double* cd = &cfd[(size_t)k * kPolyMax];
             co[0] = cd[0] = (double)logl(t1 / t0);
@@ -1132,13 +1262,14 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
                 long double sg = (n & 1) ? 1.0L : -1.0L;       // (-1)^{n+1}
                 co[n] = (double)(sg * en / n);
                 cd[n] = (double)(sg * en * (1.0L / n + 1.0L));
-                long double tail = powl(amax / t0, n) / fact;
+                long double tail = powl(amk / t0, n) / fact;
                 if (tail < 1e-18L * fabsl((long double)co[0]) && n > 2) { ++n; conv = true; break; }
             }
             nn[k] = conv ? n : 0;      // not converged: the E1 path is used
         }
         int rc2 = 0;
-        if ((rc2 = upload(c, &c->d_m0c, cf)) || (rc2 = upload(c, &c->d_m0cd, cfd)) || (rc2 = upload(c, &c->d_m0n, nn))) {
+        if ((rc2 = upload(c, &c->d_m0c, cf)) || (rc2 = upload(c, &c->d_m0cd, cfd)) || (rc2 = upload(c, &c->d_m0n, nn)) ||
+            (rc2 = upload(c, &c->d_m0amax, am))) {
             stbem_destroy(c);
             return rc2;
         }
@@ -1152,9 +1283,10 @@ int stbem_destroy(stbem_ctx* c)
     if (!c) return STBEM_OK;
     for (int s = 0; s < 7; ++s) dev_free(c, c->mat[s]);
     dev_free(c, c->v_hi); dev_free(c, c->v_lo); dev_free(c, c->d_32);
-    void* own[] = {c->d_t, c->d_vx, c->d_vy, c->d_ex, c->d_ey, c->d_len, c->d_ox, c->d_oy, c->d_mt, c->d_m0c, c->d_m0cd, c->d_m0n,
+    void* own[] = {c->d_t, c->d_vx, c->d_vy, c->d_ex, c->d_ey, c->d_len, c->d_ox, c->d_oy, c->d_mt, c->d_m0c, c->d_m0cd, c->d_m0n, c->d_m0amax, c->d_v2t_loc,
                    c->d_tri, c->d_v2t_ptr, c->d_v2t, c->d_tab, c->d_m0tab, c->part};
     for (void* p : own) if (p) (void)hipFree(p);
+    for (int q = 0; q < 7; ++q) if (c->d_blist[q]) (void)hipFree(c->d_blist[q]);
     delete c;
     return STBEM_OK;
 }
@@ -1188,6 +1320,25 @@ int stbem_assemble(stbem_ctx* c, unsigned mask, void* stream)
         if (mask & op) {
             int rc = assemble_one(c, op, S(stream));
             if (rc) return rc;
+        }
+    return STBEM_OK;
+}
+
+int stbem_release(stbem_ctx* c, unsigned mask)
+{
+    if (!c) return STBEM_EINVAL;
+    if (mask & ~127u) return fail(c, STBEM_EINVAL, "bad operator mask %u", mask);
+    const unsigned ops[7] = {STBEM_V, STBEM_K, STBEM_D, STBEM_M0, STBEM_DV, STBEM_DK, STBEM_DM0};
+    for (unsigned op : ops)
+        if (mask & op) {
+            int slot = op_slot(op);
+            dev_free(c, c->mat[slot]);
+            c->mat[slot] = nullptr;
+            c->mat_bytes[slot] = 0;
+            if (op == STBEM_V || op == STBEM_D) {       // FP32 copies derive from V and D
+                dev_free(c, c->v_hi); dev_free(c, c->v_lo); dev_free(c, c->d_32);
+                c->v_hi = c->v_lo = c->d_32 = nullptr;
+            }
         }
     return STBEM_OK;
 }

@@ -172,6 +172,40 @@ def manufactured(bnd_xy, t_nodes, vtx_xy, alpha, kvec):
     return g, u0, w_ref
 
 
+def sine_solution(bnd_xy, t_nodes, vtx_xy, alpha, theta=math.pi / 8):
+    """Data of u(x,t) = exp(-t/alpha) sin(x1 cos(theta) + x2 sin(theta)),
+    the exact solution of the paper's experiments (Sec. 4).  Same
+    discretisation as manufactured(): nodal in space x exact time mean."""
+    t = np.asarray(t_nodes, dtype=np.float64)
+    h = np.diff(t)
+    tavg = alpha * (np.exp(-t[:-1] / alpha) - np.exp(-t[1:] / alpha)) / h
+    kh = np.array([math.cos(theta), math.sin(theta)])
+    xb = np.asarray(bnd_xy, dtype=np.float64)
+    g = (tavg[:, None] * np.sin(xb @ kh)[None, :]).reshape(-1)
+    u0 = np.sin(np.asarray(vtx_xy, dtype=np.float64) @ kh)
+    d = np.roll(xb, -1, axis=0) - xb
+    L = np.hypot(d[:, 0], d[:, 1])
+    e = d / L[:, None]
+    nrm = np.stack([e[:, 1], -e[:, 0]], axis=1)
+    # mean over gamma_i of cos(kh.x) (kh.n_i): kh.x is linear along the segment
+    a, b = xb @ kh, np.roll(xb, -1, axis=0) @ kh
+    with np.errstate(invalid="ignore", divide="ignore"):
+        cavg = np.where(np.abs(b - a) > 1e-14, (np.sin(b) - np.sin(a)) / np.where(b == a, 1, b - a), np.cos(a))
+    w_ref = (tavg[:, None] * ((nrm @ kh) * cavg)[None, :]).reshape(-1)
+    return g, u0, w_ref
+
+
+def paper_level(L: int) -> "Workload":
+    """The experiment of Sec. 4: Q = (0,1)^3, alpha = 10, uniform meshes with
+    h_x = h_t = 2^-L (N_Gamma = 4 * 2^L segments, N_I = 2^L steps, N = 4 * 4^L,
+    as in Table 1); Omega_h is the matching 2^L grid."""
+    n = 2 ** L
+    bnd, t, (vx, tr), alpha = square_polygon(n), uniform_times(n), square_grid(n), 10.0
+    g, u0, w_ref = sine_solution(bnd, t, vx, alpha)
+    return Workload(name=f"paper_L{L}", alpha=alpha, t_nodes=t, bnd_xy=bnd, vtx_xy=vx, tri=tr,
+                    kvec=np.array([math.cos(math.pi / 8), math.sin(math.pi / 8)]), g=g, u0=u0, w_ref=w_ref)
+
+
 # ----------------------------------------------------------------- configs
 CONFIGS = ("tiny", "medium", "precision", "lshape", "diff")
 
