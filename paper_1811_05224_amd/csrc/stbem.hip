@@ -736,12 +736,13 @@ __global__ __launch_bounds__(kWG) void k_basis_comb(const double* __restrict__ Q
 __global__ __launch_bounds__(kWG) void k_split(long long n, const double* __restrict__ a, float* __restrict__ hi,
                                                float* __restrict__ lo)
 {
-    long long e = (long long)blockIdx.x * kWG + threadIdx.x;
-    if (e >= n) return;
-    double v = a[e];
-    float h = (float)v;
-    hi[e] = h;
-    if (lo) lo[e] = (float)(v - (double)h);
+    const long long stride = (long long)gridDim.x * kWG;
+    for (long long e = (long long)blockIdx.x * kWG + threadIdx.x; e < n; e += stride) {
+        double v = a[e];
+        float h = (float)v;
+        hi[e] = h;
+        if (lo) lo[e] = (float)(v - (double)h);
+    }
 }
 
 }  // namespace
@@ -863,7 +864,7 @@ Mesh2 mesh(const stbem_ctx* c)
     return m;
 }
 
-inline unsigned grid1(long long n) { return (unsigned)((n + kWG - 1) / kWG); }
+inline long long grid1(long long n) { return (n + kWG - 1) / kWG; }
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -881,22 +882,35 @@ int ensure_part(stbem_ctx* c)
     return 0;
 }
 
+// A dispatch's grid size is counted in work-items in 32 bits: launches over
+// block lists are split so that workgroups x 256 stays below 2^32.
+constexpr long long kMaxWG = (0xffffffffLL / kWG) - 1;
+
+inline int blocks_per_launch(long long tiles)
+{
+    long long b = kMaxWG / (tiles > 0 ? tiles : 1);
+    return (int)(b > 0x7fffffff ? 0x7fffffff : (b < 1 ? 1 : b));
+}
+
 template <int OP>
 int launch_assemble(stbem_ctx* c, int store, double* o64, float* hi, float* lo, hipStream_t s)
 {
     const int slot = OP == OP_V ? 0 : OP == OP_K ? 1 : OP == OP_D ? 2 : OP == OP_DV ? 4 : 5;
     int t1 = (c->ng + kTile - 1) / kTile;
-    long long nwg = c->nlist_gen[slot] * (long long)t1 * t1;
-    if (nwg == 0) return 0;
-    if (nwg > 0x7fffffffLL) return fail(c, STBEM_EINVAL, "problem too large for one launch");
+    const long long tiles = (long long)t1 * t1;
     Geom g = geom(c);
-    const int* bl = c->d_blist[slot];
-    if (store == ST_F64)
-        hipLaunchKernelGGL((k_assemble<OP, ST_F64>), dim3((unsigned)nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64, hi, lo);
-    else if (store == ST_F32)
-        hipLaunchKernelGGL((k_assemble<OP, ST_F32>), dim3((unsigned)nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64, hi, lo);
-    else
-        hipLaunchKernelGGL((k_assemble<OP, ST_HILO>), dim3((unsigned)nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64, hi, lo);
+    const int step = blocks_per_launch(tiles);
+    for (int off = 0; off < c->nlist_gen[slot]; off += step) {
+        const int cnt = std::min(step, c->nlist_gen[slot] - off);
+        const int* bl = c->d_blist[slot] + off;
+        dim3 gr((unsigned)(cnt * tiles)), blk(kWG);
+        if (store == ST_F64)
+            hipLaunchKernelGGL((k_assemble<OP, ST_F64>), gr, blk, 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64, hi, lo);
+        else if (store == ST_F32)
+            hipLaunchKernelGGL((k_assemble<OP, ST_F32>), gr, blk, 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64, hi, lo);
+        else
+            hipLaunchKernelGGL((k_assemble<OP, ST_HILO>), gr, blk, 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64, hi, lo);
+    }
     HIPCHK(c, hipGetLastError());
     return 0;
 }
@@ -906,8 +920,13 @@ void launch_vkfar(stbem_ctx* c, int slot, const int* bl, int cnt, double* o, hip
 {
     int ti = (c->ng + kTile - 1) / kTile;
     int tj = OP == OP_V ? ti : (c->ng + kTile - 2) / (kTile - 1);
-    long long nwg = (long long)cnt * ti * tj;
-    if (nwg > 0) hipLaunchKernelGGL((k_assemble_vkfar<OP, Q>), dim3((unsigned)nwg), dim3(kWG), 0, s, geom(c), c->d_tab, bl, ti, tj, o);
+    const long long tiles = (long long)ti * tj;
+    const int step = blocks_per_launch(tiles);
+    for (int off = 0; off < cnt; off += step) {
+        const int n = std::min(step, cnt - off);
+        hipLaunchKernelGGL((k_assemble_vkfar<OP, Q>), dim3((unsigned)(n * tiles)), dim3(kWG), 0, s, geom(c), c->d_tab,
+                           bl + off, ti, tj, o);
+    }
 }
 
 template <int OP>
@@ -981,17 +1000,20 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
         if (rc) return rc;
         int t1 = (c->ng + kTile - 1) / kTile;
         const int* bl = c->d_blist[2] + c->nlist_gen[2];
+        const long long tiles = (long long)t1 * t1;
+        const int step = blocks_per_launch(tiles);
         for (int q = 3; q <= 8; ++q) {
-            long long nwg = (long long)c->nlist_far[2][q] * t1 * t1;
-            if (nwg > 0) {
-                dim3 gr((unsigned)nwg), blk(kWG);
+            for (int off = 0; off < c->nlist_far[2][q]; off += step) {
+                const int n = std::min(step, c->nlist_far[2][q] - off);
+                dim3 gr((unsigned)(n * tiles)), blk(kWG);
+                const int* b2 = bl + off;
                 switch (q) {
-                case 3: hipLaunchKernelGGL(k_assemble_dfar<3>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, bl, t1, o, (float*)nullptr); break;
-                case 4: hipLaunchKernelGGL(k_assemble_dfar<4>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, bl, t1, o, (float*)nullptr); break;
-                case 5: hipLaunchKernelGGL(k_assemble_dfar<5>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, bl, t1, o, (float*)nullptr); break;
-                case 6: hipLaunchKernelGGL(k_assemble_dfar<6>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, bl, t1, o, (float*)nullptr); break;
-                case 7: hipLaunchKernelGGL(k_assemble_dfar<7>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, bl, t1, o, (float*)nullptr); break;
-                default: hipLaunchKernelGGL(k_assemble_dfar<8>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, bl, t1, o, (float*)nullptr); break;
+                case 3: hipLaunchKernelGGL(k_assemble_dfar<3>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, b2, t1, o, (float*)nullptr); break;
+                case 4: hipLaunchKernelGGL(k_assemble_dfar<4>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, b2, t1, o, (float*)nullptr); break;
+                case 5: hipLaunchKernelGGL(k_assemble_dfar<5>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, b2, t1, o, (float*)nullptr); break;
+                case 6: hipLaunchKernelGGL(k_assemble_dfar<6>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, b2, t1, o, (float*)nullptr); break;
+                case 7: hipLaunchKernelGGL(k_assemble_dfar<7>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, b2, t1, o, (float*)nullptr); break;
+                default: hipLaunchKernelGGL(k_assemble_dfar<8>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, b2, t1, o, (float*)nullptr); break;
                 }
             }
             bl += c->nlist_far[2][q];
@@ -1577,8 +1599,9 @@ int stbem_prepare_ir(stbem_ctx* c, void* stream)
     if (!c->v_lo) c->v_lo = (float*)dev_alloc(c, fb);
     if (!c->d_32) c->d_32 = (float*)dev_alloc(c, fb);
     if (!c->v_hi || !c->v_lo || !c->d_32) return fail(c, STBEM_ENOMEM, "FP32 storage (3 x %zu bytes)", fb);
-    hipLaunchKernelGGL(k_split, dim3(grid1(c->packed)), dim3(kWG), 0, s, c->packed, (const double*)c->mat[0], c->v_hi, c->v_lo);
-    hipLaunchKernelGGL(k_split, dim3(grid1(c->packed)), dim3(kWG), 0, s, c->packed, (const double*)c->mat[2], c->d_32, (float*)nullptr);
+    const unsigned gs = (unsigned)std::min<long long>(grid1(c->packed), 1LL << 20);   // grid-stride
+    hipLaunchKernelGGL(k_split, dim3(gs), dim3(kWG), 0, s, c->packed, (const double*)c->mat[0], c->v_hi, c->v_lo);
+    hipLaunchKernelGGL(k_split, dim3(gs), dim3(kWG), 0, s, c->packed, (const double*)c->mat[2], c->d_32, (float*)nullptr);
     HIPCHK(c, hipGetLastError());
     return STBEM_OK;
 }
@@ -1680,8 +1703,9 @@ int stbem_entries(stbem_ctx* c, unsigned op, long long n, const int* idx, double
 {
     if (!c || (n > 0 && (!idx || !out))) return STBEM_EINVAL;
     if (n == 0) return STBEM_OK;
+    if (n > kMaxWG * kWG) return fail(c, STBEM_EINVAL, "at most %lld entries per call", kMaxWG * kWG);
     hipStream_t s = S(stream);
-    unsigned nwg = grid1(n);
+    unsigned nwg = (unsigned)grid1(n);
     Geom g = geom(c);
     switch (op) {
     case STBEM_V: hipLaunchKernelGGL(k_entries<OP_V>, dim3(nwg), dim3(kWG), 0, s, g, c->d_tab, c->ord, c->lmax, n, idx, out); break;
