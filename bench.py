@@ -169,10 +169,10 @@ def cpu_baseline(wl, nsamp):
     o = Oracle.from_workload(wl)
     rng = np.random.default_rng(0)
     ng, nt = wl.n_gamma, wl.n_t
-    n = nsamp or 3000
+    n = nsamp or 40000
     res = {}
     total_e, total_s = 0, 0.0
-    for op, cnt in (("V", n), ("K", n), ("D", max(n // 10, 50))):
+    for op, cnt in (("V", n), ("K", n), ("D", max(n // 8, 50))):
         k = rng.integers(0, nt, cnt)
         m = np.minimum(k, rng.integers(0, nt, cnt))
         idx = np.stack([k, m, rng.integers(0, ng, cnt), rng.integers(0, ng, cnt)], 1)
@@ -185,7 +185,7 @@ def cpu_baseline(wl, nsamp):
     # V, K, D weighted equally: entries of the three matrices per second
     rate = 3.0 / sum(1.0 / res[op] for op in ("V", "K", "D"))
     return {"value": rate, "unit": "entries/s", "cores": o.nthreads, "kind": "oracle",
-            "sample": f"{n} random V_h, {n} K_h, {max(n // 10, 50)} D_h entries of the same workload "
+            "sample": f"{n} random V_h, {n} K_h, {max(n // 8, 50)} D_h entries of the same workload "
                       f"({total_s:.1f} s); per-operator entries/s " + ", ".join(f"{k}={v:.0f}" for k, v in res.items())}
 
 
