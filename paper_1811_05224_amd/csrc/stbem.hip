@@ -308,6 +308,114 @@ __global__ __launch_bounds__(kWG) void k_assemble_dfar(Geom g, const Tables* __r
     else out32[off] = (float)acc;
 }
 
+// D_h on touching time elements (d <= 1, closed form in time): one workgroup
+// = one 16 x 16 tile.  Each of the 34 x 34 half-segment piece pairs of the
+// tile enters up to four entries, so its moments are computed once into LDS.
+// An entry takes the raw-kernel form when all 16 pairs of its supports are
+// well separated, else the by-parts form (the boundary terms of the
+// integration by parts cancel only within one entry, so the choice is per
+// entry, never per pair).  The raw entries of the tile are done first, then,
+// if the tile has any, the by-parts entries, reusing the moment array.
+__global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __restrict__ Tg, Orders O,
+                                                        const int* __restrict__ blist, int tiles_1d,
+                                                        double* __restrict__ out64)
+{
+    __shared__ Tables T;
+    __shared__ TimeBlock tb;
+    __shared__ Piece pc[2][kDP];
+    __shared__ double mom[kDP][kDP][5];
+    __shared__ unsigned char form[kTile][kTile];   // 0 by-parts, 1 raw, 2 outside the matrix
+    const int tid = threadIdx.x;
+    const long long tiles = (long long)tiles_1d * tiles_1d;
+    const long long b = blist[blockIdx.x / tiles];
+    const int tile = (int)(blockIdx.x % tiles);
+    int k, m;
+    block_of(b, k, m);
+    if (tid == 0) time_block(g, k, m, tb);
+    {
+        const double* src = reinterpret_cast<const double*>(Tg);
+        double* dst = reinterpret_cast<double*>(&T);
+        for (int e = tid; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
+    }
+    const int I0 = (tile / tiles_1d) * kTile, J0 = (tile % tiles_1d) * kTile;
+    const int np = 2 * g.ng;
+    if (tid < 2 * kDP) {
+        const int side = tid / kDP, u = tid % kDP;
+        const int base = side ? J0 : I0;
+        pc[side][u] = half_piece(g, ((2 * base - 1 + u) % np + np) % np);
+    }
+    __syncthreads();
+    const int il = tid / kTile, jl = tid % kTile;
+    const int i = I0 + il, j = J0 + jl;
+    const bool inside = i < g.ng && j < g.ng;
+    const int ui = 2 * il, vj = 2 * jl;
+    int my = 2;
+    if (inside) my = d_support_eta(&pc[0][ui], &pc[1][vj]) > O.eta_raw ? 1 : 0;
+    form[il][jl] = (unsigned char)my;
+    const int any_bp = __syncthreads_or(my == 0);
+
+    // which form does a pair need: entries (u/2 - 1 or u/2, v/2 - 1 or v/2)
+    auto needs = [&](int u, int v, int f) {
+        const int i1 = u / 2, j1 = v / 2;
+        bool r = false;
+        for (int a = i1 - 1; a <= i1; ++a)
+            for (int c = j1 - 1; c <= j1; ++c)
+                if (a >= 0 && a < kTile && c >= 0 && c < kTile && form[a][c] == f) r = true;
+        return r;
+    };
+    auto hat = [&](const DualSupport& sp, int u, double len, double& a0, double& a1) {
+        a0 = sp.v0[u]; a1 = sp.v0[u] + sp.slope[u] * len;
+    };
+    DualSupport si, sj;
+    if (inside) { si = dual_support(g, i); sj = dual_support(g, j); }
+    const long long off = b * (long long)g.ng * g.ng + (long long)i * g.ng + j;
+
+    // pass 1: raw-form entries
+    for (int e = tid; e < kDP * kDP; e += kWG) {
+        const int u = e / kDP, v = e % kDP;
+        if (needs(u, v, 1)) d_pair_raw(T, O, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v]);
+    }
+    __syncthreads();
+    if (my == 1) {
+        double acc = 0.0;
+        for (int u = 0; u < 4; ++u) {
+            double a0, a1;
+            hat(si, u, pc[0][ui + u].len, a0, a1);
+            for (int v = 0; v < 4; ++v) {
+                double b0, b1;
+                hat(sj, v, pc[1][vj + v].len, b0, b1);
+                const double* M = mom[ui + u][vj + v];
+                acc += a0 * (b0 * M[0] + b1 * M[1]) + a1 * (b0 * M[2] + b1 * M[3]);
+            }
+        }
+        out64[off] = acc;
+    }
+    if (!any_bp) return;
+    __syncthreads();
+
+    // pass 2: by-parts entries (curl part psi'_P psi'_Q m0 + the normal part)
+    for (int e = tid; e < kDP * kDP; e += kWG) {
+        const int u = e / kDP, v = e % kDP;
+        if (needs(u, v, 0)) d_pair_bp(T, O, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v]);
+    }
+    __syncthreads();
+    if (my == 0) {
+        double acc = 0.0;
+        for (int u = 0; u < 4; ++u) {
+            double a0, a1;
+            hat(si, u, pc[0][ui + u].len, a0, a1);
+            for (int v = 0; v < 4; ++v) {
+                double b0, b1;
+                hat(sj, v, pc[1][vj + v].len, b0, b1);
+                const double* M = mom[ui + u][vj + v];
+                acc += si.slope[u] * sj.slope[v] * M[0]
+                     + a0 * (b0 * M[1] + b1 * M[2]) + a1 * (b0 * M[3] + b1 * M[4]);
+            }
+        }
+        out64[off] = acc;
+    }
+}
+
 template <int OP>
 __global__ __launch_bounds__(kWG) void k_entries(Geom g, const Tables* __restrict__ Tg, Orders O, double lmax,
                                                  long long n, const int* __restrict__ idx, double* __restrict__ out)
@@ -770,6 +878,7 @@ struct stbem_ctx {
     float *v_hi = nullptr, *v_lo = nullptr, *d_32 = nullptr;
     // block lists per operator slot: [generic | far Q=3..8 (V, K) or tile kernel (D)]
     int* d_blist[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int nlist_touch[7] = {0, 0, 0, 0, 0, 0, 0};   // D_h: touching blocks for the tile kernel (list head)
     int nlist_gen[7] = {0, 0, 0, 0, 0, 0, 0};
     int nlist_far[7][9] = {};
     // work
@@ -902,7 +1011,7 @@ int launch_assemble(stbem_ctx* c, int store, double* o64, float* hi, float* lo, 
     const int step = blocks_per_launch(tiles);
     for (int off = 0; off < c->nlist_gen[slot]; off += step) {
         const int cnt = std::min(step, c->nlist_gen[slot] - off);
-        const int* bl = c->d_blist[slot] + off;
+        const int* bl = c->d_blist[slot] + c->nlist_touch[slot] + off;
         dim3 gr((unsigned)(cnt * tiles)), blk(kWG);
         if (store == ST_F64)
             hipLaunchKernelGGL((k_assemble<OP, ST_F64>), gr, blk, 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64, hi, lo);
@@ -932,7 +1041,7 @@ void launch_vkfar(stbem_ctx* c, int slot, const int* bl, int cnt, double* o, hip
 template <int OP>
 int launch_far(stbem_ctx* c, int slot, double* o, hipStream_t s)
 {
-    const int* bl = c->d_blist[slot] + c->nlist_gen[slot];
+    const int* bl = c->d_blist[slot] + c->nlist_touch[slot] + c->nlist_gen[slot];
     int off = 0;
     launch_vkfar<OP, 3>(c, slot, bl + off, c->nlist_far[slot][3], o, s); off += c->nlist_far[slot][3];
     launch_vkfar<OP, 4>(c, slot, bl + off, c->nlist_far[slot][4], o, s); off += c->nlist_far[slot][4];
@@ -955,18 +1064,21 @@ int build_block_lists(stbem_ctx* c)
     TimeBlock tb;
     for (int e = 0; e < 5; ++e) {
         const int op = ops[e], slot = slots[e];
-        std::vector<int> gen, far[9];
+        std::vector<int> touch, gen, far[9];
         for (int k = 0; k < c->nt; ++k)
             for (int m = 0; m <= k; ++m) {
                 int b = (int)((long long)k * (k + 1) / 2 + m);
                 time_block(g, k, m, tb);
                 int q = q_block(op, c->lmax, block_min_lag(g.t, k, m), g.alpha);
-                if (!tb.ser || op == OP_DV || op == OP_DK) gen.push_back(b);
+                if (op == OP_D && tb.d <= 1) touch.push_back(b);
+                else if (!tb.ser || op == OP_DV || op == OP_DK) gen.push_back(b);
                 else if (q >= 3 && q <= 8) far[q].push_back(b);
                 else gen.push_back(b);
             }
-        std::vector<int> all(gen);
+        std::vector<int> all(touch);
+        all.insert(all.end(), gen.begin(), gen.end());
         for (int q = 0; q < 9; ++q) { all.insert(all.end(), far[q].begin(), far[q].end()); c->nlist_far[slot][q] = (int)far[q].size(); }
+        c->nlist_touch[slot] = (int)touch.size();
         c->nlist_gen[slot] = (int)gen.size();
         int rc = upload(c, &c->d_blist[slot], all);
         if (rc) return rc;
@@ -996,12 +1108,17 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
         return op == STBEM_V ? launch_far<OP_V>(c, 0, o, s) : launch_far<OP_K>(c, 1, o, s);
     }
     case STBEM_D: {
-        int rc = launch_assemble<OP_D>(c, ST_F64, o, nullptr, nullptr, s);
-        if (rc) return rc;
         int t1 = (c->ng + kTile - 1) / kTile;
-        const int* bl = c->d_blist[2] + c->nlist_gen[2];
         const long long tiles = (long long)t1 * t1;
         const int step = blocks_per_launch(tiles);
+        for (int off = 0; off < c->nlist_touch[2]; off += step) {
+            const int n = std::min(step, c->nlist_touch[2] - off);
+            hipLaunchKernelGGL(k_assemble_dnear, dim3((unsigned)(n * tiles)), dim3(kWG), 0, s, geom(c), c->d_tab, c->ord,
+                               (const int*)(c->d_blist[2] + off), t1, o);
+        }
+        int rc = launch_assemble<OP_D>(c, ST_F64, o, nullptr, nullptr, s);
+        if (rc) return rc;
+        const int* bl = c->d_blist[2] + c->nlist_touch[2] + c->nlist_gen[2];
         for (int q = 3; q <= 8; ++q) {
             for (int off = 0; off < c->nlist_far[2][q]; off += step) {
                 const int n = std::min(step, c->nlist_far[2][q] - off);

@@ -65,12 +65,16 @@ struct Geom {
 };
 
 // Quadrature orders chosen by the host per problem.
+constexpr int kNearClasses = 6;
+
 struct Orders {
     int q_sing;          // Gauss-Legendre order of the singular rules (smooth parts)
     int q_log;           // order of the -ln u rule
-    int q_near[4];       // regular rule on touching time elements by distance class
-    double eta_cut[3];   // distance/length thresholds between the classes
+    int q_near[kNearClasses];         // regular rule on touching time elements by distance class
+    double eta_cut[kNearClasses - 1]; // distance/length thresholds between the classes
     double eta_raw;      // D_h: pieces farther apart use the raw-kernel form
+    double q_tol;        // touching elements: bound on the Gauss remainder of the e^{-z} factor
+    double z_floor;      // entries below e^{-z_floor} of the block maximum need absolute accuracy only
 };
 
 // ------------------------------------------------------------------ E1
@@ -131,6 +135,7 @@ struct TimeBlock {
     double lnd[4];
     int ndel;
     double dc, inv_dc;    // centre distance (separated)
+    double w2;            // alpha / (4 smallest lag): z = w2 r^2 bounds a / delta
     double c[kMaxTerms];  // mu_2n / dc^2n
     double rinv[2 * kMaxTerms + 2];   // 1/n for the Laguerre recurrence
 };
@@ -142,6 +147,10 @@ SDEV void time_block(const Geom& g, int k, int m, TimeBlock& tb)
     tb.d = (k - m >= 2) ? 2 : (k - m);
     tb.nterm = 0;
     tb.ser = 0;
+    {
+        double lag = (k == m) ? hk : (k == m + 1 ? (hk < hm ? hk : hm) : g.t[k] - g.t[m + 1]);
+        tb.w2 = 0.25 * g.alpha / lag;
+    }
     if (tb.d == 0) {
         tb.ndel = 1; tb.del[0] = hk; tb.sgn[0] = 1.0;
     } else if (tb.d == 1) {
@@ -423,21 +432,46 @@ SDEV void rule_vertex(const Tables& T, const Piece& P, const Piece& Q, int rel, 
     }
 }
 
+// Order of the regular rule on a pair of pieces of touching time elements.
+// Two things limit it: the distance to the r = 0 singularity (classes of
+// eta = distance / length), and the factor e^{-z}, z = w2 r^2, which changes
+// by dz = w2 (r_hi^2 - r_lo^2) across the pair.  For the second, the q-point
+// Gauss remainder of e^{-dz s} on [0, 1] relative to its integral is at most
+// c_q dz^{2q} e^{dz}, c_q = (q!)^4 / ((2q+1) ((2q)!)^3); pairs whose factor
+// is below e^{-z_floor} (of the block maximum, attained at r = 0) need that
+// bound only relative to e^{-z_floor}.
+SDEV int q_touch(const Orders& O, const TimeBlock& tb, const Piece& P, const Piece& Q, double eta, int qinc)
+{
+    int qe = O.q_near[kNearClasses - 1];
+    for (int c = kNearClasses - 2; c >= 0; --c)
+        if (eta < O.eta_cut[c]) qe = O.q_near[c];
+    const double rlo = eta * (P.len > Q.len ? P.len : Q.len), rhi = rlo + P.len + Q.len;
+    const double zlo = tb.w2 * rlo * rlo, dz = tb.w2 * (rhi * rhi - rlo * rlo);
+    const double lim = O.q_tol * exp(-dz) * (zlo > O.z_floor ? exp(zlo - O.z_floor) : 1.0);
+    const double dz2 = dz * dz;
+    double c = 1.0 / 24.0, pw = dz2;   // c_1, dz^2
+    int q = 1;
+    while (q < kMaxGL && c * pw > lim) {
+        const double a = 2.0 * q + 1.0;
+        c *= (double)(q + 1) * (q + 1) * (q + 1) * (q + 1) * a / ((a + 2.0) * (a * (a + 1.0)) * (a * (a + 1.0)) * (a * (a + 1.0)));
+        pw *= dz2;
+        ++q;
+    }
+    q += qinc;
+    q = q < 3 ? 3 : q;
+    q = q > qe ? q : qe;
+    return q > kMaxGL ? kMaxGL : q;
+}
+
 template <class KF>
-SDEV void pair_integral(const Tables& T, const Orders& O, const TimeBlock& tb, int q_far,
+SDEV void pair_integral(const Tables& T, const Orders& O, const TimeBlock& tb, int q_far, int qinc,
                         const Piece& P, const Piece& Q, KF& kf)
 {
     if (tb.d >= 2) { rule_regular(T, P, Q, q_far, kf); return; }
     int rel = relation(P, Q);
     if (rel == 1) { rule_coincident(T, P, O.q_sing, O.q_log, kf); return; }
     if (rel >= 2) { rule_vertex(T, P, Q, rel, O.q_sing, O.q_log, kf); return; }
-    double eta = sep_ratio(P, Q);
-    int q = O.q_near[3];
-    if (eta < O.eta_cut[0]) q = O.q_near[0];
-    else if (eta < O.eta_cut[1]) q = O.q_near[1];
-    else if (eta < O.eta_cut[2]) q = O.q_near[2];
-    q = q > q_far ? q : q_far;
-    rule_regular(T, P, Q, q, kf);
+    rule_regular(T, P, Q, q_touch(O, tb, P, Q, sep_ratio(P, Q), qinc), kf);
 }
 
 // ---------------------------------------------------------- kernel functors
@@ -550,6 +584,87 @@ struct KernD {
     }
 };
 
+// Moments of one pair of half-segment pieces on touching time elements, for
+// D_h entries assembled from shared piece-pair moments.  x^, y^ in [0, 1] are
+// the arclength coordinates on P and Q divided by the lengths; a dual hat is
+// a0 (1 - x^) + a1 x^ on each piece of its support.
+// By-parts form: m[0] = int int Delta F_V; m[1..4] = alpha n_P.n_Q times the
+// moments of Delta F_D against (1-x^)(1-y^), (1-x^) y^, x^ (1-y^), x^ y^.
+struct DMomBP {
+    const TimeBlock& tb; double alpha, iLP, iLQ; double m[5];
+    SDEV DMomBP(const TimeBlock& t, double al, const Piece& P, const Piece& Q)
+        : tb(t), alpha(al), iLP(1.0 / P.len), iLQ(1.0 / Q.len), m{0.0, 0.0, 0.0, 0.0, 0.0} {}
+    SDEV void add(double v, double d, double sP, double sQ)
+    {
+        const double x = sP * iLP, y = sQ * iLQ;
+        m[0] += v;
+        m[1] += d * (1.0 - x) * (1.0 - y); m[2] += d * (1.0 - x) * y;
+        m[3] += d * x * (1.0 - y);         m[4] += d * x * y;
+    }
+    SDEV void val(double w, double sP, double sQ, double, double, double r2)
+    {
+        TouchVals s = touch<true, false, true, false, false>(tb, 0.25 * alpha * r2, alpha);
+        add(w * s.v, w * s.dd, sP, sQ);
+    }
+    SDEV void split(double wa, double wb, double sP, double sQ, double, double, double r2, double lnr)
+    {
+        SplitVals s = touch_split<true, false, true, false, false>(tb, 0.25 * alpha * r2, lnr, alpha);
+        add(wa * s.v.a + wb * s.v.b, wa * s.dd.a + wb * s.dd.b, sP, sQ);
+    }
+};
+
+// Raw-kernel form (pieces apart): moments of alpha n_P.n_Q Delta F_D minus the
+// tangential Hessian term t_P^T Hess t_Q of Delta F_V, against the same four
+// bilinear shapes.  Only the regular rule is used with it.
+struct DMomRaw {
+    const TimeBlock& tb; double alpha, cn, tt, txx, txy, tyx, tyy, iLP, iLQ; double m[4];
+    SDEV DMomRaw(const TimeBlock& t, double al, const Piece& P, const Piece& Q)
+        : tb(t), alpha(al), cn(al * (P.nx * Q.nx + P.ny * Q.ny)), tt(P.ex * Q.ex + P.ey * Q.ey),
+          txx(P.ex), txy(P.ey), tyx(Q.ex), tyy(Q.ey), iLP(1.0 / P.len), iLQ(1.0 / Q.len), m{0.0, 0.0, 0.0, 0.0} {}
+    SDEV void val(double w, double sP, double sQ, double dx, double dy, double r2)
+    {
+        TouchH s = touch_h(tb, 0.25 * alpha * r2);
+        const double zt = (dx * txx + dy * txy) * (dx * tyx + dy * tyy);
+        const double h = 0.25 * alpha * alpha * s.vaa * zt + 0.5 * alpha * s.va * tt;
+        const double k = w * (cn * s.dd - h);
+        const double x = sP * iLP, y = sQ * iLQ;
+        m[0] += k * (1.0 - x) * (1.0 - y); m[1] += k * (1.0 - x) * y;
+        m[2] += k * x * (1.0 - y);         m[3] += k * x * y;
+    }
+};
+
+// Moment sets of one piece pair (touching elements), cn folded in.
+SDEV void d_pair_bp(const Tables& T, const Orders& O, const TimeBlock& tb, double alpha,
+                    const Piece& P, const Piece& Q, double* m)
+{
+    DMomBP f(tb, alpha, P, Q);
+    pair_integral(T, O, tb, 0, 0, P, Q, f);
+    const double cn = alpha * (P.nx * Q.nx + P.ny * Q.ny);
+    m[0] = f.m[0];
+    for (int c = 1; c < 5; ++c) m[c] = cn * f.m[c];
+}
+
+SDEV void d_pair_raw(const Tables& T, const Orders& O, const TimeBlock& tb, double alpha,
+                     const Piece& P, const Piece& Q, double* m)
+{
+    DMomRaw f(tb, alpha, P, Q);
+    rule_regular(T, P, Q, q_touch(O, tb, P, Q, sep_ratio(P, Q), 0), f);
+    for (int c = 0; c < 4; ++c) m[c] = f.m[c];
+}
+
+// separation of the supports of two dual hats (pieces P[0..3], Q[0..3]):
+// the smallest eta over the 16 pairs, 0 for pairs that touch
+SDEV double d_support_eta(const Piece* P, const Piece* Q)
+{
+    double eta = 1e300;
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) {
+            double e = relation(P[u], Q[v]) ? 0.0 : sep_ratio(P[u], Q[v]);
+            eta = e < eta ? e : eta;
+        }
+    return eta;
+}
+
 // ------------------------------------------------------- quadrature orders
 // Order of the tensor rule for a smooth kernel that varies on the length
 // scale sqrt(4 delta_min / alpha) (delta_min: smallest time lag of the
@@ -570,9 +685,11 @@ SDEV int q_time(double lmax, double delta_min, double alpha)
 // Order of the regular rule for operator op on block (k, m): the alpha-
 // derivative kernels vanish like r^2 at coincidence and K carries the factor
 // (x-y).n/r^2, both need more points than V and D for the same accuracy.
+SDEV int q_inc(int op) { return op == OP_K ? 1 : (op == OP_DV || op == OP_DK) ? 2 : 0; }
+
 SDEV int q_block(int op, double lmax, double delta_min, double alpha)
 {
-    int q = q_time(lmax, delta_min, alpha) + (op == OP_K ? 1 : (op == OP_DV || op == OP_DK) ? 2 : 0);
+    int q = q_time(lmax, delta_min, alpha) + q_inc(op);
     return q > kMaxGL ? kMaxGL : q;
 }
 
@@ -609,15 +726,15 @@ SDEV double entry(const Tables& T, const Orders& O, const Geom& g, const TimeBlo
     if (OP == OP_V || OP == OP_DV) {
         Piece P = seg_piece(g, i), Q = seg_piece(g, j);
         KernV<OP == OP_DV> kf(tb, g.alpha);
-        pair_integral(T, O, tb, q_far, P, Q, kf);
+        pair_integral(T, O, tb, q_far, q_inc(OP), P, Q, kf);
         return kf.acc;
     } else if (OP == OP_K || OP == OP_DK) {
         // hat_j: rising on segment j-1 (shape sQ/L), falling on segment j
         int jm = j == 0 ? g.ng - 1 : j - 1;
         Piece P = seg_piece(g, i), Q1 = seg_piece(g, jm), Q2 = seg_piece(g, j);
         KernK<OP == OP_DK> k1(tb, g.alpha, Q1), k2(tb, g.alpha, Q2);
-        if (relation(P, Q1) != 1) pair_integral(T, O, tb, q_far, P, Q1, k1);   // coincident: (x-y).n = 0
-        if (relation(P, Q2) != 1) pair_integral(T, O, tb, q_far, P, Q2, k2);
+        if (relation(P, Q1) != 1) pair_integral(T, O, tb, q_far, q_inc(OP), P, Q1, k1);   // coincident: (x-y).n = 0
+        if (relation(P, Q2) != 1) pair_integral(T, O, tb, q_far, q_inc(OP), P, Q2, k2);
         return k1.acc1 + k2.acc0;
     } else {
         DualSupport si = dual_support(g, i), sj = dual_support(g, j);
@@ -649,7 +766,7 @@ SDEV double entry(const Tables& T, const Orders& O, const Geom& g, const TimeBlo
                 kf.txx = P.ex; kf.txy = P.ey; kf.tyx = Q.ex; kf.tyy = Q.ey;
                 kf.tt = P.ex * Q.ex + P.ey * Q.ey;
                 kf.raw = raw;
-                pair_integral(T, O, tb, q_far, P, Q, kf);
+                pair_integral(T, O, tb, q_far, q_inc(OP), P, Q, kf);
                 acc += kf.acc;
             }
         }

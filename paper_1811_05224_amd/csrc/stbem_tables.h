@@ -43,9 +43,13 @@ inline Orders default_orders()
     Orders o;
     o.q_sing = 12;
     o.q_log = 6;
-    o.q_near[0] = 12; o.q_near[1] = 10; o.q_near[2] = 8; o.q_near[3] = 6;
-    o.eta_cut[0] = 1.5; o.eta_cut[1] = 3.0; o.eta_cut[2] = 6.0;
+    const int q[kNearClasses] = {12, 10, 8, 6, 5, 4};
+    const double cut[kNearClasses - 1] = {1.5, 3.0, 6.0, 12.0, 24.0};
+    for (int c = 0; c < kNearClasses; ++c) o.q_near[c] = q[c];
+    for (int c = 0; c + 1 < kNearClasses; ++c) o.eta_cut[c] = cut[c];
     o.eta_raw = 4.0;
+    o.q_tol = 1e-15;
+    o.z_floor = 18.42;    // ln 1e8
     return o;
 }
 
