@@ -3,8 +3,8 @@ N = 32768, Omega 64^2), in the configuration bench.py times.
 
 Entries: stratified samples (touching/separated time elements, coincident,
 adjacent, near and far spatial pairs) compared with the oracle one by one;
-the floor of the relative error uses the oracle's largest value among the
-sampled entries of the same block (diagonal and its neighbours included).
+the floor of the relative error is 1e-8 of the block's scale (the oracle's
+largest sampled value, for K_h its largest value in the sampled row).
 Solution: the oracle evaluates single rows of V_h, K_h, M_h and M_h^0 and
 checks the residual of the GPU solution row by row.
 """
@@ -13,6 +13,7 @@ import pytest
 
 import workloads as W
 from oracle.oracle import Oracle
+from floor_rule import block_floor
 
 pytestmark = pytest.mark.gpu
 
@@ -51,10 +52,7 @@ def test_medium_sampled_entries(medium, op, tol):
     b = idx[:, 0].astype(np.int64) * (idx[:, 0] + 1) // 2 + idx[:, 1]
     t = lambda a: torch.as_tensor(np.asarray(a, dtype=np.int64), device=P.device)
     got = P[t(b), t(idx[:, 2]), t(idx[:, 3])].cpu().numpy()
-    scale = {}
-    for n, (k, m) in enumerate(zip(idx[:, 0], idx[:, 1])):
-        scale[(k, m)] = max(scale.get((k, m), 0.0), abs(ref[n]))
-    floor = np.array([1e-8 * scale[(k, m)] for k, m in zip(idx[:, 0], idx[:, 1])])
+    floor = block_floor(o, op, idx, ref, c.ng)
     e = np.abs(got - ref) / np.maximum(np.abs(ref), floor + 1e-300)
     print(op, "samples", len(idx), "max err", e.max())
     assert e.max() <= tol

@@ -15,6 +15,7 @@ import pytest
 
 import workloads as W
 from oracle.oracle import Oracle
+from floor_rule import block_floor
 
 pytestmark = pytest.mark.gpu
 
@@ -38,10 +39,7 @@ def _check_entries(c, o, op, code, idx, tol):
     b = idx[:, 0].astype(np.int64) * (idx[:, 0] + 1) // 2 + idx[:, 1]
     t = lambda a: torch.as_tensor(np.asarray(a, dtype=np.int64), device=P.device)
     got = P[t(b), t(idx[:, 2]), t(idx[:, 3])].cpu().numpy()
-    scale = {}
-    for n, (k, m) in enumerate(zip(idx[:, 0], idx[:, 1])):
-        scale[(k, m)] = max(scale.get((k, m), 0.0), abs(ref[n]))
-    floor = np.array([1e-8 * scale[(k, m)] for k, m in zip(idx[:, 0], idx[:, 1])])
+    floor = block_floor(o, op, idx, ref, c.ng)
     e = np.abs(got - ref) / np.maximum(np.abs(ref), floor + 1e-300)
     print(op, "samples", len(idx), "max err", e.max())
     for w in np.argsort(e)[::-1][:6]:
