@@ -325,6 +325,8 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
     __shared__ Piece pc[2][kDP];
     __shared__ double mom[kDP][kDP][5];
     __shared__ unsigned char form[kTile][kTile];   // 0 by-parts, 1 raw, 2 outside the matrix
+    __shared__ short list[kDP * kDP];              // pairs to compute, costly ones first
+    __shared__ int nlist[2];
     const int tid = threadIdx.x;
     const long long tiles = (long long)tiles_1d * tiles_1d;
     const long long b = blist[blockIdx.x / tiles];
@@ -370,10 +372,37 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
     if (inside) { si = dual_support(g, i); sj = dual_support(g, j); }
     const long long off = b * (long long)g.ng * g.ng + (long long)i * g.ng + j;
 
+    // Pairs a pass needs, compacted so that no lane idles on unneeded pairs;
+    // for the by-parts pass the singular pairs (many more nodes) go first so
+    // that they are spread over the lanes of the first round.  The order of
+    // the list does not change any result: each pair's moments are computed
+    // by one lane with the same arithmetic.
+    auto build_list = [&](int f) {
+        if (tid < 2) nlist[tid] = 0;
+        __syncthreads();
+        if (f == 0)
+            for (int e = tid; e < kDP * kDP; e += kWG) {
+                const int u = e / kDP, v = e % kDP;
+                if (needs(u, v, f) && relation(pc[0][u], pc[1][v])) list[atomicAdd(&nlist[0], 1)] = (short)e;
+            }
+        __syncthreads();
+        if (tid == 0) nlist[1] = nlist[0];
+        __syncthreads();
+        for (int e = tid; e < kDP * kDP; e += kWG) {
+            const int u = e / kDP, v = e % kDP;
+            if (needs(u, v, f) && !(f == 0 && relation(pc[0][u], pc[1][v]))) list[atomicAdd(&nlist[1], 1)] = (short)e;
+        }
+        __syncthreads();
+        return nlist[1];
+    };
+
     // pass 1: raw-form entries
-    for (int e = tid; e < kDP * kDP; e += kWG) {
-        const int u = e / kDP, v = e % kDP;
-        if (needs(u, v, 1)) d_pair_raw(T, O, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v]);
+    {
+        const int n = build_list(1);
+        for (int e = tid; e < n; e += kWG) {
+            const int u = list[e] / kDP, v = list[e] % kDP;
+            d_pair_raw(T, O, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v]);
+        }
     }
     __syncthreads();
     if (my == 1) {
@@ -394,9 +423,12 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
     __syncthreads();
 
     // pass 2: by-parts entries (curl part psi'_P psi'_Q m0 + the normal part)
-    for (int e = tid; e < kDP * kDP; e += kWG) {
-        const int u = e / kDP, v = e % kDP;
-        if (needs(u, v, 0)) d_pair_bp(T, O, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v]);
+    {
+        const int n = build_list(0);
+        for (int e = tid; e < n; e += kWG) {
+            const int u = list[e] / kDP, v = list[e] % kDP;
+            d_pair_bp(T, O, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v]);
+        }
     }
     __syncthreads();
     if (my == 0) {

@@ -435,8 +435,9 @@ SDEV void rule_vertex(const Tables& T, const Piece& P, const Piece& Q, int rel, 
 // Order of the regular rule on a pair of pieces of touching time elements.
 // Two things limit it: the distance to the r = 0 singularity (classes of
 // eta = distance / length), and the factor e^{-z}, z = w2 r^2, which changes
-// by dz = w2 (r_hi^2 - r_lo^2) across the pair.  For the second, the q-point
-// Gauss remainder of e^{-dz s} on [0, 1] relative to its integral is at most
+// along one piece by at most dz = w2 L (2 r_lo + L) (L the longer length,
+// r_lo the distance of the pieces).  For the second, the q-point Gauss
+// remainder of e^{-dz s} on [0, 1] relative to its integral is at most
 // c_q dz^{2q} e^{dz}, c_q = (q!)^4 / ((2q+1) ((2q)!)^3); pairs whose factor
 // is below e^{-z_floor} (of the block maximum, attained at r = 0) need that
 // bound only relative to e^{-z_floor}.
@@ -445,8 +446,8 @@ SDEV int q_touch(const Orders& O, const TimeBlock& tb, const Piece& P, const Pie
     int qe = O.q_near[kNearClasses - 1];
     for (int c = kNearClasses - 2; c >= 0; --c)
         if (eta < O.eta_cut[c]) qe = O.q_near[c];
-    const double rlo = eta * (P.len > Q.len ? P.len : Q.len), rhi = rlo + P.len + Q.len;
-    const double zlo = tb.w2 * rlo * rlo, dz = tb.w2 * (rhi * rhi - rlo * rlo);
+    const double L = P.len > Q.len ? P.len : Q.len, rlo = eta * L;
+    const double zlo = tb.w2 * rlo * rlo, dz = tb.w2 * L * (2.0 * rlo + L);
     const double lim = O.q_tol * exp(-dz) * (zlo > O.z_floor ? exp(zlo - O.z_floor) : 1.0);
     const double dz2 = dz * dz;
     double c = 1.0 / 24.0, pw = dz2;   // c_1, dz^2
