@@ -27,10 +27,19 @@ METRIC = "entries/s (V_h,K_h,D_h) + precond. GMRES solve s to 1e-10, FP64 vs FP3
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
-# FP64 VALU operations per stored entry of each assembly kernel on the
-# medium workload, from the rocprofv3 FP64 instruction counters
-# (profiles/assembly_flops_medium.md); None until measured.
-FLOP_PER_ENTRY = {"V": None, "K": None, "D": None}
+# Per work unit of each kernel on the medium workload (units as reported by
+# the library's launch timing: matrix entries, or (row, triangle) pairs for
+# the M_h^0 moment kernels), measured with rocprofv3 counters:
+#   FP64 operations = 64 x (ADD_F64 + MUL_F64 + 2 FMA_F64 + TRANS_F64) wave
+#   instructions (inactive lanes included), profiles/counters_fp64_medium.md;
+#   HBM bytes = 2 x FETCH_SIZE + WRITE_SIZE (KiB x 1024), the factors from a
+#   1 GiB device copy read by the same counters, profiles/counters_hbm_medium.md.
+# A kernel changed after its counters were taken has no entry here.
+FLOP_PER_UNIT = {}
+HBM_BYTES_PER_UNIT = {}
+# bytes streamed per stored entry by the matrix-vector kernels
+GEMV_BYTES = {"k_gemv_n_vec<double>": 8, "k_gemv_t_vec<double>": 8, "k_gemv_n_vec<float hi+lo>": 8,
+              "k_gemv_t_vec<float hi+lo>": 8, "k_gemv_n_vec<float>": 4, "k_gemv_t_vec<float>": 4}
 
 
 def parse():
@@ -102,12 +111,15 @@ def main():
         step(None)
     torch.cuda.synchronize()
     rec = []
+    ctx.set_timing(True)      # HIP events around every assembly and GEMV launch, on its stream
     t0 = time.perf_counter()
     for _ in range(args.steps):
         f, w64, w32 = step(rec)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / args.steps
+    ktimes = ctx.kernel_times()
+    ctx.set_timing(False)
 
     entries = ctx.packed_entries            # per causal matrix
     avg = {k: float(np.mean([r[k] for r in rec])) for k in ("V", "K", "D", "M0", "rhs", "solve64", "solve32")}
@@ -131,14 +143,8 @@ def main():
     ir_vs_fp64 = float(np.linalg.norm(w32n - w64n) / np.linalg.norm(w64n))
     disc64 = float(np.linalg.norm(w64n - wl.w_ref) / np.linalg.norm(wl.w_ref))
 
-    dominant = max(("V", "K", "D", "M0"), key=lambda k: avg[k])
-    if dominant != "M0" and FLOP_PER_ENTRY.get(dominant):
-        achieved = FLOP_PER_ENTRY[dominant] * entries / (avg[dominant] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "kernel": f"k_assemble<{dominant}>"}
-    else:
-        roof = {"bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
-                "traffic": None, "kernel": f"assembly of {dominant} (flop count not yet measured)"}
+    roof = roofline(ktimes)
+    kernel_ms = {k: round(v[1] / args.steps, 3) for k, v in sorted(ktimes.items(), key=lambda kv: -kv[1][1])}
 
     out = {
         "metric": METRIC, "value": value, "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
@@ -156,10 +162,33 @@ def main():
         "fp32_refined_vs_fp64_rel_err": ir_vs_fp64, "discretisation_err_vs_exact_flux": disc64,
         "gemv_V": {"ms": gemv_ms, "GB/s": gemv_gbs, "frac_hbm": gemv_gbs / HBM_PEAK_GBS},
         "roofline": roof,
+        "kernel_ms_per_step": kernel_ms,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def roofline(ktimes):
+    """Roofline of the kernel with the largest event time in the timed steps:
+    algorithmic work per launch (per-unit figure x units per launch) over the
+    average launch duration from the HIP events."""
+    name, (launches, ms, units) = max(ktimes.items(), key=lambda kv: kv[1][1])
+    per_launch_s = ms * 1e-3 / launches
+    per_launch_units = units / launches
+    traffic = HBM_BYTES_PER_UNIT.get(name)
+    traffic = traffic * per_launch_units if traffic is not None else None
+    if name in GEMV_BYTES:
+        achieved = GEMV_BYTES[name] * per_launch_units / per_launch_s / 1e9
+        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": name,
+                "launch_ms": per_launch_s * 1e3, "units_per_launch": per_launch_units}
+    flop = FLOP_PER_UNIT.get(name)
+    achieved = flop * per_launch_units / per_launch_s / 1e12 if flop is not None else None
+    return {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS if achieved is not None else None, "traffic": traffic,
+            "kernel": name, "launch_ms": per_launch_s * 1e3, "units_per_launch": per_launch_units,
+            "flop_per_unit": flop}
 
 
 def cpu_baseline(wl, nsamp):

@@ -175,6 +175,26 @@ int stbem_grad_alpha(stbem_ctx* ctx, const double* lambda_dev, const double* w_d
  * device code (idx_dev: n quadruples (k, m, i, j) as int32; out_dev: n). */
 int stbem_entries(stbem_ctx* ctx, unsigned op, long long n, const int* idx_dev, double* out_dev, void* stream);
 
+/* Launch timing, for measuring kernels in place.  With on = 1 every launch
+ * of the assembly kernels and of the matrix-vector kernels is bracketed by
+ * HIP events recorded on the stream it runs on (a few microseconds of host
+ * work per launch); on = 0 stops.  Either call first waits for and drops the
+ * records taken so far.  stbem_kernel_times sums the records per kernel name
+ * (the names of the kernels in the library): launches, event time in ms and
+ * the work units the launches processed: matrix entries for the V_h, K_h,
+ * D_h kernels and the matrix-vector kernels, (row, triangle) pairs for the
+ * M_h^0 moment kernels, matrix entries for the M_h^0 gather.  It writes at
+ * most `cap` records to `out` (host) and returns the number of names, or a
+ * negative error; it waits for the recorded events. */
+typedef struct {
+    char name[48];
+    long long launches;
+    double ms;
+    double units;
+} stbem_kernel_time;
+int stbem_set_timing(stbem_ctx* ctx, int on);
+int stbem_kernel_times(stbem_ctx* ctx, stbem_kernel_time* out, int cap);
+
 #ifdef __cplusplus
 }
 #endif

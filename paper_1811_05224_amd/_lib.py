@@ -24,6 +24,11 @@ class stbem_solve_opts(ctypes.Structure):
                 ("ir_tol", ctypes.c_double)]
 
 
+class stbem_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_longlong), ("ms", ctypes.c_double),
+                ("units", ctypes.c_double)]
+
+
 class stbem_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer", ctypes.c_int), ("relres", ctypes.c_double),
                 ("true_relres", ctypes.c_double)]
@@ -62,6 +67,8 @@ def load():
         "stbem_solve": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(stbem_solve_opts), ctypes.POINTER(stbem_solve_info), vp]),
         "stbem_grad_alpha": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "stbem_entries": (ctypes.c_int, [vp, ctypes.c_uint, ctypes.c_longlong, vp, vp, vp]),
+        "stbem_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
+        "stbem_kernel_times": (ctypes.c_int, [vp, ctypes.POINTER(stbem_kernel_time), ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -72,4 +79,5 @@ def load():
 
 EXPORTED = ["stbem_create", "stbem_destroy", "stbem_last_error", "stbem_set_allocator", "stbem_sizes",
             "stbem_assemble", "stbem_release", "stbem_matrix", "stbem_apply", "stbem_mass", "stbem_precondition", "stbem_rhs",
-            "stbem_prepare_ir", "stbem_solve", "stbem_grad_alpha", "stbem_entries"]
+            "stbem_prepare_ir", "stbem_solve", "stbem_grad_alpha", "stbem_entries", "stbem_set_timing",
+            "stbem_kernel_times"]

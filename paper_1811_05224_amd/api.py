@@ -175,6 +175,17 @@ class Context:
                                               self._stream()), "stbem_grad_alpha")
         return out
 
+    def set_timing(self, on=True):
+        self._check(self.lib.stbem_set_timing(self._h, 1 if on else 0), "stbem_set_timing")
+
+    def kernel_times(self):
+        """{kernel name: (launches, event ms, work units)} recorded since timing was switched on."""
+        cap = 64
+        buf = (L.stbem_kernel_time * cap)()
+        n = self.lib.stbem_kernel_times(self._h, buf, cap)
+        self._check(min(n, 0), "stbem_kernel_times")
+        return {buf[e].name.decode(): (buf[e].launches, buf[e].ms, buf[e].units) for e in range(min(n, cap))}
+
     def entries(self, op, idx):
         idx = torch.as_tensor(np.asarray(idx, dtype=np.int32).reshape(-1, 4), device=self.device).contiguous()
         out = self.vec(n=idx.shape[0])

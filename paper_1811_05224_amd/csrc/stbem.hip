@@ -920,6 +920,10 @@ struct stbem_ctx {
     stbem_free_fn release = nullptr;
     void* user = nullptr;
     std::string err;
+    // launch timing (stbem_set_timing): one event pair per launch
+    struct TRec { std::string name; double units; hipEvent_t a, b; };
+    bool timing = false;
+    std::vector<TRec> trecs;
 };
 
 namespace {
@@ -1023,6 +1027,39 @@ int ensure_part(stbem_ctx* c)
     return 0;
 }
 
+// Brackets one kernel launch with HIP events on its stream when timing is on.
+struct KTimer {
+    stbem_ctx* c; hipStream_t s; long long idx = -1;
+    KTimer(stbem_ctx* c_, const char* name, double units, hipStream_t s_) : c(c_), s(s_)
+    {
+        if (!c->timing) return;
+        stbem_ctx::TRec r{name, units, nullptr, nullptr};
+        if (hipEventCreate(&r.a) != hipSuccess) return;
+        if (hipEventCreate(&r.b) != hipSuccess) { (void)hipEventDestroy(r.a); return; }
+        (void)hipEventRecord(r.a, s);
+        c->trecs.push_back(r);
+        idx = (long long)c->trecs.size() - 1;
+    }
+    void stop()
+    {
+        if (idx >= 0) (void)hipEventRecord(c->trecs[idx].b, s);
+        idx = -1;
+    }
+    ~KTimer() { stop(); }
+};
+
+void clear_timing(stbem_ctx* c)
+{
+    for (auto& r : c->trecs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    c->trecs.clear();
+}
+
+std::string kname(const char* base, int a) { return std::string(base) + "<" + std::to_string(a) + ">"; }
+std::string kname(const char* base, int a, int b)
+{
+    return std::string(base) + "<" + std::to_string(a) + ", " + std::to_string(b) + ">";
+}
+
 // A dispatch's grid size is counted in work-items in 32 bits: launches over
 // block lists are split so that workgroups x 256 stays below 2^32.
 constexpr long long kMaxWG = (0xffffffffLL / kWG) - 1;
@@ -1045,6 +1082,7 @@ int launch_assemble(stbem_ctx* c, int store, double* o64, float* hi, float* lo, 
         const int cnt = std::min(step, c->nlist_gen[slot] - off);
         const int* bl = c->d_blist[slot] + c->nlist_touch[slot] + off;
         dim3 gr((unsigned)(cnt * tiles)), blk(kWG);
+        KTimer kt(c, kname("k_assemble", OP, store).c_str(), (double)cnt * g.ng * g.ng, s);
         if (store == ST_F64)
             hipLaunchKernelGGL((k_assemble<OP, ST_F64>), gr, blk, 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64, hi, lo);
         else if (store == ST_F32)
@@ -1065,6 +1103,7 @@ void launch_vkfar(stbem_ctx* c, int slot, const int* bl, int cnt, double* o, hip
     const int step = blocks_per_launch(tiles);
     for (int off = 0; off < cnt; off += step) {
         const int n = std::min(step, cnt - off);
+        KTimer kt(c, kname("k_assemble_vkfar", OP, Q).c_str(), (double)n * c->ng * c->ng, s);
         hipLaunchKernelGGL((k_assemble_vkfar<OP, Q>), dim3((unsigned)(n * tiles)), dim3(kWG), 0, s, geom(c), c->d_tab,
                            bl + off, ti, tj, o);
     }
@@ -1145,6 +1184,7 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
         const int step = blocks_per_launch(tiles);
         for (int off = 0; off < c->nlist_touch[2]; off += step) {
             const int n = std::min(step, c->nlist_touch[2] - off);
+            KTimer kt(c, "k_assemble_dnear", (double)n * c->ng * c->ng, s);
             hipLaunchKernelGGL(k_assemble_dnear, dim3((unsigned)(n * tiles)), dim3(kWG), 0, s, geom(c), c->d_tab, c->ord,
                                (const int*)(c->d_blist[2] + off), t1, o);
         }
@@ -1156,6 +1196,7 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
                 const int n = std::min(step, c->nlist_far[2][q] - off);
                 dim3 gr((unsigned)(n * tiles)), blk(kWG);
                 const int* b2 = bl + off;
+                KTimer kt(c, kname("k_assemble_dfar", q).c_str(), (double)n * c->ng * c->ng, s);
                 switch (q) {
                 case 3: hipLaunchKernelGGL(k_assemble_dfar<3>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, b2, t1, o, (float*)nullptr); break;
                 case 4: hipLaunchKernelGGL(k_assemble_dfar<4>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, b2, t1, o, (float*)nullptr); break;
@@ -1188,17 +1229,20 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
             // the kernel with the singular rules, the others the regular one
             long long nf = r0 < c->ng ? std::min<long long>(nr, c->ng - r0) : 0, nl = nr - nf;
             if (nf > 0) {
+                KTimer kt(c, op == STBEM_M0 ? "k_m0_tri<false, true>" : "k_m0_tri<true, true>", (double)nf * c->ntri, s);
                 if (op == STBEM_M0)
                     hipLaunchKernelGGL((k_m0_tri<false, true>), dim3((unsigned)(nf * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), r0, 0LL, tchunk, scratch);
                 else
                     hipLaunchKernelGGL((k_m0_tri<true, true>), dim3((unsigned)(nf * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), r0, 0LL, tchunk, scratch);
             }
             if (nl > 0) {
+                KTimer kt(c, op == STBEM_M0 ? "k_m0_tri<false, false>" : "k_m0_tri<true, false>", (double)nl * c->ntri, s);
                 if (op == STBEM_M0)
                     hipLaunchKernelGGL((k_m0_tri<false, false>), dim3((unsigned)(nl * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), r0, nf, tchunk, scratch);
                 else
                     hipLaunchKernelGGL((k_m0_tri<true, false>), dim3((unsigned)(nl * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), r0, nf, tchunk, scratch);
             }
+            KTimer kt(c, "k_m0_gather", (double)nr * c->nv, s);
             hipLaunchKernelGGL(k_m0_gather, dim3((unsigned)(nr * vchunk)), dim3(kWG), 0, s, mesh(c), (const int*)c->d_v2t_loc, r0, vchunk, (const double*)scratch, o);
             if (hipGetLastError() != hipSuccess) rc = fail(c, STBEM_EHIP, "M0 kernels");
         }
@@ -1220,6 +1264,9 @@ int packed_apply(stbem_ctx* c, const double* A, const float* hi, const float* lo
     // vector width: the row length must be a multiple of 64 * VW
     const int vw64 = (ng % 128 == 0) ? 2 : 1;
     const int vw32 = (ng % 256 == 0) ? 4 : (ng % 128 == 0 ? 2 : 1);
+    const char* gname = !trans ? (A ? "k_gemv_n_vec<double>" : hi ? "k_gemv_n_vec<float hi+lo>" : "k_gemv_n_vec<float>")
+                               : (A ? "k_gemv_t_vec<double>" : hi ? "k_gemv_t_vec<float hi+lo>" : "k_gemv_t_vec<float>");
+    KTimer kt(c, gname, (double)c->nblk * ng * ng, s);
     if (!trans) {
         int rowchunks = (ng + 15) / 16;
         dim3 gr((unsigned)(c->nblk * rowchunks)), bl(kWG);
@@ -1256,6 +1303,7 @@ int packed_apply(stbem_ctx* c, const double* A, const float* hi, const float* lo
         }
     }
     HIPCHK(c, hipGetLastError());
+    kt.stop();
     hipLaunchKernelGGL(k_gemv_reduce, dim3(grid1(c->n)), dim3(kWG), 0, s, c->part, y, c->ng, c->nt, trans);
     HIPCHK(c, hipGetLastError());
     return 0;
@@ -1458,8 +1506,42 @@ int stbem_destroy(stbem_ctx* c)
                    c->d_tri, c->d_v2t_ptr, c->d_v2t, c->d_tab, c->d_m0tab, c->part};
     for (void* p : own) if (p) (void)hipFree(p);
     for (int q = 0; q < 7; ++q) if (c->d_blist[q]) (void)hipFree(c->d_blist[q]);
+    clear_timing(c);
     delete c;
     return STBEM_OK;
+}
+
+int stbem_set_timing(stbem_ctx* c, int on)
+{
+    if (!c) return STBEM_EINVAL;
+    for (auto& r : c->trecs) (void)hipEventSynchronize(r.b);
+    clear_timing(c);
+    c->timing = on != 0;
+    return STBEM_OK;
+}
+
+int stbem_kernel_times(stbem_ctx* c, stbem_kernel_time* out, int cap)
+{
+    if (!c || (cap > 0 && !out) || cap < 0) return STBEM_EINVAL;
+    std::vector<stbem_kernel_time> agg;
+    for (auto& r : c->trecs) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return fail(c, STBEM_EHIP, "timing event");
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return fail(c, STBEM_EHIP, "timing event");
+        size_t e = 0;
+        while (e < agg.size() && r.name != agg[e].name) ++e;
+        if (e == agg.size()) {
+            stbem_kernel_time k;
+            memset(&k, 0, sizeof k);
+            snprintf(k.name, sizeof k.name, "%s", r.name.c_str());
+            agg.push_back(k);
+        }
+        agg[e].launches += 1;
+        agg[e].ms += ms;
+        agg[e].units += r.units;
+    }
+    for (size_t e = 0; e < agg.size() && (int)e < cap; ++e) out[e] = agg[e];
+    return (int)agg.size();
 }
 
 int stbem_set_allocator(stbem_ctx* c, stbem_alloc_fn alloc, stbem_free_fn release, void* user)
