@@ -493,8 +493,9 @@ __global__ __launch_bounds__(kWG) void k_m0_tri(Geom g, Mesh2 mesh, const Tables
     if (t >= mesh.ntri) return;
     const long long row = row0 + lrow;          // row = k * ng + i
     const int k = (int)(row / g.ng), i = (int)(row % g.ng);
-    // k >= 1: the kernel varies on the time scale sqrt(4 t_k / alpha)
-    int qs = 8;
+    // k >= 1: the kernel varies on the time scale sqrt(4 t_k / alpha); k = 0:
+    // the order follows the distance of the triangle (m0_tri_moments)
+    int qs = 3;
     if (k > 0) {
         qs = q_time(fmax(g.len[i], MO.omax), g.t[k], g.alpha) + 1;
         qs = qs < 4 ? 4 : qs;
@@ -517,6 +518,95 @@ __global__ __launch_bounds__(kWG) void k_m0_gather(Mesh2 mesh, const int* __rest
     double acc = 0.0;
     for (int p = mesh.v2t_ptr[j]; p < mesh.v2t_ptr[j + 1]; ++p) acc += sr[mesh.v2t[p] * 3 + v2t_loc[p]];
     out[(row0 + lrow) * mesh.nv + j] = acc;
+}
+
+// M_h^0 rows k >= ksplit: every (segment, triangle) pair lies in the range
+// of the power series G_k = sc sum_n c_{k,n} a^n, a = alpha r^2/4, so the
+// rows differ only by their coefficients.  The moments of a^n against the
+// hats, S[i][n][t][v] = int_{gamma_i} int_t a^n lambda_v, are computed once
+// with the quadrature the rows need at t_{ksplit} (the most demanding of
+// them), gathered per vertex j into G[i][n][j], and every row is one
+// contraction M0[(k,i), j] = sc sum_n c_{k,n} G[i][n][j].
+// One lane per (segment, triangle, local vertex) of a chunk of segments.
+__global__ __launch_bounds__(kWG) void k_m0_pow(Geom g, Mesh2 mesh, const Tables* __restrict__ Tg, double omax,
+                                                double tsplit, int i0, int ni, int npow, double* __restrict__ S)
+{
+    __shared__ Tables T;
+    {
+        const double* src = reinterpret_cast<const double*>(Tg);
+        double* dst = reinterpret_cast<double*>(&T);
+        for (int e = threadIdx.x; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
+    }
+    __syncthreads();
+    const long long per_i = 3LL * mesh.ntri;
+    const long long e = (long long)blockIdx.x * kWG + threadIdx.x;
+    if (e >= (long long)ni * per_i) return;
+    const int il = (int)(e / per_i), rem = (int)(e % per_i), t = rem / 3, v = rem % 3;
+    const int i = i0 + il;
+    int qs = q_time(fmax(g.len[i], omax), tsplit, g.alpha) + 1;
+    qs = qs < 4 ? 4 : qs;
+    const Piece P = seg_piece(g, i);
+    const Tri3 tr = load_tri3(mesh, t);
+    const double e1x = tr.bx - tr.ax, e1y = tr.by - tr.ay, e2x = tr.cx - tr.ax, e2y = tr.cy - tr.ay;
+    const double area2 = fabs(e1x * e2y - e1y * e2x), q4 = 0.25 * g.alpha;
+    double mom[kPolyMax];
+#pragma unroll
+    for (int n = 0; n < kPolyMax; ++n) mom[n] = 0.0;
+    for (int a = 0; a < qs; ++a) {
+        const double u = T.gl_x[qs][a], wu = T.gl_w[qs][a] * (1.0 - u);
+        for (int b = 0; b < qs; ++b) {
+            const double vv = T.gl_x[qs][b] * (1.0 - u), w = wu * T.gl_w[qs][b] * area2;
+            const double lam = v == 0 ? 1.0 - u - vv : (v == 1 ? u : vv);
+            const double yx = tr.ax + u * e1x + vv * e2x, yy = tr.ay + u * e1y + vv * e2y;
+            for (int c = 0; c < qs; ++c) {
+                const double sx = P.len * T.gl_x[qs][c];
+                const double dx = P.ax + sx * P.ex - yx, dy = P.ay + sx * P.ey - yy;
+                const double aa = q4 * (dx * dx + dy * dy);
+                double pw = w * lam * T.gl_w[qs][c];
+#pragma unroll
+                for (int n = 0; n < kPolyMax; ++n) {
+                    if (n < npow) { mom[n] += pw; pw *= aa; }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < kPolyMax; ++n)
+        if (n < npow) S[(((long long)il * npow + n) * mesh.ntri + t) * 3 + v] = mom[n] * P.len;
+}
+
+// G[i][n][j] = sum over the triangles of vertex j (fixed order)
+__global__ __launch_bounds__(kWG) void k_m0_pow_gather(Mesh2 mesh, const int* __restrict__ v2t_loc, int i0, int ni,
+                                                       int npow, const double* __restrict__ S, double* __restrict__ G)
+{
+    const long long e = (long long)blockIdx.x * kWG + threadIdx.x;
+    if (e >= (long long)ni * npow * mesh.nv) return;
+    const int j = (int)(e % mesh.nv);
+    const long long ln = e / mesh.nv;          // il * npow + n
+    const double* s = S + ln * mesh.ntri * 3;
+    double acc = 0.0;
+    for (int p = mesh.v2t_ptr[j]; p < mesh.v2t_ptr[j + 1]; ++p) acc += s[mesh.v2t[p] * 3 + v2t_loc[p]];
+    G[((long long)i0 * npow + ln) * mesh.nv + j] = acc;
+}
+
+// rows k = ksplit .. nt-1: M0[(k,i), j] = sc sum_n coef[k][n] G[i][n][j]
+__global__ __launch_bounds__(kWG) void k_m0_pow_apply(int ng, int nv, int nt, int ksplit, int npow,
+                                                      const double* __restrict__ coef, double sc,
+                                                      const double* __restrict__ G, double* __restrict__ out)
+{
+    const long long e = (long long)blockIdx.x * kWG + threadIdx.x;
+    if (e >= (long long)ng * nv) return;
+    const int i = (int)(e / nv), j = (int)(e % nv);
+    double gm[kPolyMax];
+#pragma unroll
+    for (int n = 0; n < kPolyMax; ++n) gm[n] = n < npow ? G[((long long)i * npow + n) * nv + j] : 0.0;
+    for (int k = ksplit; k < nt; ++k) {
+        const double* ck = coef + (long long)k * kPolyMax;
+        double acc = 0.0;
+#pragma unroll
+        for (int n = kPolyMax - 1; n >= 0; --n) acc += ck[n] * gm[n];
+        out[((long long)k * ng + i) * nv + j] = sc * acc;
+    }
 }
 
 // ---------------------------------------------------------------- GEMV
@@ -898,6 +988,7 @@ struct stbem_ctx {
     double *d_t = nullptr, *d_vx = nullptr, *d_vy = nullptr, *d_ex = nullptr, *d_ey = nullptr, *d_len = nullptr;
     double *d_ox = nullptr, *d_oy = nullptr, *d_mt = nullptr;
     double *d_m0c = nullptr, *d_m0cd = nullptr, *d_m0amax = nullptr;
+    int m0_ksplit = 0, m0_npow = 0;   // M0 rows k >= m0_ksplit by moments of powers (none if == nt)
     int *d_m0n = nullptr, *d_v2t_loc = nullptr;
     int *d_tri = nullptr, *d_v2t_ptr = nullptr, *d_v2t = nullptr;
     Tables* d_tab = nullptr;
@@ -1157,6 +1248,50 @@ int build_block_lists(stbem_ctx* c)
     return 0;
 }
 
+// M0 rows k >= m0_ksplit from the power moments (k_m0_pow, _gather, _apply)
+int m0_power_rows(stbem_ctx* c, bool deriv, double* o, hipStream_t s)
+{
+    const int npow = c->m0_npow;
+    const long long per_i = (long long)npow * c->ntri * 3 * (long long)sizeof(double);
+    long long ni = (1LL << 30) / (per_i > 0 ? per_i : 1);
+    ni = ni < 1 ? 1 : (ni > c->ng ? c->ng : ni);
+    double* S = (double*)dev_alloc(c, (size_t)(ni * per_i));
+    double* G = (double*)dev_alloc(c, (size_t)c->ng * npow * c->nv * sizeof(double));
+    if (!S || !G) {
+        dev_free(c, S); dev_free(c, G);
+        return fail(c, STBEM_ENOMEM, "M0 power-moment buffers");
+    }
+    Geom g = geom(c);
+    int rc = 0;
+    for (int i0 = 0; i0 < c->ng && !rc; i0 += (int)ni) {
+        const int n = (int)std::min<long long>(ni, c->ng - i0);
+        const long long lanes = (long long)n * c->ntri * 3, glanes = (long long)n * npow * c->nv;
+        {
+            KTimer kt(c, "k_m0_pow", (double)n * c->ntri, s);
+            hipLaunchKernelGGL(k_m0_pow, dim3((unsigned)((lanes + kWG - 1) / kWG)), dim3(kWG), 0, s, g, mesh(c), c->d_tab,
+                               c->m0ord.omax, c->t[c->m0_ksplit], i0, n, npow, S);
+        }
+        {
+            KTimer kt(c, "k_m0_pow_gather", (double)n * npow * c->nv, s);
+            hipLaunchKernelGGL(k_m0_pow_gather, dim3((unsigned)((glanes + kWG - 1) / kWG)), dim3(kWG), 0, s, mesh(c),
+                               (const int*)c->d_v2t_loc, i0, n, npow, (const double*)S, G);
+        }
+        if (hipGetLastError() != hipSuccess) rc = fail(c, STBEM_EHIP, "M0 power-moment kernels");
+    }
+    if (!rc) {
+        const long long lanes = (long long)c->ng * c->nv;
+        const double sc = (deriv ? 1.0 : c->alpha) * kInv4Pi;
+        KTimer kt(c, "k_m0_pow_apply", (double)(c->nt - c->m0_ksplit) * lanes, s);
+        hipLaunchKernelGGL(k_m0_pow_apply, dim3((unsigned)((lanes + kWG - 1) / kWG)), dim3(kWG), 0, s, c->ng, c->nv, c->nt,
+                           c->m0_ksplit, npow, (const double*)(deriv ? c->d_m0cd : c->d_m0c), sc, (const double*)G, o);
+        if (hipGetLastError() != hipSuccess) rc = fail(c, STBEM_EHIP, "M0 power-moment contraction");
+    }
+    (void)hipStreamSynchronize(s);
+    dev_free(c, S);
+    dev_free(c, G);
+    return rc;
+}
+
 int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
 {
     int slot = op_slot(op);
@@ -1223,8 +1358,9 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
         if (!scratch) return fail(c, STBEM_ENOMEM, "M0 scratch of %lld bytes", rows * per_row);
         int tchunk = (c->ntri + kWG - 1) / kWG, vchunk = (c->nv + kWG - 1) / kWG;
         int rc = 0;
-        for (long long r0 = 0; r0 < c->n && !rc; r0 += rows) {
-            long long nr = c->n - r0 < rows ? c->n - r0 : rows;
+        const long long nrow = (long long)c->m0_ksplit * c->ng;   // rows of the per-row kernels
+        for (long long r0 = 0; r0 < nrow && !rc; r0 += rows) {
+            long long nr = nrow - r0 < rows ? nrow - r0 : rows;
             // rows r0 .. r0+nr: those of the first time element (row < ng) take
             // the kernel with the singular rules, the others the regular one
             long long nf = r0 < c->ng ? std::min<long long>(nr, c->ng - r0) : 0, nl = nr - nf;
@@ -1248,6 +1384,7 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
         }
         (void)hipStreamSynchronize(s);
         dev_free(c, scratch);
+        if (!rc && c->m0_ksplit < c->nt) rc = m0_power_rows(c, op == STBEM_DM0, o, s);
         return rc;
     }
     }
@@ -1443,6 +1580,7 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
     c->ord = default_orders();
     if ((rc = build_block_lists(c))) { stbem_destroy(c); return rc; }
     c->m0ord.qs_near = 12; c->m0ord.qt_near = 12; c->m0ord.near_ratio = 0.5;
+    c->m0ord.q_tol = c->ord.q_tol; c->m0ord.z_floor = c->ord.z_floor;
     c->m0ord.omax = 0.0;
     for (int t = 0; t < c->ntri; ++t)
         for (int e = 0; e < 3; ++e) {
@@ -1486,6 +1624,11 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
             }
             nn[k] = conv ? n : 0;      // not converged: the E1 path is used
         }
+        // rows whose series covers every pair (amax reached) from ksplit on
+        c->m0_ksplit = c->nt;
+        c->m0_npow = 0;
+        for (int k = c->nt - 1; k >= 1 && nn[k] > 0 && am[k] >= amax; --k) c->m0_ksplit = k;
+        for (int k = c->m0_ksplit; k < c->nt; ++k) c->m0_npow = std::max(c->m0_npow, nn[k]);
         int rc2 = 0;
         if ((rc2 = upload(c, &c->d_m0c, cf)) || (rc2 = upload(c, &c->d_m0cd, cfd)) || (rc2 = upload(c, &c->d_m0n, nn)) ||
             (rc2 = upload(c, &c->d_m0amax, am))) {

@@ -59,53 +59,7 @@ SDEV double m0_smooth0(const Geom& g, double r2, double lnr)
     return DERIV ? (Ez - exp(-z)) * kInv4Pi : g.alpha * kInv4Pi * Ez;
 }
 
-struct Tri {
-    double ax, ay, bx, by, cx, cy;
-    double gx, gy, g0;      // phi_j(y) = g0 + gx y_x + gy y_y
-};
-
-SDEV Tri load_tri(const Mesh2& m, int t, int j)
-{
-    Tri T;
-    int v0 = m.tri[3 * t], v1 = m.tri[3 * t + 1], v2 = m.tri[3 * t + 2];
-    T.ax = m.ox[v0]; T.ay = m.oy[v0]; T.bx = m.ox[v1]; T.by = m.oy[v1]; T.cx = m.ox[v2]; T.cy = m.oy[v2];
-    // hat of vertex j: phi(y) = cross(C' - B', y - B') / cross(B - A, C - A)
-    double px, py, qx, qy;   // B', C': the two other vertices in CCW order after j
-    if (j == v0) { px = T.bx; py = T.by; qx = T.cx; qy = T.cy; }
-    else if (j == v1) { px = T.cx; py = T.cy; qx = T.ax; qy = T.ay; }
-    else { px = T.ax; py = T.ay; qx = T.bx; qy = T.by; }
-    double det = (T.bx - T.ax) * (T.cy - T.ay) - (T.by - T.ay) * (T.cx - T.ax);
-    T.gx = -(qy - py) / det;
-    T.gy = (qx - px) / det;
-    T.g0 = ((qx - px) * (-py) - (qy - py) * (-px)) / det;
-    return T;
-}
-
-// regular rule: qs Gauss points on the segment, qt x qt collapsed Gauss on
-// the triangle; f(r2) * phi_j
-template <class F>
-SDEV double m0_regular(const Tables& T, const Piece& S, const Tri& tr, int qs, int qt, F f)
-{
-    double e1x = tr.bx - tr.ax, e1y = tr.by - tr.ay, e2x = tr.cx - tr.ax, e2y = tr.cy - tr.ay;
-    double area2 = fabs(e1x * e2y - e1y * e2x);
-    double acc = 0.0;
-    for (int a = 0; a < qt; ++a) {
-        double u = T.gl_x[qt][a], wu = T.gl_w[qt][a] * (1.0 - u);
-        for (int b = 0; b < qt; ++b) {
-            double v = T.gl_x[qt][b] * (1.0 - u), w = wu * T.gl_w[qt][b] * area2;
-            double yx = tr.ax + u * e1x + v * e2x, yy = tr.ay + u * e1y + v * e2y;
-            double phi = tr.g0 + tr.gx * yx + tr.gy * yy;
-            double inner = 0.0;
-            for (int c = 0; c < qs; ++c) {
-                double s = S.len * T.gl_x[qs][c];
-                double dx = S.ax + s * S.ex - yx, dy = S.ay + s * S.ey - yy;
-                inner += T.gl_w[qs][c] * f(dx * dx + dy * dy);
-            }
-            acc += w * phi * inner;
-        }
-    }
-    return acc * S.len;
-}
+struct Tri { double ax, ay, bx, by, cx, cy; };   // vertices only (distance tests)
 
 // u ln(u^2 + d^2) - 2u + 2 d atan(u/d), and (1/2)[(u^2+d^2) ln(u^2+d^2) - u^2]
 SDEV double logU(double u, double d)
@@ -118,61 +72,6 @@ SDEV double logW(double u, double d)
 {
     double q = u * u + d * d;
     return 0.5 * ((q > 0.0 ? q * log(q) : 0.0) - u * u);
-}
-
-// int_omega phi_j(y) ln|x - y| dy in closed form: sum over the CCW edges
-// (p, p + E) of the signed sub-triangles (x, p, p + E) in polar form
-SDEV double log_potential(const Tri& tr, double x, double y)
-{
-    const double vx[3] = {tr.ax, tr.bx, tr.cx}, vy[3] = {tr.ay, tr.by, tr.cy};
-    double phx = tr.g0 + tr.gx * x + tr.gy * y;
-    double acc = 0.0;
-    for (int e = 0; e < 3; ++e) {
-        int f = e == 2 ? 0 : e + 1;
-        double Px = vx[e] - x, Py = vy[e] - y, Ex = vx[f] - vx[e], Ey = vy[f] - vy[e];
-        double J = Px * Ey - Py * Ex;
-        double E2 = Ex * Ex + Ey * Ey;
-        if (fabs(J) <= 1e-14 * E2) continue;
-        double tau0 = -(Px * Ex + Py * Ey) / E2;
-        double del = fabs(J) / E2;
-        double dU = logU(1.0 - tau0, del) - logU(-tau0, del);
-        double dW = logW(1.0 - tau0, del) - logW(-tau0, del);
-        double lE = log(E2);
-        double I0 = 0.5 * lE + 0.5 * dU;
-        double I1 = 0.25 * lE + 0.5 * (dW + tau0 * dU);
-        double g0 = tr.gx * Px + tr.gy * Py, g1 = tr.gx * Ex + tr.gy * Ey;
-        acc += J * (-0.25 * phx - (g0 + 0.5 * g1) / 9.0 + (0.5 * phx + g0 / 3.0) * I0 + g1 * I1 / 3.0);
-    }
-    return acc;
-}
-
-// int_{gamma_i} log_potential ds: tanh-sinh on the pieces of the segment
-// between the projections of the triangle vertices
-SDEV double seg_log_potential(const M0Tables& D, const Piece& S, const Tri& tr)
-{
-    double cuts[5];
-    int nc = 0;
-    cuts[nc++] = 0.0;
-    const double vx[3] = {tr.ax, tr.bx, tr.cx}, vy[3] = {tr.ay, tr.by, tr.cy};
-    for (int v = 0; v < 3; ++v) {
-        double s = (vx[v] - S.ax) * S.ex + (vy[v] - S.ay) * S.ey;
-        if (s > 1e-12 * S.len && s < S.len * (1.0 - 1e-12)) cuts[nc++] = s;
-    }
-    cuts[nc++] = S.len;
-    for (int a = 1; a < nc; ++a)
-        for (int b = a; b > 0 && cuts[b] < cuts[b - 1]; --b) { double t = cuts[b]; cuts[b] = cuts[b - 1]; cuts[b - 1] = t; }
-    double acc = 0.0;
-    for (int p = 0; p + 1 < nc; ++p) {
-        double s0 = cuts[p], h = cuts[p + 1] - cuts[p];
-        if (h <= 0.0) continue;
-        double part = 0.0;
-        for (int q = 0; q < D.nde; ++q) {
-            double s = s0 + h * D.de_x[q];
-            part += D.de_w[q] * log_potential(tr, S.ax + s * S.ex, S.ay + s * S.ey);
-        }
-        acc += h * part;
-    }
-    return acc;
 }
 
 SDEV double seg_tri_dist(const Piece& S, const Tri& tr)
@@ -193,7 +92,7 @@ SDEV double seg_tri_dist(const Piece& S, const Tri& tr)
     return sqrt(d2);
 }
 
-struct M0Orders { int qs_near, qt_near; double near_ratio, omax; };
+struct M0Orders { int qs_near, qt_near; double near_ratio, omax, q_tol, z_floor; };
 
 // For k >= 1, with z = a/t, E1(a/t_{k+1}) - E1(a/t_k) = ln(t_{k+1}/t_k)
 // + Ein(a/t_{k+1}) - Ein(a/t_k) is a power series in a; when a/t_k stays
@@ -208,52 +107,6 @@ SDEV double m0_poly(const double* c, int n, double a)
     for (int q = n - 2; q >= 0; --q) p = p * a + c[q];
     return p;
 }
-
-// one entry M0[(k,i), j] (or its alpha-derivative)
-template <bool DERIV>
-SDEV double m0_entry(const Tables& T, const M0Tables& D, const M0Orders& MO, const Geom& g,
-                     const Mesh2& m, int k, int i, int j, int qs, int qt, const M0Poly& PP)
-{
-    Piece S = seg_piece(g, i);
-    double acc = 0.0;
-    if (k > 0 && PP.n[k] > 0) {
-        const double* c = (DERIV ? PP.cd : PP.c) + (long long)k * kPolyMax;
-        const int n = PP.n[k];
-        const double scale = (DERIV ? 1.0 : g.alpha) * kInv4Pi, q4 = 0.25 * g.alpha;
-        for (int p = m.v2t_ptr[j]; p < m.v2t_ptr[j + 1]; ++p) {
-            Tri tr = load_tri(m, m.v2t[p], j);
-            acc += m0_regular(T, S, tr, qs, qt, [&](double r2) { return m0_poly(c, n, q4 * r2); });
-        }
-        return scale * acc;
-    }
-    for (int p = m.v2t_ptr[j]; p < m.v2t_ptr[j + 1]; ++p) {
-        Tri tr = load_tri(m, m.v2t[p], j);
-        if (k == 0) {
-            double dx1 = tr.bx - tr.ax, dy1 = tr.by - tr.ay, dx2 = tr.cx - tr.ax, dy2 = tr.cy - tr.ay;
-            double diam = sqrt(fmax(fmax(dx1 * dx1 + dy1 * dy1, dx2 * dx2 + dy2 * dy2),
-                                    (dx2 - dx1) * (dx2 - dx1) + (dy2 - dy1) * (dy2 - dy1)));
-            double size = fmax(diam, S.len);
-            double eta = seg_tri_dist(S, tr) / size;
-            if (eta < MO.near_ratio) {
-                // touching or close: exact split S(r^2) - B ln r
-                double sm = m0_regular(T, S, tr, MO.qs_near, MO.qt_near,
-                                       [&](double r2) { return m0_smooth0<DERIV>(g, r2, 0.5 * log(r2)); });
-                double B = DERIV ? kInv2Pi : g.alpha * kInv2Pi;
-                acc += sm - B * seg_log_potential(D, S, tr);
-                continue;
-            }
-            // the log singularity sits at relative distance eta: Gauss order
-            // for a branch point at that distance (error ~ rho(eta)^(-2q))
-            int qn = eta >= 2.0 ? 8 : (eta >= 1.0 ? 12 : kMaxGL);
-            int q0s = qs > qn ? qs : qn, q0t = qt > qn ? qt : qn;
-            acc += m0_regular(T, S, tr, q0s, q0t, [&](double r2) { return m0_kernel<DERIV>(g, k, r2); });
-            continue;
-        }
-        acc += m0_regular(T, S, tr, qs, qt, [&](double r2) { return m0_kernel<DERIV>(g, k, r2); });
-    }
-    return acc;
-}
-
 
 // ------------------------------------------------ per-triangle moments
 // All three barycentric hats of a triangle from one set of kernel values.
@@ -382,8 +235,13 @@ SDEV void m0_tri_moments(const Tables& T, const M0Tables& D, const M0Orders& MO,
             for (int v = 0; v < 3; ++v) out[v] = sm[v] - B * lg[v];
             return;
         }
-        int qn = eta >= 2.0 ? 8 : (eta >= 1.0 ? 12 : kMaxGL);
-        int q0 = qs > qn ? qs : qn;
+        // ln r singularity at distance eta * size; the factor e^{-z},
+        // z = alpha r^2 / (4 t_1), changes by dz along the elements
+        int qn = eta < 1.0 ? kMaxGL : eta < 2.0 ? 12 : eta < 4.0 ? 8 : eta < 8.0 ? 6 : eta < 16.0 ? 5 : 4;
+        const double w2 = 0.25 * g.alpha / g.t[1], rlo = eta * size;
+        const int qz = q_slope(w2 * rlo * rlo, w2 * size * (2.0 * rlo + size), MO.q_tol, MO.z_floor);
+        int q0 = qn > qz ? qn : qz;
+        q0 = q0 > qs ? q0 : qs;
         m0_regular3(T, S, tr, q0, q0, [&](double r2) { return m0_kernel<DERIV>(g, 0, r2); }, out);
         return;
     }

@@ -441,14 +441,9 @@ SDEV void rule_vertex(const Tables& T, const Piece& P, const Piece& Q, int rel, 
 // c_q dz^{2q} e^{dz}, c_q = (q!)^4 / ((2q+1) ((2q)!)^3); pairs whose factor
 // is below e^{-z_floor} (of the block maximum, attained at r = 0) need that
 // bound only relative to e^{-z_floor}.
-SDEV int q_touch(const Orders& O, const TimeBlock& tb, const Piece& P, const Piece& Q, double eta, int qinc)
+SDEV int q_slope(double zlo, double dz, double q_tol, double z_floor)
 {
-    int qe = O.q_near[kNearClasses - 1];
-    for (int c = kNearClasses - 2; c >= 0; --c)
-        if (eta < O.eta_cut[c]) qe = O.q_near[c];
-    const double L = P.len > Q.len ? P.len : Q.len, rlo = eta * L;
-    const double zlo = tb.w2 * rlo * rlo, dz = tb.w2 * L * (2.0 * rlo + L);
-    const double lim = O.q_tol * exp(-dz) * (zlo > O.z_floor ? exp(zlo - O.z_floor) : 1.0);
+    const double lim = q_tol * exp(-dz) * (zlo > z_floor ? exp(zlo - z_floor) : 1.0);
     const double dz2 = dz * dz;
     double c = 1.0 / 24.0, pw = dz2;   // c_1, dz^2
     int q = 1;
@@ -458,7 +453,17 @@ SDEV int q_touch(const Orders& O, const TimeBlock& tb, const Piece& P, const Pie
         pw *= dz2;
         ++q;
     }
-    q += qinc;
+    return q;
+}
+
+SDEV int q_touch(const Orders& O, const TimeBlock& tb, const Piece& P, const Piece& Q, double eta, int qinc)
+{
+    int qe = O.q_near[kNearClasses - 1];
+    for (int c = kNearClasses - 2; c >= 0; --c)
+        if (eta < O.eta_cut[c]) qe = O.q_near[c];
+    const double L = P.len > Q.len ? P.len : Q.len, rlo = eta * L;
+    const double zlo = tb.w2 * rlo * rlo, dz = tb.w2 * L * (2.0 * rlo + L);
+    int q = q_slope(zlo, dz, O.q_tol, O.z_floor) + qinc;
     q = q < 3 ? 3 : q;
     q = q > qe ? q : qe;
     return q > kMaxGL ? kMaxGL : q;
