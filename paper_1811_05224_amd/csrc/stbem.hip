@@ -1590,8 +1590,10 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
         }
     {
         // M0 rows k >= 1: power series of ln(t1/t0) + Ein(a/t1) - Ein(a/t0) in
-        // a = alpha r^2 / 4, usable when a/t0 <= 2 for every pair (r <= R,
-        // the diameter of the bounding box of Gamma_h and Omega_h)
+        // a = alpha r^2 / 4, used for pairs with a/t0 <= 4 (the alternating
+        // terms reach at most 4^4/4! = 10.7 times the leading one while the sum
+        // is >= e^{-4} of it: < 1e-13 relative rounding); R = the diameter of
+        // the bounding box of Gamma_h and Omega_h bounds r
         double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
         for (int v = 0; v < c->ng; ++v) { xmin = std::fmin(xmin, c->vx[v]); xmax = std::fmax(xmax, c->vx[v]); ymin = std::fmin(ymin, c->vy[v]); ymax = std::fmax(ymax, c->vy[v]); }
         for (int v = 0; v < c->nv; ++v) { xmin = std::fmin(xmin, c->ox[v]); xmax = std::fmax(xmax, c->ox[v]); ymin = std::fmin(ymin, c->oy[v]); ymax = std::fmax(ymax, c->oy[v]); }
@@ -1602,7 +1604,7 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
         std::vector<double> am(c->nt, 0.0);
         for (int k = 1; k < c->nt; ++k) {
             long double t0 = c->t[k], t1 = c->t[k + 1], h = (long double)c->t[k + 1] - (long double)c->t[k];
-            double amk = std::fmin(2.0 * c->t[k], amax);   // the series is used for a <= amk
+            double amk = std::fmin(4.0 * c->t[k], amax);   // the series is used for a <= amk
             am[k] = amk;
             double* co = &cf[(size_t)k * kPolyMax];
             double* cd = &cfd[(size_t)k * kPolyMax];

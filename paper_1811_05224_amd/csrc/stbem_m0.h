@@ -96,9 +96,9 @@ struct M0Orders { int qs_near, qt_near; double near_ratio, omax, q_tol, z_floor;
 
 // For k >= 1, with z = a/t, E1(a/t_{k+1}) - E1(a/t_k) = ln(t_{k+1}/t_k)
 // + Ein(a/t_{k+1}) - Ein(a/t_k) is a power series in a; when a/t_k stays
-// <= 2 (a <= amax[k]) it is evaluated from precomputed coefficients
+// <= 4 (a <= amax[k]) it is evaluated from precomputed coefficients
 // (row-wise table, Horner); farther pairs use E1 directly.  DERIV adds -(e^{-a/t_{k+1}} - e^{-a/t_k}).
-constexpr int kPolyMax = 30;
+constexpr int kPolyMax = 40;
 struct M0Poly { const double* c; const double* cd; const int* n; const double* amax; };   // [nt][kPolyMax], [nt], [nt]
 
 SDEV double m0_poly(const double* c, int n, double a)
