@@ -42,26 +42,57 @@ __device__ __forceinline__ void block_of(long long b, int& k, int& m)
     m = (int)(b - kk * (kk + 1) / 2);
 }
 
-enum Store { ST_F64 = 0, ST_F32 = 1, ST_HILO = 2 };
+// V_h, dV_h/dalpha and D_h blocks are symmetric in space (the kernel of a
+// block (k, m) is symmetric in x and y), so only the tiles (ti, tj) with
+// ti <= tj are launched and an off-diagonal tile also stores its transpose.
+constexpr bool sym_op(int op) { return op == OP_V || op == OP_DV || op == OP_D; }
 
-template <int OP, int ST>
+inline long long tiles_per_block(int t1, bool sym) { return sym ? (long long)t1 * (t1 + 1) / 2 : (long long)t1 * t1; }
+
+// tile number -> (ti, tj): row-major over all tiles, or over the upper triangle
+__device__ __forceinline__ void tile_of(int tile, int t1, bool sym, int& ti, int& tj)
+{
+    if (!sym) { ti = tile / t1; tj = tile % t1; return; }
+    int r = 0, n = t1;
+    while (tile >= n) { tile -= n; ++r; --n; }
+    ti = r; tj = r + tile;
+}
+
+// Store the tile value of lane (il, jl) (entry (I0+il, J0+jl) of the block at
+// boff) and, for an off-diagonal tile of a symmetric operator, the transposed
+// tile, staged through LDS so that both stores are row-contiguous.  Every
+// lane of the workgroup must call it.
+__device__ __forceinline__ void store_tile(double (*stage)[kTile + 1], bool sym, double v, bool live, long long boff,
+                                          int ng, int I0, int J0, int il, int jl, double* __restrict__ out)
+{
+    if (live) out[boff + (long long)(I0 + il) * ng + J0 + jl] = v;
+    if (!sym || I0 == J0) return;
+    stage[il][jl] = v;
+    __syncthreads();
+    const int r = J0 + il, col = I0 + jl;
+    if (r < ng && col < ng) out[boff + (long long)r * ng + col] = stage[jl][il];
+}
+
+template <int OP>
 __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restrict__ Tg, Orders O,
                                                   double lmax, const int* __restrict__ blist, int tiles_1d,
-                                                  double* __restrict__ out64, float* __restrict__ hi,
-                                                  float* __restrict__ lo)
+                                                  double* __restrict__ out64)
 {
+    constexpr bool SYM = sym_op(OP);
     __shared__ Tables T;
     __shared__ TimeBlock tb;
     __shared__ int qf;
+    __shared__ double stage[kTile][kTile + 1];
     const int tid = threadIdx.x;
     {
         const double* src = reinterpret_cast<const double*>(Tg);
         double* dst = reinterpret_cast<double*>(&T);
         for (int e = tid; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
     }
-    const long long tiles = (long long)tiles_1d * tiles_1d;
+    const long long tiles = SYM ? (long long)tiles_1d * (tiles_1d + 1) / 2 : (long long)tiles_1d * tiles_1d;
     const long long b = blist[blockIdx.x / tiles];
-    const int tile = (int)(blockIdx.x % tiles);
+    int ti, tj;
+    tile_of((int)(blockIdx.x % tiles), tiles_1d, SYM, ti, tj);
     int k, m;
     block_of(b, k, m);
     if (tid == 0) {
@@ -69,17 +100,11 @@ __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restri
         qf = q_block(OP, lmax, block_min_lag(g.t, k, m), g.alpha);
     }
     __syncthreads();
-    const int i = (tile / tiles_1d) * kTile + tid / kTile;
-    const int j = (tile % tiles_1d) * kTile + tid % kTile;
-    if (i >= g.ng || j >= g.ng) return;
-    double v = entry<OP>(T, O, g, tb, qf, i, j);
-    const long long off = b * (long long)g.ng * g.ng + (long long)i * g.ng + j;
-    if (ST == ST_F64) out64[off] = v;
-    else {
-        float h = (float)v;
-        hi[off] = h;
-        if (ST == ST_HILO) lo[off] = (float)(v - (double)h);
-    }
+    const int il = tid / kTile, jl = tid % kTile, I0 = ti * kTile, J0 = tj * kTile;
+    const int i = I0 + il, j = J0 + jl;
+    const bool live = i < g.ng && j < g.ng;
+    double v = live ? entry<OP>(T, O, g, tb, qf, i, j) : 0.0;
+    store_tile(stage, SYM, v, live, b * (long long)g.ng * g.ng, g.ng, I0, J0, il, jl, out64);
 }
 
 // V_h and K_h on separated time elements (series), Gauss order Q fixed at
@@ -140,12 +165,16 @@ __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __
                                                         const int* __restrict__ blist, int tiles_i, int tiles_j,
                                                         double* __restrict__ out64)
 {
+    constexpr bool SYM = OP == OP_V;
     __shared__ Tables T;
     __shared__ TimeBlock tb;
+    __shared__ double stage[kTile][kTile + 1];
     const int tid = threadIdx.x;
-    const long long tiles = (long long)tiles_i * tiles_j;
+    const long long tiles = SYM ? (long long)tiles_i * (tiles_i + 1) / 2 : (long long)tiles_i * tiles_j;
     const long long b = blist[blockIdx.x / tiles];
-    const int tile = (int)(blockIdx.x % tiles);
+    int ti, tj;
+    if (SYM) tile_of((int)(blockIdx.x % tiles), tiles_i, true, ti, tj);
+    else { const int tile = (int)(blockIdx.x % tiles); ti = tile / tiles_j; tj = tile % tiles_j; }
     int k, m;
     block_of(b, k, m);
     if (tid == 0) time_block(g, k, m, tb);
@@ -156,10 +185,10 @@ __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __
     }
     __syncthreads();
     const int ty = tid / kTile, tx = tid % kTile;
-    const int i = (tile / tiles_j) * kTile + ty;
+    const int i = ti * kTile + ty;
     // V: column j = J0 + tx.  K: the tile covers segments J0-1 .. J0+14 and
     // writes the 15 hats J0 .. J0+14 (hat j = rising part on j-1 + falling on j)
-    const int J0 = (tile % tiles_j) * (OP == OP_K ? kTile - 1 : kTile);
+    const int J0 = tj * (OP == OP_K ? kTile - 1 : kTile);
     int jseg = OP == OP_K ? J0 - 1 + tx : J0 + tx;
     jseg = jseg < 0 ? jseg + g.ng : (jseg >= g.ng ? jseg - g.ng : jseg);
     double m0 = 0.0, m1 = 0.0;
@@ -171,7 +200,7 @@ __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __
     }
     const long long rowoff = b * (long long)g.ng * g.ng + (long long)i * g.ng;
     if (OP == OP_V) {
-        if (live) out64[rowoff + J0 + tx] = m0;
+        store_tile(stage, true, m0, live, b * (long long)g.ng * g.ng, g.ng, ti * kTile, J0, ty, tx, out64);
     } else {
         // lanes of one tile row are consecutive: the rising moment of segment
         // j - 1 sits in the lane to the left
@@ -252,18 +281,20 @@ __device__ __forceinline__ void far_dpair(const Tables& T, const TimeBlock& tb, 
 
 
 template <int Q>
-__global__ __launch_bounds__(kWG) void k_assemble_dfar(Geom g, const Tables* __restrict__ Tg, double lmax,
+__global__ __launch_bounds__(kWG) void k_assemble_dfar(Geom g, const Tables* __restrict__ Tg,
                                                        const int* __restrict__ blist, int tiles_1d,
-                                                       double* __restrict__ out64, float* __restrict__ out32)
+                                                       double* __restrict__ out64)
 {
     __shared__ Tables T;
     __shared__ TimeBlock tb;
     __shared__ double mom[kDP][kDP][4];
     __shared__ double pc[2][kDP][7];       // ax ay ex ey len nx ny
+    __shared__ double stage[kTile][kTile + 1];
     const int tid = threadIdx.x;
-    const long long tiles = (long long)tiles_1d * tiles_1d;
+    const long long tiles = (long long)tiles_1d * (tiles_1d + 1) / 2;
     const long long b = blist[blockIdx.x / tiles];
-    const int tile = (int)(blockIdx.x % tiles);
+    int ti, tj;
+    tile_of((int)(blockIdx.x % tiles), tiles_1d, true, ti, tj);
     int k, m;
     block_of(b, k, m);
     if (tid == 0) time_block(g, k, m, tb);
@@ -272,7 +303,7 @@ __global__ __launch_bounds__(kWG) void k_assemble_dfar(Geom g, const Tables* __r
         double* dst = reinterpret_cast<double*>(&T);
         for (int e = tid; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
     }
-    const int I0 = (tile / tiles_1d) * kTile, J0 = (tile % tiles_1d) * kTile;
+    const int I0 = ti * kTile, J0 = tj * kTile;
     const int np = 2 * g.ng;
     if (tid < 2 * kDP) {
         int side = tid / kDP, u = tid % kDP;
@@ -288,24 +319,24 @@ __global__ __launch_bounds__(kWG) void k_assemble_dfar(Geom g, const Tables* __r
         far_dpair<Q>(T, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v]);
     }
     __syncthreads();
-    const int i = I0 + tid / kTile, j = J0 + tid % kTile;
-    if (i >= g.ng || j >= g.ng) return;
-    DualSupport si = dual_support(g, i), sj = dual_support(g, j);
-    const int ui = 2 * (i - I0), vj = 2 * (j - J0);
+    const int il = tid / kTile, jl = tid % kTile, i = I0 + il, j = J0 + jl;
+    const bool live = i < g.ng && j < g.ng;
     double acc = 0.0;
+    if (live) {
+        DualSupport si = dual_support(g, i), sj = dual_support(g, j);
+        const int ui = 2 * il, vj = 2 * jl;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const double a0 = si.v0[u], a1 = si.v0[u] + si.slope[u] * pc[0][ui + u][4];
+        for (int u = 0; u < 4; ++u) {
+            const double a0 = si.v0[u], a1 = si.v0[u] + si.slope[u] * pc[0][ui + u][4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const double b0 = sj.v0[v], b1 = sj.v0[v] + sj.slope[v] * pc[1][vj + v][4];
-            const double* M = mom[ui + u][vj + v];
-            acc += a0 * (b0 * M[0] + b1 * M[1]) + a1 * (b0 * M[2] + b1 * M[3]);
+            for (int v = 0; v < 4; ++v) {
+                const double b0 = sj.v0[v], b1 = sj.v0[v] + sj.slope[v] * pc[1][vj + v][4];
+                const double* M = mom[ui + u][vj + v];
+                acc += a0 * (b0 * M[0] + b1 * M[1]) + a1 * (b0 * M[2] + b1 * M[3]);
+            }
         }
     }
-    const long long off = b * (long long)g.ng * g.ng + (long long)i * g.ng + j;
-    if (out64) out64[off] = acc;
-    else out32[off] = (float)acc;
+    store_tile(stage, true, acc, live, b * (long long)g.ng * g.ng, g.ng, I0, J0, il, jl, out64);
 }
 
 // D_h on touching time elements (d <= 1, closed form in time): one workgroup
@@ -327,10 +358,12 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
     __shared__ unsigned char form[kTile][kTile];   // 0 by-parts, 1 raw, 2 outside the matrix
     __shared__ short list[kDP * kDP];              // pairs to compute, costly ones first
     __shared__ int nlist[2];
+    __shared__ double stage[kTile][kTile + 1];
     const int tid = threadIdx.x;
-    const long long tiles = (long long)tiles_1d * tiles_1d;
+    const long long tiles = (long long)tiles_1d * (tiles_1d + 1) / 2;
     const long long b = blist[blockIdx.x / tiles];
-    const int tile = (int)(blockIdx.x % tiles);
+    int ti, tj;
+    tile_of((int)(blockIdx.x % tiles), tiles_1d, true, ti, tj);
     int k, m;
     block_of(b, k, m);
     if (tid == 0) time_block(g, k, m, tb);
@@ -339,7 +372,7 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
         double* dst = reinterpret_cast<double*>(&T);
         for (int e = tid; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
     }
-    const int I0 = (tile / tiles_1d) * kTile, J0 = (tile % tiles_1d) * kTile;
+    const int I0 = ti * kTile, J0 = tj * kTile;
     const int np = 2 * g.ng;
     if (tid < 2 * kDP) {
         const int side = tid / kDP, u = tid % kDP;
@@ -370,7 +403,7 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
     };
     DualSupport si, sj;
     if (inside) { si = dual_support(g, i); sj = dual_support(g, j); }
-    const long long off = b * (long long)g.ng * g.ng + (long long)i * g.ng + j;
+    double val = 0.0;
 
     // Pairs a pass needs, compacted so that no lane idles on unneeded pairs;
     // for the by-parts pass the singular pairs (many more nodes) go first so
@@ -417,35 +450,37 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
                 acc += a0 * (b0 * M[0] + b1 * M[1]) + a1 * (b0 * M[2] + b1 * M[3]);
             }
         }
-        out64[off] = acc;
+        val = acc;
     }
-    if (!any_bp) return;
-    __syncthreads();
+    if (any_bp) {
+        __syncthreads();
 
-    // pass 2: by-parts entries (curl part psi'_P psi'_Q m0 + the normal part)
-    {
-        const int n = build_list(0);
-        for (int e = tid; e < n; e += kWG) {
-            const int u = list[e] / kDP, v = list[e] % kDP;
-            d_pair_bp(T, O, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v]);
-        }
-    }
-    __syncthreads();
-    if (my == 0) {
-        double acc = 0.0;
-        for (int u = 0; u < 4; ++u) {
-            double a0, a1;
-            hat(si, u, pc[0][ui + u].len, a0, a1);
-            for (int v = 0; v < 4; ++v) {
-                double b0, b1;
-                hat(sj, v, pc[1][vj + v].len, b0, b1);
-                const double* M = mom[ui + u][vj + v];
-                acc += si.slope[u] * sj.slope[v] * M[0]
-                     + a0 * (b0 * M[1] + b1 * M[2]) + a1 * (b0 * M[3] + b1 * M[4]);
+        // pass 2: by-parts entries (curl part psi'_P psi'_Q m0 + the normal part)
+        {
+            const int n = build_list(0);
+            for (int e = tid; e < n; e += kWG) {
+                const int u = list[e] / kDP, v = list[e] % kDP;
+                d_pair_bp(T, O, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v]);
             }
         }
-        out64[off] = acc;
+        __syncthreads();
+        if (my == 0) {
+            double acc = 0.0;
+            for (int u = 0; u < 4; ++u) {
+                double a0, a1;
+                hat(si, u, pc[0][ui + u].len, a0, a1);
+                for (int v = 0; v < 4; ++v) {
+                    double b0, b1;
+                    hat(sj, v, pc[1][vj + v].len, b0, b1);
+                    const double* M = mom[ui + u][vj + v];
+                    acc += si.slope[u] * sj.slope[v] * M[0]
+                         + a0 * (b0 * M[1] + b1 * M[2]) + a1 * (b0 * M[3] + b1 * M[4]);
+                }
+            }
+            val = acc;
+        }
     }
+    store_tile(stage, true, val, inside, b * (long long)g.ng * g.ng, g.ng, I0, J0, il, jl, out64);
 }
 
 template <int OP>
@@ -1162,24 +1197,19 @@ inline int blocks_per_launch(long long tiles)
 }
 
 template <int OP>
-int launch_assemble(stbem_ctx* c, int store, double* o64, float* hi, float* lo, hipStream_t s)
+int launch_assemble(stbem_ctx* c, double* o64, hipStream_t s)
 {
     const int slot = OP == OP_V ? 0 : OP == OP_K ? 1 : OP == OP_D ? 2 : OP == OP_DV ? 4 : 5;
     int t1 = (c->ng + kTile - 1) / kTile;
-    const long long tiles = (long long)t1 * t1;
+    const long long tiles = tiles_per_block(t1, sym_op(OP));
     Geom g = geom(c);
     const int step = blocks_per_launch(tiles);
     for (int off = 0; off < c->nlist_gen[slot]; off += step) {
         const int cnt = std::min(step, c->nlist_gen[slot] - off);
         const int* bl = c->d_blist[slot] + c->nlist_touch[slot] + off;
         dim3 gr((unsigned)(cnt * tiles)), blk(kWG);
-        KTimer kt(c, kname("k_assemble", OP, store).c_str(), (double)cnt * g.ng * g.ng, s);
-        if (store == ST_F64)
-            hipLaunchKernelGGL((k_assemble<OP, ST_F64>), gr, blk, 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64, hi, lo);
-        else if (store == ST_F32)
-            hipLaunchKernelGGL((k_assemble<OP, ST_F32>), gr, blk, 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64, hi, lo);
-        else
-            hipLaunchKernelGGL((k_assemble<OP, ST_HILO>), gr, blk, 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64, hi, lo);
+        KTimer kt(c, kname("k_assemble", OP).c_str(), (double)cnt * g.ng * g.ng, s);
+        hipLaunchKernelGGL((k_assemble<OP>), gr, blk, 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64);
     }
     HIPCHK(c, hipGetLastError());
     return 0;
@@ -1190,7 +1220,7 @@ void launch_vkfar(stbem_ctx* c, int slot, const int* bl, int cnt, double* o, hip
 {
     int ti = (c->ng + kTile - 1) / kTile;
     int tj = OP == OP_V ? ti : (c->ng + kTile - 2) / (kTile - 1);
-    const long long tiles = (long long)ti * tj;
+    const long long tiles = OP == OP_V ? tiles_per_block(ti, true) : (long long)ti * tj;
     const int step = blocks_per_launch(tiles);
     for (int off = 0; off < cnt; off += step) {
         const int n = std::min(step, cnt - off);
@@ -1308,14 +1338,13 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
     switch (op) {
     case STBEM_V:
     case STBEM_K: {
-        int rc = op == STBEM_V ? launch_assemble<OP_V>(c, ST_F64, o, nullptr, nullptr, s)
-                               : launch_assemble<OP_K>(c, ST_F64, o, nullptr, nullptr, s);
+        int rc = op == STBEM_V ? launch_assemble<OP_V>(c, o, s) : launch_assemble<OP_K>(c, o, s);
         if (rc) return rc;
         return op == STBEM_V ? launch_far<OP_V>(c, 0, o, s) : launch_far<OP_K>(c, 1, o, s);
     }
     case STBEM_D: {
         int t1 = (c->ng + kTile - 1) / kTile;
-        const long long tiles = (long long)t1 * t1;
+        const long long tiles = tiles_per_block(t1, true);
         const int step = blocks_per_launch(tiles);
         for (int off = 0; off < c->nlist_touch[2]; off += step) {
             const int n = std::min(step, c->nlist_touch[2] - off);
@@ -1323,7 +1352,7 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
             hipLaunchKernelGGL(k_assemble_dnear, dim3((unsigned)(n * tiles)), dim3(kWG), 0, s, geom(c), c->d_tab, c->ord,
                                (const int*)(c->d_blist[2] + off), t1, o);
         }
-        int rc = launch_assemble<OP_D>(c, ST_F64, o, nullptr, nullptr, s);
+        int rc = launch_assemble<OP_D>(c, o, s);
         if (rc) return rc;
         const int* bl = c->d_blist[2] + c->nlist_touch[2] + c->nlist_gen[2];
         for (int q = 3; q <= 8; ++q) {
@@ -1333,12 +1362,12 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
                 const int* b2 = bl + off;
                 KTimer kt(c, kname("k_assemble_dfar", q).c_str(), (double)n * c->ng * c->ng, s);
                 switch (q) {
-                case 3: hipLaunchKernelGGL(k_assemble_dfar<3>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, b2, t1, o, (float*)nullptr); break;
-                case 4: hipLaunchKernelGGL(k_assemble_dfar<4>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, b2, t1, o, (float*)nullptr); break;
-                case 5: hipLaunchKernelGGL(k_assemble_dfar<5>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, b2, t1, o, (float*)nullptr); break;
-                case 6: hipLaunchKernelGGL(k_assemble_dfar<6>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, b2, t1, o, (float*)nullptr); break;
-                case 7: hipLaunchKernelGGL(k_assemble_dfar<7>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, b2, t1, o, (float*)nullptr); break;
-                default: hipLaunchKernelGGL(k_assemble_dfar<8>, gr, blk, 0, s, geom(c), c->d_tab, c->lmax, b2, t1, o, (float*)nullptr); break;
+                case 3: hipLaunchKernelGGL(k_assemble_dfar<3>, gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o); break;
+                case 4: hipLaunchKernelGGL(k_assemble_dfar<4>, gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o); break;
+                case 5: hipLaunchKernelGGL(k_assemble_dfar<5>, gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o); break;
+                case 6: hipLaunchKernelGGL(k_assemble_dfar<6>, gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o); break;
+                case 7: hipLaunchKernelGGL(k_assemble_dfar<7>, gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o); break;
+                default: hipLaunchKernelGGL(k_assemble_dfar<8>, gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o); break;
                 }
             }
             bl += c->nlist_far[2][q];
@@ -1346,8 +1375,8 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
         HIPCHK(c, hipGetLastError());
         return 0;
     }
-    case STBEM_DV: return launch_assemble<OP_DV>(c, ST_F64, o, nullptr, nullptr, s);
-    case STBEM_DK: return launch_assemble<OP_DK>(c, ST_F64, o, nullptr, nullptr, s);
+    case STBEM_DV: return launch_assemble<OP_DV>(c, o, s);
+    case STBEM_DK: return launch_assemble<OP_DK>(c, o, s);
     case STBEM_M0:
     case STBEM_DM0: {
         // rows in chunks whose moment scratch stays below 1 GiB
