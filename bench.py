@@ -145,6 +145,7 @@ def main():
 
     roof = roofline(ktimes)
     kernel_ms = {k: round(v[1] / args.steps, 3) for k, v in sorted(ktimes.items(), key=lambda kv: -kv[1][1])}
+    kernel_units = {k: v[2] / v[0] for k, v in ktimes.items()}
 
     out = {
         "metric": METRIC, "value": value, "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
@@ -163,6 +164,7 @@ def main():
         "gemv_V": {"ms": gemv_ms, "GB/s": gemv_gbs, "frac_hbm": gemv_gbs / HBM_PEAK_GBS},
         "roofline": roof,
         "kernel_ms_per_step": kernel_ms,
+        "kernel_units_per_launch": kernel_units,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample)

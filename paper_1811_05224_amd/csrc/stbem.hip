@@ -210,6 +210,50 @@ __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __
     }
 }
 
+// K_h (and dK_h/dalpha) on touching time elements: like the far K tiles, a
+// lane integrates one segment pair (row segment i, column segment J0-1+tx)
+// once, with the rules for touching elements, for both trial shapes; hat j
+// takes the rising moment of segment j-1 from the lane to its left.  Per hat
+// this is one segment pair instead of two.
+template <int OP>
+__global__ __launch_bounds__(kWG) void k_assemble_knear(Geom g, const Tables* __restrict__ Tg, Orders O,
+                                                        const int* __restrict__ blist, int tiles_i, int tiles_j,
+                                                        double* __restrict__ out64)
+{
+    __shared__ Tables T;
+    __shared__ TimeBlock tb;
+    const int tid = threadIdx.x;
+    const long long tiles = (long long)tiles_i * tiles_j;
+    const long long b = blist[blockIdx.x / tiles];
+    const int tile = (int)(blockIdx.x % tiles);
+    int k, m;
+    block_of(b, k, m);
+    if (tid == 0) time_block(g, k, m, tb);
+    {
+        const double* src = reinterpret_cast<const double*>(Tg);
+        double* dst = reinterpret_cast<double*>(&T);
+        for (int e = tid; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
+    }
+    __syncthreads();
+    const int ty = tid / kTile, tx = tid % kTile;
+    const int i = (tile / tiles_j) * kTile + ty;
+    const int J0 = (tile % tiles_j) * (kTile - 1);
+    int jseg = J0 - 1 + tx;
+    jseg = jseg < 0 ? jseg + g.ng : (jseg >= g.ng ? jseg - g.ng : jseg);
+    double m0 = 0.0, m1 = 0.0;
+    if (i < g.ng) {
+        const Piece P = seg_piece(g, i), Q = seg_piece(g, jseg);
+        if (relation(P, Q) != 1) {          // coincident: (x-y).n = 0
+            KernK<OP == OP_DK> kf(tb, g.alpha, Q);
+            pair_integral(T, O, tb, 0, q_inc(OP), P, Q, kf);
+            m0 = kf.acc0; m1 = kf.acc1;
+        }
+    }
+    const double left = __shfl_up(m1, 1, kTile);
+    const int j = J0 + tx - 1;
+    if (tx >= 1 && i < g.ng && j < g.ng) out64[b * (long long)g.ng * g.ng + (long long)i * g.ng + j] = left + m0;
+}
+
 // D_h on separated time elements (series), one 16 x 16 tile of dual
 // functions per workgroup.  The 2*16+2 half-segment pieces that carry the
 // tile's rows (and columns) are paired once: each pair gets its four shape
@@ -1215,6 +1259,20 @@ int launch_assemble(stbem_ctx* c, double* o64, hipStream_t s)
     return 0;
 }
 
+template <int OP>
+void launch_knear(stbem_ctx* c, int slot, double* o, hipStream_t s)
+{
+    const int ti = (c->ng + kTile - 1) / kTile, tj = (c->ng + kTile - 2) / (kTile - 1);
+    const long long tiles = (long long)ti * tj;
+    const int step = blocks_per_launch(tiles);
+    for (int off = 0; off < c->nlist_touch[slot]; off += step) {
+        const int n = std::min(step, c->nlist_touch[slot] - off);
+        KTimer kt(c, kname("k_assemble_knear", OP).c_str(), (double)n * c->ng * c->ng, s);
+        hipLaunchKernelGGL((k_assemble_knear<OP>), dim3((unsigned)(n * tiles)), dim3(kWG), 0, s, geom(c), c->d_tab, c->ord,
+                           (const int*)(c->d_blist[slot] + off), ti, tj, o);
+    }
+}
+
 template <int OP, int Q>
 void launch_vkfar(stbem_ctx* c, int slot, const int* bl, int cnt, double* o, hipStream_t s)
 {
@@ -1262,7 +1320,7 @@ int build_block_lists(stbem_ctx* c)
                 int b = (int)((long long)k * (k + 1) / 2 + m);
                 time_block(g, k, m, tb);
                 int q = q_block(op, c->lmax, block_min_lag(g.t, k, m), g.alpha);
-                if (op == OP_D && tb.d <= 1) touch.push_back(b);
+                if ((op == OP_D || op == OP_K || op == OP_DK) && tb.d <= 1) touch.push_back(b);
                 else if (!tb.ser || op == OP_DV || op == OP_DK) gen.push_back(b);
                 else if (q >= 3 && q <= 8) far[q].push_back(b);
                 else gen.push_back(b);
@@ -1338,6 +1396,7 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
     switch (op) {
     case STBEM_V:
     case STBEM_K: {
+        if (op == STBEM_K) launch_knear<OP_K>(c, 1, o, s);
         int rc = op == STBEM_V ? launch_assemble<OP_V>(c, o, s) : launch_assemble<OP_K>(c, o, s);
         if (rc) return rc;
         return op == STBEM_V ? launch_far<OP_V>(c, 0, o, s) : launch_far<OP_K>(c, 1, o, s);
@@ -1376,7 +1435,7 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
         return 0;
     }
     case STBEM_DV: return launch_assemble<OP_DV>(c, o, s);
-    case STBEM_DK: return launch_assemble<OP_DK>(c, o, s);
+    case STBEM_DK: launch_knear<OP_DK>(c, 5, o, s); return launch_assemble<OP_DK>(c, o, s);
     case STBEM_M0:
     case STBEM_DM0: {
         // rows in chunks whose moment scratch stays below 1 GiB
