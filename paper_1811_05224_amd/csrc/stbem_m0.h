@@ -37,14 +37,19 @@ SDEV double m0_kernel(const Geom& g, int k, double r2)
     double a = 0.25 * g.alpha * r2;
     double t1 = g.t[k + 1], t0 = g.t[k];
     double z1 = a / t1;
+    double x1, x0;
     if (k == 0) {
-        double E = e1(z1);
-        return DERIV ? (E - exp(-z1)) * kInv4Pi : g.alpha * kInv4Pi * E;
+        double E = e1t<DERIV>(z1, x1);
+        return DERIV ? (E - x1) * kInv4Pi : g.alpha * kInv4Pi * E;
     }
     double z0 = a / t0, dE;
-    if (z0 <= 2.0) dE = log(t1 / t0) + ein(z1) - ein(z0);    // no ln a cancellation
-    else dE = e1(z1) - e1(z0);
-    if (DERIV) return (dE - exp(-z1) + exp(-z0)) * kInv4Pi;
+    if (z0 <= 2.0) {
+        dE = log(t1 / t0) + ein(z1) - ein(z0);    // no ln a cancellation
+        if (DERIV) { x1 = exp(-z1); x0 = exp(-z0); }
+    } else {
+        dE = e1t<DERIV>(z1, x1) - e1t<DERIV>(z0, x0);
+    }
+    if (DERIV) return (dE - x1 + x0) * kInv4Pi;
     return g.alpha * kInv4Pi * dE;
 }
 
@@ -53,10 +58,14 @@ template <bool DERIV>
 SDEV double m0_smooth0(const Geom& g, double r2, double lnr)
 {
     double a = 0.25 * g.alpha * r2, t1 = g.t[1], z = a / t1;
-    double Ez;   // E1(z) + 2 ln r
-    if (z <= 2.0) Ez = -kEuler - log(0.25 * g.alpha / t1) + ein(z);
-    else Ez = e1(z) + 2.0 * lnr;
-    return DERIV ? (Ez - exp(-z)) * kInv4Pi : g.alpha * kInv4Pi * Ez;
+    double Ez, ex = 0.0;   // Ez = E1(z) + 2 ln r
+    if (z <= 2.0) {
+        Ez = -kEuler - log(0.25 * g.alpha / t1) + ein(z);
+        if (DERIV) ex = exp(-z);
+    } else {
+        Ez = e1t<DERIV>(z, ex) + 2.0 * lnr;
+    }
+    return DERIV ? (Ez - ex) * kInv4Pi : g.alpha * kInv4Pi * Ez;
 }
 
 struct Tri { double ax, ay, bx, by, cx, cy; };   // vertices only (distance tests)

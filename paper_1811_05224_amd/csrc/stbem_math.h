@@ -78,26 +78,43 @@ struct Orders {
 };
 
 // ------------------------------------------------------------------ E1
-// Ein(z) = sum_{n>=1} (-1)^{n+1} z^n/(n n!), entire; used for 0 <= z <= 2.
+// Ein(z) = sum_{n>=1} (-1)^{n+1} z^n/(n n!), entire; used for 0 <= z <= 2,
+// where 24 terms leave a tail below 1e-18 of the sum (Horner form).
+struct EinCoef { double c[24]; };
+constexpr EinCoef make_ein_coef()
+{
+    EinCoef r{};
+    double f = 1.0;
+    for (int n = 1; n <= 24; ++n) {
+        f *= n;
+        r.c[n - 1] = ((n & 1) ? 1.0 : -1.0) / (n * f);
+    }
+    return r;
+}
+constexpr EinCoef kEin = make_ein_coef();
+
 SDEV double ein(double z)
 {
-    double term = z, sum = z;
+    double p = kEin.c[23];
 #pragma unroll
-    for (int n = 2; n <= 30; ++n) {
-        term *= z * (-1.0 / n);
-        sum += term * (1.0 / n);
-    }
-    return sum;
+    for (int n = 22; n >= 0; --n) p = p * z + kEin.c[n];
+    return p * z;
 }
 
-// E1(z) for z > 0: -gamma - ln z + Ein(z) for z <= 2; on [2, 64) e^{-z}
-// times a Chebyshev expansion of e^z E1(z) per octave (generated with
-// mpmath, relative error < 2.5e-16); beyond, the continued fraction
-// e^{-z}/(z+1 - 1^2/(z+3 - 2^2/(z+5 - ...))) evaluated from the tail.
-SDEV double e1(double z)
+// E1(z) for z > 0 (and, with EX, ex = e^{-z}): -gamma - ln z + Ein(z) for
+// z <= 2; on [2, 64) e^{-z} times a Chebyshev expansion of e^z E1(z) per
+// octave (generated with mpmath, relative error < 2.5e-16); beyond, the
+// continued fraction e^{-z}/(z+1 - 1^2/(z+3 - 2^2/(z+5 - ...))) evaluated
+// from the tail.  The exponential is shared with the caller.
+template <bool EX>
+SDEV double e1t(double z, double& ex)
 {
-    if (z <= 2.0) return -kEuler - log(z) + ein(z);
-    if (z > 740.0) return 0.0;
+    if (z <= 2.0) {
+        if (EX) ex = exp(-z);
+        return -kEuler - log(z) + ein(z);
+    }
+    if (z > 740.0) { ex = 0.0; return 0.0; }
+    ex = exp(-z);
     if (z < 64.0) {
         int o = z < 4.0 ? 0 : z < 8.0 ? 1 : z < 16.0 ? 2 : z < 32.0 ? 3 : 4;
         double lo = (double)(2 << o), x = (z - 1.5 * lo) / (0.5 * lo);
@@ -107,20 +124,27 @@ SDEV double e1(double z)
             double t = 2.0 * x * b1 - b2 + co[n];
             b2 = b1; b1 = t;
         }
-        return exp(-z) * (x * b1 - b2 + co[0]);
+        return ex * (x * b1 - b2 + co[0]);
     }
     double tail = 0.0;
     for (int n = 6; n >= 1; --n) tail = (double)n * n / (z + 2.0 * n + 1.0 - tail);
-    return exp(-z) / (z + 1.0 - tail);
+    return ex / (z + 1.0 - tail);
+}
+
+SDEV double e1x(double z, double& ex) { return e1t<true>(z, ex); }
+SDEV double e1(double z)
+{
+    double ex;
+    return e1t<false>(z, ex);
 }
 
 // E1(a/d) + 2 ln r written without ln a when a/d is small:
 //   E1(a/d) = -gamma - ln(alpha/4) + ln d - 2 ln r + Ein(a/d)
 // so ez(...) - 2 ln r = E1.  For large a/d it is E1 + 2 ln r directly.
-SDEV double ez_part(double z, double c0, double lnd, double lnr)
+SDEV double ez_part(double z, double c0, double lnd, double lnr, double& ex)
 {
-    if (z <= 2.0) return c0 + lnd + ein(z);
-    return e1(z) + 2.0 * lnr;
+    if (z <= 2.0) { ex = exp(-z); return c0 + lnd + ein(z); }
+    return e1x(z, ex) + 2.0 * lnr;
 }
 
 // ------------------------------------------------------------ time blocks
@@ -158,6 +182,7 @@ SDEV void time_block(const Geom& g, int k, int m, TimeBlock& tb)
         tb.del[0] = hk + hm; tb.sgn[0] = 1.0;
         tb.del[1] = hk;      tb.sgn[1] = -1.0;
         tb.del[2] = hm;      tb.sgn[2] = -1.0;
+        if (hk == hm) { tb.ndel = 2; tb.sgn[1] = -2.0; }   // equal steps: one term
     } else {
         tb.ndel = 0;
         double A = 0.5 * hk, B = 0.5 * hm;
@@ -238,8 +263,8 @@ SDEV TouchVals touch(const TimeBlock& tb, double a, double alpha)
 {
     TouchVals r = {0, 0, 0, 0, 0};
     for (int s = 0; s < tb.ndel; ++s) {
-        double d = tb.del[s], z = a / d;
-        double E = e1(z), x = exp(-z), sg = tb.sgn[s];
+        double d = tb.del[s], z = a / d, x;
+        double E = e1x(z, x), sg = tb.sgn[s];
         if (NEED_V) r.v += sg * ((d + a) * E - d * x);
         if (NEED_K) r.k += sg * (d * x - a * E);
         if (NEED_D || NEED_E) r.e += sg * E;
@@ -260,7 +285,7 @@ SDEV TouchH touch_h(const TimeBlock& tb, double a)
     double ia = 1.0 / a;
     for (int s = 0; s < tb.ndel; ++s) {
         double d = tb.del[s], z = a / d, sg = tb.sgn[s];
-        double E = e1(z), x = d * exp(-z) * ia;
+        double ez, E = e1x(z, ez), x = d * ez * ia;
         r.dd += sg * E;
         r.va += sg * (E - x);
         r.vaa += sg * x * ia;
@@ -281,7 +306,7 @@ SDEV SplitVals touch_split(const TimeBlock& tb, double a, double lnr, double alp
     double ssum = 0.0;                          // sum of signs: 1 (d=0) or -1 (d=1)
     for (int s = 0; s < tb.ndel; ++s) {
         double d = tb.del[s], z = a / d, sg = tb.sgn[s];
-        double Ez = ez_part(z, c0, tb.lnd[s], lnr), x = exp(-z);
+        double x, Ez = ez_part(z, c0, tb.lnd[s], lnr, x);
         ssum += sg;
         if (NEED_V) r.v.a += sg * ((d + a) * Ez - d * x);
         if (NEED_K) r.k.a += sg * (d * x - a * Ez);
