@@ -689,9 +689,6 @@ __global__ __launch_bounds__(kWG) void k_m0_pow_apply(int ng, int nv, int nt, in
 }
 
 // ---------------------------------------------------------------- GEMV
-template <class T>
-__device__ __forceinline__ double ld(const T* p, long long o) { return (double)p[o]; }
-
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -699,113 +696,14 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// partial[b][i] = sum_j A_b[i][j] x_m[j]: 4 waves x 4 rows per workgroup
-template <class T>
-__global__ __launch_bounds__(kWG) void k_gemv_n_part(const T* __restrict__ A, const T* __restrict__ A2,
-                                                     const double* __restrict__ x, double* __restrict__ part,
-                                                     int ng, int rowchunks)
-{
-    const long long b = blockIdx.x / rowchunks;
-    const int rc = (int)(blockIdx.x % rowchunks);
-    int k, m;
-    block_of(b, k, m);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const long long base = b * (long long)ng * ng;
-    const double* xm = x + (long long)m * ng;
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-        const int i = rc * 16 + wave * 4 + rr;
-        if (i >= ng) break;
-        const long long ro = base + (long long)i * ng;
-        double s = 0.0;
-        for (int j = lane; j < ng; j += 64) {
-            double a = ld(A, ro + j);
-            if (A2) a += ld(A2, ro + j);
-            s += a * xm[j];
-        }
-        s = wave_sum(s);
-        if (lane == 0) part[b * ng + i] = s;
-    }
-}
-
-// partial[b][j] = sum_i A_b[i][j] x_k[i]: 64 columns x 4 row groups
-template <class T>
-__global__ __launch_bounds__(kWG) void k_gemv_t_part(const T* __restrict__ A, const T* __restrict__ A2,
-                                                     const double* __restrict__ x, double* __restrict__ part,
-                                                     int ng, int colchunks)
-{
-    __shared__ double red[4][64];
-    const long long b = blockIdx.x / colchunks;
-    const int cc = (int)(blockIdx.x % colchunks);
-    int k, m;
-    block_of(b, k, m);
-    const int grp = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int j = cc * 64 + lane;
-    const long long base = b * (long long)ng * ng;
-    const double* xk = x + (long long)k * ng;
-    double s = 0.0;
-    if (j < ng)
-        for (int i = grp; i < ng; i += 4) {
-            double a = ld(A, base + (long long)i * ng + j);
-            if (A2) a += ld(A2, base + (long long)i * ng + j);
-            s += a * xk[i];
-        }
-    red[grp][lane] = s;
-    __syncthreads();
-    if (grp == 0 && j < ng) part[b * ng + j] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
-}
-
-// FP32 storage, FP32 accumulation (inner solves of the refinement)
-__global__ __launch_bounds__(kWG) void k_gemv_n_part32(const float* __restrict__ A, const double* __restrict__ x,
-                                                       double* __restrict__ part, int ng, int rowchunks)
-{
-    const long long b = blockIdx.x / rowchunks;
-    const int rc = (int)(blockIdx.x % rowchunks);
-    int k, m;
-    block_of(b, k, m);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const long long base = b * (long long)ng * ng;
-    const double* xm = x + (long long)m * ng;
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-        const int i = rc * 16 + wave * 4 + rr;
-        if (i >= ng) break;
-        const long long ro = base + (long long)i * ng;
-        float s = 0.0f;
-        for (int j = lane; j < ng; j += 64) s += A[ro + j] * (float)xm[j];
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
-        if (lane == 0) part[b * ng + i] = (double)s;
-    }
-}
-
-__global__ __launch_bounds__(kWG) void k_gemv_t_part32(const float* __restrict__ A, const double* __restrict__ x,
-                                                       double* __restrict__ part, int ng, int colchunks)
-{
-    __shared__ float red[4][64];
-    const long long b = blockIdx.x / colchunks;
-    const int cc = (int)(blockIdx.x % colchunks);
-    int k, m;
-    block_of(b, k, m);
-    const int grp = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int j = cc * 64 + lane;
-    const long long base = b * (long long)ng * ng;
-    const double* xk = x + (long long)k * ng;
-    float s = 0.0f;
-    if (j < ng)
-        for (int i = grp; i < ng; i += 4) s += A[base + (long long)i * ng + j] * (float)xk[i];
-    red[grp][lane] = s;
-    __syncthreads();
-    if (grp == 0 && j < ng) part[b * ng + j] = (double)(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
-}
-
-// Vectorised block products: VW consecutive entries per lane load.
-// T: storage type; ACC: accumulation type; HILO: A + A2 (float pair).
+// vector loads of VW consecutive elements
 template <class T, int VW>
 struct VecLd {
     typedef T type __attribute__((ext_vector_type(VW)));
 };
 
+// partial[b][i] = sum_j A_b[i][j] x_m[j]: 4 waves x 4 rows per workgroup,
+// VW-wide loads (FP64 pair, hi+lo float pair, or FP32), ACC accumulation
 template <class T, int VW, class ACC, bool HILO>
 __global__ __launch_bounds__(kWG) void k_gemv_n_vec(const T* __restrict__ A, const T* __restrict__ A2,
                                                     const double* __restrict__ x, double* __restrict__ part,

@@ -79,26 +79,16 @@ struct Orders {
 
 // ------------------------------------------------------------------ E1
 // Ein(z) = sum_{n>=1} (-1)^{n+1} z^n/(n n!), entire; used for 0 <= z <= 2,
-// where 24 terms leave a tail below 1e-18 of the sum (Horner form).
-struct EinCoef { double c[24]; };
-constexpr EinCoef make_ein_coef()
-{
-    EinCoef r{};
-    double f = 1.0;
-    for (int n = 1; n <= 24; ++n) {
-        f *= n;
-        r.c[n - 1] = ((n & 1) ? 1.0 : -1.0) / (n * f);
-    }
-    return r;
-}
-constexpr EinCoef kEin = make_ein_coef();
-
+// where 24 terms leave a tail below 1e-18 of the sum.
 SDEV double ein(double z)
 {
-    double p = kEin.c[23];
+    double term = z, sum = z;
 #pragma unroll
-    for (int n = 22; n >= 0; --n) p = p * z + kEin.c[n];
-    return p * z;
+    for (int n = 2; n <= 24; ++n) {
+        term *= z * (-1.0 / n);
+        sum += term * (1.0 / n);
+    }
+    return sum;
 }
 
 // E1(z) for z > 0 (and, with EX, ex = e^{-z}): -gamma - ln z + Ein(z) for

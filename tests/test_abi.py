@@ -71,3 +71,13 @@ def test_no_cpu_fallback_without_gpu():
     import workloads as W
     with pytest.raises(P.StbemError):
         P.Context.from_workload(W.make("custom"))
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libstbem.so not built")
+def test_null_context_rejected():
+    """Entry points given no context return STBEM_EINVAL without touching a device."""
+    from paper_1811_05224_amd import _lib as L
+    lib = L.load()
+    assert lib.stbem_set_timing(None, 1) == -1
+    assert lib.stbem_kernel_times(None, None, 0) == -1
+    assert lib.stbem_destroy(None) == 0

@@ -53,6 +53,40 @@ def test_assembly_small_all_entries(small, op):
     assert e.max() <= TOL[op]
 
 
+def test_symmetric_blocks_stored_exactly_symmetric(small):
+    """V_h, dV_h/dalpha and D_h blocks are symmetric in space; the kernels
+    compute the tiles on and above the block diagonal and store the mirror,
+    so every stored block equals its transpose bit for bit (K_h is not
+    symmetric and is not mirrored)."""
+    wl, o, c, L = small
+    for code in (L.V, L.DV, L.D):
+        P = c.packed(code).cpu().numpy()
+        assert np.array_equal(P, np.transpose(P, (0, 2, 1)))
+    Kp = c.packed(L.K).cpu().numpy()
+    assert not np.array_equal(Kp, np.transpose(Kp, (0, 2, 1)))
+
+
+def test_launch_timing_records(small):
+    """The launch timing of the library reports every assembly kernel of a
+    V_h + D_h + K_h assembly with its work units (matrix entries of the
+    blocks it processed) and a positive event time; switching it off drops
+    the records."""
+    wl, o, c, L = small
+    c.set_timing(True)
+    c.assemble(L.V | L.K | L.D)
+    rec = c.kernel_times()
+    c.set_timing(False)
+    assert c.kernel_times() == {}
+    entries = c.packed_entries
+    by_op = {"V": ("k_assemble<0>", "k_assemble_vkfar<0,"), "K": ("k_assemble_knear<1>", "k_assemble<1>", "k_assemble_vkfar<1,"),
+             "D": ("k_assemble_dnear", "k_assemble<2>", "k_assemble_dfar<")}
+    for op, prefixes in by_op.items():
+        units = sum(u for name, (n, ms, u) in rec.items() if name.startswith(prefixes))
+        assert units == entries, (op, units, entries)
+    for name, (n, ms, u) in rec.items():
+        assert n >= 1 and ms > 0.0 and u > 0, name
+
+
 @pytest.mark.parametrize("deriv", [False, True])
 def test_m0_small_all_entries(small, deriv):
     wl, o, c, L = small
