@@ -59,19 +59,32 @@ __device__ __forceinline__ void tile_of(int tile, int t1, bool sym, int& ti, int
 }
 
 // Store the tile value of lane (il, jl) (entry (I0+il, J0+jl) of the block at
-// boff) and, for an off-diagonal tile of a symmetric operator, the transposed
-// tile, staged through LDS so that both stores are row-contiguous.  Every
-// lane of the workgroup must call it.
+// boff).  For a symmetric operator an off-diagonal tile also stores its
+// transposed tile, and a diagonal tile stores the values of its upper half
+// (il <= jl) in both halves, staged through LDS so that the stores are
+// row-contiguous and the stored blocks are exactly symmetric.  Every lane of
+// the workgroup must call it.
 __device__ __forceinline__ void store_tile(double (*stage)[kTile + 1], bool sym, double v, bool live, long long boff,
                                           int ng, int I0, int J0, int il, int jl, double* __restrict__ out)
 {
-    if (live) out[boff + (long long)(I0 + il) * ng + J0 + jl] = v;
-    if (!sym || I0 == J0) return;
+    if (!sym) {
+        if (live) out[boff + (long long)(I0 + il) * ng + J0 + jl] = v;
+        return;
+    }
     stage[il][jl] = v;
     __syncthreads();
+    if (I0 == J0) {
+        if (live) out[boff + (long long)(I0 + il) * ng + J0 + jl] = il <= jl ? v : stage[jl][il];
+        return;
+    }
+    if (live) out[boff + (long long)(I0 + il) * ng + J0 + jl] = v;
     const int r = J0 + il, col = I0 + jl;
     if (r < ng && col < ng) out[boff + (long long)r * ng + col] = stage[jl][il];
 }
+
+// lanes whose value a symmetric tile takes from the mirror: the lower half
+// of a diagonal tile
+__device__ __forceinline__ bool mirrored(bool sym, int I0, int J0, int il, int jl) { return sym && I0 == J0 && il > jl; }
 
 template <int OP>
 __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restrict__ Tg, Orders O,
@@ -103,7 +116,7 @@ __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restri
     const int il = tid / kTile, jl = tid % kTile, I0 = ti * kTile, J0 = tj * kTile;
     const int i = I0 + il, j = J0 + jl;
     const bool live = i < g.ng && j < g.ng;
-    double v = live ? entry<OP>(T, O, g, tb, qf, i, j) : 0.0;
+    double v = live && !mirrored(SYM, I0, J0, il, jl) ? entry<OP>(T, O, g, tb, qf, i, j) : 0.0;
     store_tile(stage, SYM, v, live, b * (long long)g.ng * g.ng, g.ng, I0, J0, il, jl, out64);
 }
 
@@ -193,7 +206,7 @@ __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __
     jseg = jseg < 0 ? jseg + g.ng : (jseg >= g.ng ? jseg - g.ng : jseg);
     double m0 = 0.0, m1 = 0.0;
     const bool live = i < g.ng && (OP == OP_K || J0 + tx < g.ng);
-    if (live) {
+    if (live && !mirrored(SYM, ti * kTile, J0, ty, tx)) {
         const double P[5] = {g.vx[i], g.vy[i], g.ex[i], g.ey[i], g.len[i]};
         const double Qs[5] = {g.vx[jseg], g.vy[jseg], g.ex[jseg], g.ey[jseg], g.len[jseg]};
         far_pair<Q, OP == OP_V>(T, tb, g.alpha, P, Qs, g.ey[jseg], -g.ex[jseg], m0, m1);
@@ -366,7 +379,7 @@ __global__ __launch_bounds__(kWG) void k_assemble_dfar(Geom g, const Tables* __r
     const int il = tid / kTile, jl = tid % kTile, i = I0 + il, j = J0 + jl;
     const bool live = i < g.ng && j < g.ng;
     double acc = 0.0;
-    if (live) {
+    if (live && !mirrored(true, I0, J0, il, jl)) {
         DualSupport si = dual_support(g, i), sj = dual_support(g, j);
         const int ui = 2 * il, vj = 2 * jl;
 #pragma unroll
@@ -482,7 +495,8 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
         }
     }
     __syncthreads();
-    if (my == 1) {
+    const bool mir = mirrored(true, I0, J0, il, jl);
+    if (my == 1 && !mir) {
         double acc = 0.0;
         for (int u = 0; u < 4; ++u) {
             double a0, a1;
@@ -508,7 +522,7 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
             }
         }
         __syncthreads();
-        if (my == 0) {
+        if (my == 0 && !mir) {
             double acc = 0.0;
             for (int u = 0; u < 4; ++u) {
                 double a0, a1;
