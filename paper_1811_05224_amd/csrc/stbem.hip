@@ -572,10 +572,6 @@ __global__ __launch_bounds__(kWG) void k_m0_tri(Geom g, Mesh2 mesh, const Tables
 {
     __shared__ Tables T;
     __shared__ M0Tables D;
-    __shared__ double coef[kPolyMax];         // the row's power-series coefficients
-    const long long lrow = lrow0 + blockIdx.x / nchunk;       // row within the chunk
-    const long long row = row0 + lrow;          // row = k * ng + i, one row per workgroup
-    const int k = (int)(row / g.ng), i = (int)(row % g.ng);
     {
         const double* src = reinterpret_cast<const double*>(Tg);
         double* dst = reinterpret_cast<double*>(&T);
@@ -583,11 +579,13 @@ __global__ __launch_bounds__(kWG) void k_m0_tri(Geom g, Mesh2 mesh, const Tables
         const double* s2 = reinterpret_cast<const double*>(Dg);
         double* d2 = reinterpret_cast<double*>(&D);
         for (int e = threadIdx.x; e < (int)(sizeof(M0Tables) / sizeof(double)); e += kWG) d2[e] = s2[e];
-        if (!FIRST && threadIdx.x < kPolyMax) coef[threadIdx.x] = (DERIV ? PP.cd : PP.c)[(long long)k * kPolyMax + threadIdx.x];
     }
     __syncthreads();
+    const long long lrow = lrow0 + blockIdx.x / nchunk;       // row within the chunk
     const int t = (int)(blockIdx.x % nchunk) * kWG + threadIdx.x;
     if (t >= mesh.ntri) return;
+    const long long row = row0 + lrow;          // row = k * ng + i
+    const int k = (int)(row / g.ng), i = (int)(row % g.ng);
     // k >= 1: the kernel varies on the time scale sqrt(4 t_k / alpha); k = 0:
     // the order follows the distance of the triangle (m0_tri_moments)
     int qs = 3;
@@ -596,7 +594,7 @@ __global__ __launch_bounds__(kWG) void k_m0_tri(Geom g, Mesh2 mesh, const Tables
         qs = qs < 4 ? 4 : qs;
     }
     double mom[3];
-    m0_tri_moments<DERIV, FIRST>(T, D, MO, g, mesh, PP, k, i, t, qs, mom, FIRST ? nullptr : coef);
+    m0_tri_moments<DERIV, FIRST>(T, D, MO, g, mesh, PP, k, i, t, qs, mom);
     double* o = scratch + (lrow * mesh.ntri + t) * 3;
     o[0] = mom[0]; o[1] = mom[1]; o[2] = mom[2];
 }

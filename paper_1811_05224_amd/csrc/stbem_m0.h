@@ -220,64 +220,11 @@ SDEV void seg_log_potential3(const M0Tables& D, const Piece& S, const Tri3& tr, 
     }
 }
 
-// m0_regular3 for rows k >= 1 with QS points per direction: the QS segment
-// nodes of a triangle node are evaluated together; when all of them lie in
-// the power-series range (a <= amax) the series runs in lockstep over them
-// (QS independent Horner chains, one coefficient read per step), otherwise
-// node by node with E1 beyond amax.  Same arithmetic as the per-node path.
-template <int QS, bool DERIV>
-SDEV void m0_regular3_series(const Tables& T, const Geom& g, int k, const Piece& S, const Tri3& tr,
-                             const double* c, int n, double amax, double* out)
-{
-    const double e1x_ = tr.bx - tr.ax, e1y_ = tr.by - tr.ay, e2x = tr.cx - tr.ax, e2y = tr.cy - tr.ay;
-    const double area2 = fabs(e1x_ * e2y - e1y_ * e2x), q4 = 0.25 * g.alpha, sc = (DERIV ? 1.0 : g.alpha) * kInv4Pi;
-    double o0 = 0.0, o1 = 0.0, o2 = 0.0;
-    for (int a = 0; a < QS; ++a) {
-        const double u = T.gl_x[QS][a], wu = T.gl_w[QS][a] * (1.0 - u);
-        for (int b = 0; b < QS; ++b) {
-            const double v = T.gl_x[QS][b] * (1.0 - u), w = wu * T.gl_w[QS][b] * area2;
-            const double yx = tr.ax + u * e1x_ + v * e2x, yy = tr.ay + u * e1y_ + v * e2y;
-            double aa[QS], r2[QS], f[QS];
-            bool inside = true;
-#pragma unroll
-            for (int cc = 0; cc < QS; ++cc) {
-                const double sx = S.len * T.gl_x[QS][cc];
-                const double dx = S.ax + sx * S.ex - yx, dy = S.ay + sx * S.ey - yy;
-                r2[cc] = dx * dx + dy * dy;
-                aa[cc] = q4 * r2[cc];
-                inside = inside && aa[cc] <= amax;
-            }
-            if (inside) {
-#pragma unroll
-                for (int cc = 0; cc < QS; ++cc) f[cc] = c[n - 1];
-                for (int q = n - 2; q >= 0; --q) {
-                    const double cq = c[q];
-#pragma unroll
-                    for (int cc = 0; cc < QS; ++cc) f[cc] = f[cc] * aa[cc] + cq;
-                }
-#pragma unroll
-                for (int cc = 0; cc < QS; ++cc) f[cc] *= sc;
-            } else {
-#pragma unroll
-                for (int cc = 0; cc < QS; ++cc)
-                    f[cc] = aa[cc] <= amax ? sc * m0_poly(c, n, aa[cc]) : m0_kernel<DERIV>(g, k, r2[cc]);
-            }
-            double inner = 0.0;
-#pragma unroll
-            for (int cc = 0; cc < QS; ++cc) inner += T.gl_w[QS][cc] * f[cc];
-            inner *= w;
-            o0 += (1.0 - u - v) * inner; o1 += u * inner; o2 += v * inner;
-        }
-    }
-    out[0] = o0 * S.len; out[1] = o1 * S.len; out[2] = o2 * S.len;
-}
-
 // the three moments int_{gamma_i} int_omega hat_v G_k ds dy of triangle t;
 // FIRST: rows of the first time element (k = 0, singular kernel), else k >= 1
 template <bool DERIV, bool FIRST>
 SDEV void m0_tri_moments(const Tables& T, const M0Tables& D, const M0Orders& MO, const Geom& g,
-                         const Mesh2& m, const M0Poly& PP, int k, int i, int t, int qs, double* out,
-                         const double* coef = nullptr)
+                         const Mesh2& m, const M0Poly& PP, int k, int i, int t, int qs, double* out)
 {
     Piece S = seg_piece(g, i);
     Tri3 tr = load_tri3(m, t);
@@ -309,15 +256,7 @@ SDEV void m0_tri_moments(const Tables& T, const M0Tables& D, const M0Orders& MO,
     }
     const int n = PP.n[k];
     if (n > 0) {
-        const double* c = coef ? coef : (DERIV ? PP.cd : PP.c) + (long long)k * kPolyMax;
-        switch (qs) {
-        case 4: m0_regular3_series<4, DERIV>(T, g, k, S, tr, c, n, PP.amax[k], out); return;
-        case 5: m0_regular3_series<5, DERIV>(T, g, k, S, tr, c, n, PP.amax[k], out); return;
-        case 6: m0_regular3_series<6, DERIV>(T, g, k, S, tr, c, n, PP.amax[k], out); return;
-        case 7: m0_regular3_series<7, DERIV>(T, g, k, S, tr, c, n, PP.amax[k], out); return;
-        case 8: m0_regular3_series<8, DERIV>(T, g, k, S, tr, c, n, PP.amax[k], out); return;
-        default: break;
-        }
+        const double* c = (DERIV ? PP.cd : PP.c) + (long long)k * kPolyMax;
         const double amax = PP.amax[k], q4 = 0.25 * g.alpha, sc = (DERIV ? 1.0 : g.alpha) * kInv4Pi;
         m0_regular3(T, S, tr, qs, qs, [&](double r2) {
             double a = q4 * r2;
