@@ -110,10 +110,13 @@ struct M0Orders { int qs_near, qt_near; double near_ratio, omax, q_tol, z_floor;
 constexpr int kPolyMax = 40;
 struct M0Poly { const double* c; const double* cd; const int* n; const double* amax; };   // [nt][kPolyMax], [nt], [nt]
 
-SDEV double m0_poly(const double* c, int n, double a)
+// Horner over the full zero-padded coefficient row (leading zeros leave it
+// unchanged), unrolled so that the coefficient loads are issued ahead
+SDEV double m0_poly(const double* c, int, double a)
 {
-    double p = c[n - 1];
-    for (int q = n - 2; q >= 0; --q) p = p * a + c[q];
+    double p = c[kPolyMax - 1];
+#pragma unroll
+    for (int q = kPolyMax - 2; q >= 0; --q) p = p * a + c[q];
     return p;
 }
 

@@ -109,9 +109,14 @@ SDEV double e1t(double z, double& ex)
         int o = z < 4.0 ? 0 : z < 8.0 ? 1 : z < 16.0 ? 2 : z < 32.0 ? 3 : 4;
         double lo = (double)(2 << o), x = (z - 1.5 * lo) / (0.5 * lo);
         const double* co = kE1Cheb[o];
+        // fixed length (shorter octaves are zero-padded, which leaves the
+        // recurrence unchanged), unrolled so that the coefficient loads of
+        // the lane's octave are issued ahead of the recurrence
         double b1 = 0.0, b2 = 0.0;
-        for (int n = kE1ChebN[o] - 1; n >= 1; --n) {
-            double t = 2.0 * x * b1 - b2 + co[n];
+        const double x2 = 2.0 * x;
+#pragma unroll
+        for (int n = kE1ChebMax - 1; n >= 1; --n) {
+            double t = x2 * b1 - b2 + co[n];
             b2 = b1; b1 = t;
         }
         return ex * (x * b1 - b2 + co[0]);
