@@ -716,8 +716,10 @@ struct VecLd {
     typedef T type __attribute__((ext_vector_type(VW)));
 };
 
-// partial[b][i] = sum_j A_b[i][j] x_m[j]: 4 waves x 4 rows per workgroup,
-// VW-wide loads (FP64 pair, hi+lo float pair, or FP32), ACC accumulation
+// partial[b][i] = sum_j A_b[i][j] x_m[j]: 4 waves x kRowsPerWave rows per
+// workgroup, VW-wide loads (FP64 pair, hi+lo float pair, or FP32), ACC
+// accumulation; the rows of a wave keep kRowsPerWave loads per lane in flight
+constexpr int kRowsPerWave = 8;
 template <class T, int VW, class ACC, bool HILO>
 __global__ __launch_bounds__(kWG) void k_gemv_n_vec(const T* __restrict__ A, const T* __restrict__ A2,
                                                     const double* __restrict__ x, double* __restrict__ part,
@@ -732,14 +734,16 @@ __global__ __launch_bounds__(kWG) void k_gemv_n_vec(const T* __restrict__ A, con
     const long long base = b * (long long)ng * ng;
     const double* xm = x + (long long)m * ng;
     const int span = 64 * VW;
-    ACC s[4] = {0, 0, 0, 0};
+    ACC s[kRowsPerWave];
+#pragma unroll
+    for (int rr = 0; rr < kRowsPerWave; ++rr) s[rr] = 0;
     for (int c = lane * VW; c < ng; c += span) {
         ACC xv[VW];
 #pragma unroll
         for (int q = 0; q < VW; ++q) xv[q] = (ACC)xm[c + q];
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int i = rc * 16 + wave * 4 + rr;
+        for (int rr = 0; rr < kRowsPerWave; ++rr) {
+            const int i = (rc * 4 + wave) * kRowsPerWave + rr;
             if (i < ng) {
                 const long long o = base + (long long)i * ng + c;
                 VT a = *reinterpret_cast<const VT*>(A + o);
@@ -755,11 +759,11 @@ __global__ __launch_bounds__(kWG) void k_gemv_n_vec(const T* __restrict__ A, con
         }
     }
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
+    for (int rr = 0; rr < kRowsPerWave; ++rr) {
         ACC v = s[rr];
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-        const int i = rc * 16 + wave * 4 + rr;
+        const int i = (rc * 4 + wave) * kRowsPerWave + rr;
         if (lane == 0 && i < ng) part[b * ng + i] = (double)v;
     }
 }
@@ -1405,7 +1409,7 @@ int packed_apply(stbem_ctx* c, const double* A, const float* hi, const float* lo
                                : (A ? "k_gemv_t_vec<double>" : hi ? "k_gemv_t_vec<float hi+lo>" : "k_gemv_t_vec<float>");
     KTimer kt(c, gname, (double)c->nblk * ng * ng, s);
     if (!trans) {
-        int rowchunks = (ng + 15) / 16;
+        int rowchunks = (ng + 4 * kRowsPerWave - 1) / (4 * kRowsPerWave);
         dim3 gr((unsigned)(c->nblk * rowchunks)), bl(kWG);
         if (A) {
             if (vw64 == 2) hipLaunchKernelGGL((k_gemv_n_vec<double, 2, double, false>), gr, bl, 0, s, A, (const double*)nullptr, x, c->part, ng, rowchunks);
