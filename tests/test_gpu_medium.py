@@ -95,3 +95,22 @@ def test_medium_solution_rows(medium):
             scale = np.abs(vrow) @ np.abs(wn[cols]) + np.abs(krow) @ np.abs(wl.g[cols]) + np.abs(m0row) @ np.abs(wl.u0)
             print("mode", mode, "row", (k, i), "residual/scale", abs(lhs - rhs) / scale)
             assert abs(lhs - rhs) <= 1e-10 * scale
+
+
+def test_medium_bench_tolerances_reach_1e10(medium):
+    """The solve tolerances bench.py times with (FP64 GMRES to a 3e-11
+    preconditioned residual; FP32-stored refinement to a 1e-12 FP64 residual
+    with 1e-6 inner solves) give solutions within 1e-10 (relative l2) of an
+    FP64 solve to 1e-15, whose residual against oracle rows is checked by
+    test_medium_solution_rows."""
+    wl, o, c, L = medium
+    f = c.rhs(wl.g, wl.u0)
+    wref, iref = c.solve(f, tol=1e-15, max_it=800)
+    nr = float(np.linalg.norm(wref.cpu().numpy()))
+    w64, i64 = c.solve(f, tol=3e-11, max_it=400)
+    w32, i32 = c.solve(f, tol=1e-12, max_it=400, mode=L.FP32_IR, inner_tol=1e-6, max_outer=12, ir_tol=1e-12)
+    assert i64.status == 0 and i32.status == 0
+    e64 = float(np.linalg.norm((w64 - wref).cpu().numpy())) / nr
+    e32 = float(np.linalg.norm((w32 - wref).cpu().numpy())) / nr
+    print("FP64", i64.iters, "iterations, error", e64, "; FP32-refined", i32.outer, "outer", i32.iters, "inner, error", e32)
+    assert e64 <= 1e-10 and e32 <= 1e-10
