@@ -1,11 +1,14 @@
 // stbem: HIP kernels for gfx950 and the host runtime behind include/stbem.h.
 //
 // Assembly (VALU-bound): one workgroup = one 16 x 16 tile of one causal
-// block (k, m), k >= m; the upper blocks are never launched.  The quadrature
-// tables and the time-block data (lags, series moments) live in LDS; each lane
-// computes one entry and the lanes of a row store consecutive doubles.
+// block (k, m), k >= m; the upper blocks are never launched, and for the
+// symmetric operators only the tiles on and above the block diagonal.  The
+// quadrature tables and the time-block data (lags, series moments) live in
+// LDS; lanes either compute one entry each or share piece-pair moments in LDS
+// across the entries of the tile, and the lanes of a row store consecutive
+// doubles.
 // GEMV (HBM-bound): pass 1 computes one partial vector per stored block
-// (a wavefront per row for A x, a lane per column for A^T x), pass 2 adds the
+// (8 rows per wavefront for A x, a lane per column for A^T x), pass 2 adds the
 // partials of a block row (or column) in a fixed order, so results are
 // bitwise reproducible.  GMRES keeps the Krylov basis in HBM; the small
 // Hessenberg least-squares problem is solved on the host.
