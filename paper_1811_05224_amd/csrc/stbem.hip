@@ -721,7 +721,8 @@ struct VecLd {
 
 // partial[b][i] = sum_j A_b[i][j] x_m[j]: 4 waves x kRowsPerWave rows per
 // workgroup, VW-wide loads (FP64 pair, hi+lo float pair, or FP32), ACC
-// accumulation; the rows of a wave keep kRowsPerWave loads per lane in flight
+// accumulation; the rows of a wave keep kRowsPerWave loads per lane in flight.
+// The matrix is streamed once per product, so its loads are non-temporal.
 constexpr int kRowsPerWave = 8;
 template <class T, int VW, class ACC, bool HILO>
 __global__ __launch_bounds__(kWG) void k_gemv_n_vec(const T* __restrict__ A, const T* __restrict__ A2,
@@ -749,9 +750,9 @@ __global__ __launch_bounds__(kWG) void k_gemv_n_vec(const T* __restrict__ A, con
             const int i = (rc * 4 + wave) * kRowsPerWave + rr;
             if (i < ng) {
                 const long long o = base + (long long)i * ng + c;
-                VT a = *reinterpret_cast<const VT*>(A + o);
+                VT a = __builtin_nontemporal_load(reinterpret_cast<const VT*>(A + o));
                 if (HILO) {
-                    VT a2 = *reinterpret_cast<const VT*>(A2 + o);
+                    VT a2 = __builtin_nontemporal_load(reinterpret_cast<const VT*>(A2 + o));
 #pragma unroll
                     for (int q = 0; q < VW; ++q) s[rr] += ((ACC)a[q] + (ACC)a2[q]) * xv[q];
                 } else {
@@ -794,9 +795,9 @@ __global__ __launch_bounds__(kWG) void k_gemv_t_vec(const T* __restrict__ A, con
         for (int i = grp; i < ng; i += 4) {
             const long long o = base + (long long)i * ng + j0;
             const ACC xi = (ACC)xk[i];
-            VT a = *reinterpret_cast<const VT*>(A + o);
+            VT a = __builtin_nontemporal_load(reinterpret_cast<const VT*>(A + o));
             if (HILO) {
-                VT a2 = *reinterpret_cast<const VT*>(A2 + o);
+                VT a2 = __builtin_nontemporal_load(reinterpret_cast<const VT*>(A2 + o));
 #pragma unroll
                 for (int q = 0; q < VW; ++q) s[q] += ((ACC)a[q] + (ACC)a2[q]) * xi;
             } else {
