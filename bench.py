@@ -37,7 +37,7 @@ FP64_PEAK_TFLOPS = 78.6
 # A kernel changed after its counters were taken has no entry here.
 FLOP_PER_UNIT = {'k_assemble_dfar<3>': 4899.3,
     'k_assemble_vkfar<1, 4>': 2861.2,
-    'k_assemble_dnear': 36718.7,
+    'k_assemble_dnear': 36715.4,
     'k_m0_tri<false, false>': 22827.6,
     'k_assemble_dfar<4>': 16779.9,
     'k_m0_tri<false, true>': 78802.3,
@@ -50,24 +50,24 @@ FLOP_PER_UNIT = {'k_assemble_dfar<3>': 4899.3,
     'k_m0_pow_gather': 6.0,
     'k_m0_pow_apply': 81.0,
     'k_m0_gather': 6.0}
-HBM_BYTES_PER_UNIT = {'k_assemble_dfar<3>': 8.002,
-    'k_gemv_n_vec<double>': 8.218,
+HBM_BYTES_PER_UNIT = {'k_gemv_n_vec<double>': 8.035,
+    'k_assemble_dfar<3>': 8.002,
     'k_assemble_vkfar<1, 4>': 9.627,
     'k_assemble_dnear': 8.07,
-    'k_m0_tri<false, false>': 24.1,
-    'k_gemv_n_vec<float>': 4.065,
+    'k_m0_tri<false, false>': 24.099,
     'k_assemble_dfar<4>': 8.006,
-    'k_m0_tri<false, true>': 24.494,
+    'k_m0_tri<false, true>': 24.49,
+    'k_gemv_n_vec<float>': 4.035,
     'k_assemble_vkfar<1, 5>': 9.631,
-    'k_assemble<0>': 8.051,
+    'k_assemble<0>': 8.049,
     'k_assemble_knear<1>': 9.659,
     'k_assemble_vkfar<0, 3>': 8.002,
     'k_m0_pow': 888.5,
     'k_assemble_vkfar<0, 4>': 8.006,
-    'k_gemv_n_vec<float hi+lo>': 8.223,
-    'k_m0_pow_gather': 70.196,
-    'k_m0_pow_apply': 10.823,
-    'k_m0_gather': 67.148}
+    'k_gemv_n_vec<float hi+lo>': 8.035,
+    'k_m0_pow_gather': 70.92,
+    'k_m0_pow_apply': 10.821,
+    'k_m0_gather': 67.238}
 # bytes streamed per stored entry by the matrix-vector kernels
 GEMV_BYTES = {"k_gemv_n_vec<double>": 8, "k_gemv_t_vec<double>": 8, "k_gemv_n_vec<float hi+lo>": 8,
               "k_gemv_t_vec<float hi+lo>": 8, "k_gemv_n_vec<float>": 4, "k_gemv_t_vec<float>": 4}
