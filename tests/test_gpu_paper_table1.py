@@ -50,3 +50,34 @@ def test_table1_iteration_counts():
         assert abs(got[lev][1] - ref[lev][2]) <= 0.5 * ref[lev][2]
     errs = [got[l][2] for l in range(2, 8)]
     assert all(b < a for a, b in zip(errs, errs[1:]))        # the flux converges under refinement
+
+
+def test_table2_mesh_D_entries_sampled():
+    """D_h on the 65 536-element mesh of Table 2 (512 segments x 128 steps,
+    alpha = 10), the mesh whose assembly bench.py times against the paper:
+    sampled entries against the oracle with the floor rule (block scale =
+    the oracle's largest |entry| in the sampled row), tolerance 2e-12."""
+    import paper_1811_05224_amd as P
+    from paper_1811_05224_amd import _lib as L
+    from oracle.oracle import Oracle
+    wl = W.paper_level(7)
+    c = P.Context.from_workload(wl)
+    c.assemble(L.D)
+    o = Oracle.from_workload(wl)
+    rng = np.random.default_rng(7)
+    rows = [(0, 0, 5), (1, 0, 300), (1, 1, 0), (60, 59, 128), (127, 127, 511), (127, 0, 77), (90, 40, 256)] + \
+           [(int(k), int(rng.integers(0, k + 1)), int(rng.integers(0, c.ng))) for k in rng.integers(0, c.nt, 3)]
+    import torch
+    Pk = c.packed(L.D)
+    worst = 0.0
+    for (k, m, i) in rows:
+        cols = sorted({(i + s) % c.ng for s in (-3, -2, -1, 0, 1, 2, 3, 64, 128, 255)} | set(int(j) for j in rng.integers(0, c.ng, 6)))
+        full = np.array([(k, m, i, j) for j in range(c.ng)], dtype=np.int32)
+        ref_row = o.entries("D", full)
+        b = k * (k + 1) // 2 + m
+        got = Pk[b, i].cpu().numpy()
+        floor = 1e-8 * np.abs(ref_row).max()
+        e = np.abs(got[cols] - ref_row[cols]) / np.maximum(np.abs(ref_row[cols]), floor)
+        worst = max(worst, float(e.max()))
+        print((k, m, i), "max floor-rule error", e.max())
+    assert worst <= 2e-12
