@@ -129,7 +129,9 @@ int stbem_mass(stbem_ctx* ctx, int trans, const double* x_dev, double* y_dev, vo
 int stbem_precondition(stbem_ctx* ctx, int trans, const double* r_dev, double* z_dev, void* stream);
 
 /* Right-hand side of eq.(4): f = (1/2 M_h + K_h) g - M_h^0 u0.
- * Needs STBEM_K and STBEM_M0 (u0_dev may be NULL: u0 = 0, M_h^0 not needed). */
+ * Needs STBEM_K; u0_dev may be NULL (u0 = 0).  If STBEM_M0 is not assembled,
+ * M_h^0 u0 is computed in row chunks without storing M_h^0 (for meshes where
+ * the N x n_vtx matrix does not fit); the result is the same product. */
 int stbem_rhs(stbem_ctx* ctx, const double* g_dev, const double* u0_dev, double* f_dev, void* stream);
 
 /* FP32 copies for the refinement solve: V_h as a float pair hi + lo
@@ -174,6 +176,19 @@ int stbem_grad_alpha(stbem_ctx* ctx, const double* lambda_dev, const double* w_d
 /* Sampled entries of V/K/D/dV/dK computed directly by the assembly kernels'
  * device code (idx_dev: n quadruples (k, m, i, j) as int32; out_dev: n). */
 int stbem_entries(stbem_ctx* ctx, unsigned op, long long n, const int* idx_dev, double* out_dev, void* stream);
+
+/* Block-Toeplitz storage for uniform time steps (on = 1).  With equal steps
+ * the block (k, m) of V_h, K_h, D_h and their alpha-derivatives depends on
+ * k - m only (the time integrals depend on the lags), so only the N_I blocks
+ * (d, 0), d = 0..N_I-1, are assembled and stored: block d at element offset
+ * d * n_bnd^2, row-major; products are sum over lags of one GEMM each
+ * (rocBLAS).  Returns STBEM_EINVAL if the steps differ by more than 1e-12
+ * relative.  Switching frees the assembled causal operators (and the FP32
+ * copies) after a device synchronisation; they must be assembled again.
+ * The FP32 refinement needs packed storage and is refused in this mode.
+ * stbem_sizes still reports the packed size; stbem_matrix reports the
+ * stored bytes. */
+int stbem_set_toeplitz(stbem_ctx* ctx, int on);
 
 /* Launch timing, for measuring kernels in place.  With on = 1 every launch
  * of the assembly kernels and of the matrix-vector kernels is bracketed by

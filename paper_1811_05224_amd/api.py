@@ -63,6 +63,7 @@ class Context:
         n, ng, nt, nv, packed = ctypes.c_longlong(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_longlong()
         self.lib.stbem_sizes(h, ctypes.byref(n), ctypes.byref(ng), ctypes.byref(nt), ctypes.byref(nv), ctypes.byref(packed))
         self.n, self.ng, self.nt, self.nv, self.packed_entries = n.value, ng.value, nt.value, nv.value, packed.value
+        self.toeplitz = False
 
     @classmethod
     def from_workload(cls, wl, **kw):
@@ -124,7 +125,14 @@ class Context:
         return t[: nb.value].view(torch.float64)
 
     def packed(self, op):
-        return self.matrix(op).view(self.nt * (self.nt + 1) // 2, self.ng, self.ng)
+        """Stored blocks of a causal operator: [k(k+1)/2 + m] packed, or [k - m] in block-Toeplitz mode."""
+        nb = self.nt if self.toeplitz else self.nt * (self.nt + 1) // 2
+        return self.matrix(op).view(nb, self.ng, self.ng)
+
+    def set_toeplitz(self, on=True):
+        """Block-Toeplitz storage (uniform time steps only); frees the assembled causal operators."""
+        self._check(self.lib.stbem_set_toeplitz(self._h, 1 if on else 0), "stbem_set_toeplitz")
+        self.toeplitz = bool(on)
 
     def apply(self, op, x, trans=False, out=None):
         x = self.vec(x)

@@ -13,6 +13,7 @@
 // bitwise reproducible.  GMRES keeps the Krylov basis in HBM; the small
 // Hessenberg least-squares problem is solved on the host.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <cmath>
 #include <cstdarg>
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restri
     const int i = I0 + il, j = J0 + jl;
     const bool live = i < g.ng && j < g.ng;
     double v = live && !mirrored(SYM, I0, J0, il, jl) ? entry<OP>(T, O, g, tb, qf, i, j) : 0.0;
-    store_tile(stage, SYM, v, live, b * (long long)g.ng * g.ng, g.ng, I0, J0, il, jl, out64);
+    store_tile(stage, SYM, v, live, block_slot(g, b, k, m) * g.ng * g.ng, g.ng, I0, J0, il, jl, out64);
 }
 
 // V_h and K_h on separated time elements (series), Gauss order Q fixed at
@@ -214,9 +215,9 @@ __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __
         const double Qs[5] = {g.vx[jseg], g.vy[jseg], g.ex[jseg], g.ey[jseg], g.len[jseg]};
         far_pair<Q, OP == OP_V>(T, tb, g.alpha, P, Qs, g.ey[jseg], -g.ex[jseg], m0, m1);
     }
-    const long long rowoff = b * (long long)g.ng * g.ng + (long long)i * g.ng;
+    const long long boff = block_slot(g, b, k, m) * g.ng * g.ng, rowoff = boff + (long long)i * g.ng;
     if (OP == OP_V) {
-        store_tile(stage, true, m0, live, b * (long long)g.ng * g.ng, g.ng, ti * kTile, J0, ty, tx, out64);
+        store_tile(stage, true, m0, live, boff, g.ng, ti * kTile, J0, ty, tx, out64);
     } else {
         // lanes of one tile row are consecutive: the rising moment of segment
         // j - 1 sits in the lane to the left
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(kWG) void k_assemble_knear(Geom g, const Tables* __
     }
     const double left = __shfl_up(m1, 1, kTile);
     const int j = J0 + tx - 1;
-    if (tx >= 1 && i < g.ng && j < g.ng) out64[b * (long long)g.ng * g.ng + (long long)i * g.ng + j] = left + m0;
+    if (tx >= 1 && i < g.ng && j < g.ng) out64[block_slot(g, b, k, m) * g.ng * g.ng + (long long)i * g.ng + j] = left + m0;
 }
 
 // D_h on separated time elements (series), one 16 x 16 tile of dual
@@ -396,7 +397,7 @@ __global__ __launch_bounds__(kWG) void k_assemble_dfar(Geom g, const Tables* __r
             }
         }
     }
-    store_tile(stage, true, acc, live, b * (long long)g.ng * g.ng, g.ng, I0, J0, il, jl, out64);
+    store_tile(stage, true, acc, live, block_slot(g, b, k, m) * g.ng * g.ng, g.ng, I0, J0, il, jl, out64);
 }
 
 // D_h on touching time elements (d <= 1, closed form in time): one workgroup
@@ -541,7 +542,7 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
             val = acc;
         }
     }
-    store_tile(stage, true, val, inside, b * (long long)g.ng * g.ng, g.ng, I0, J0, il, jl, out64);
+    store_tile(stage, true, val, inside, block_slot(g, b, k, m) * g.ng * g.ng, g.ng, I0, J0, il, jl, out64);
 }
 
 template <int OP>
@@ -1010,6 +1011,9 @@ struct stbem_ctx {
     stbem_free_fn release = nullptr;
     void* user = nullptr;
     std::string err;
+    // block-Toeplitz storage (stbem_set_toeplitz): block (k, m) at lag k - m
+    bool toep = false;
+    rocblas_handle blas = nullptr;
     // launch timing (stbem_set_timing): one event pair per launch
     struct TRec { std::string name; double units; hipEvent_t a, b; };
     bool timing = false;
@@ -1081,6 +1085,7 @@ Geom geom(const stbem_ctx* c)
     Geom g;
     g.ng = c->ng; g.nt = c->nt; g.alpha = c->alpha;
     g.vx = c->d_vx; g.vy = c->d_vy; g.ex = c->d_ex; g.ey = c->d_ey; g.len = c->d_len; g.t = c->d_t;
+    g.toep = c->toep ? 1 : 0;
     return g;
 }
 
@@ -1148,6 +1153,13 @@ std::string kname(const char* base, int a) { return std::string(base) + "<" + st
 std::string kname(const char* base, int a, int b)
 {
     return std::string(base) + "<" + std::to_string(a) + ", " + std::to_string(b) + ">";
+}
+
+// stored entries of a causal operator: packed lower block triangle, or one
+// block per lag in block-Toeplitz mode
+long long causal_entries(const stbem_ctx* c)
+{
+    return c->toep ? (long long)c->nt * c->ng * c->ng : c->packed;
 }
 
 // A dispatch's grid size is counted in work-items in 32 bits: launches over
@@ -1236,7 +1248,7 @@ int build_block_lists(stbem_ctx* c)
         const int op = ops[e], slot = slots[e];
         std::vector<int> touch, gen, far[9];
         for (int k = 0; k < c->nt; ++k)
-            for (int m = 0; m <= k; ++m) {
+            for (int m = 0; m <= (c->toep ? 0 : k); ++m) {
                 int b = (int)((long long)k * (k + 1) / 2 + m);
                 time_block(g, k, m, tb);
                 int q = q_block(op, c->lmax, block_min_lag(g.t, k, m), g.alpha);
@@ -1304,7 +1316,7 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
 {
     int slot = op_slot(op);
     size_t bytes = (op == STBEM_M0 || op == STBEM_DM0) ? (size_t)c->n * c->nv * sizeof(double)
-                                                      : (size_t)c->packed * sizeof(double);
+                                                      : (size_t)causal_entries(c) * sizeof(double);
     if ((op == STBEM_M0 || op == STBEM_DM0) && c->nv == 0) return fail(c, STBEM_EINVAL, "no Omega mesh for M0");
     if (c->mat[slot] && c->mat_bytes[slot] != bytes) { dev_free(c, c->mat[slot]); c->mat[slot] = nullptr; }
     if (!c->mat[slot]) {
@@ -1399,10 +1411,44 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
     return fail(c, STBEM_EINVAL, "unknown operator %u", op);
 }
 
+// y = A x for block-Toeplitz storage A_d = block (m + d, m): with X, Y the
+// N_Gamma x N_I column-major views of x, y (column m = time element m),
+//   Y[:, d:] += A_d X[:, :N_I-d]      (A^T: Y[:, :N_I-d] += A_d^T X[:, d:])
+// for d = 0, 1, ... in this order, one GEMM per lag; A_d is stored
+// row-major, i.e. as A_d^T in column-major terms.
+int toeplitz_apply(stbem_ctx* c, const double* A, int trans, const double* x, double* y, hipStream_t s)
+{
+    if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success) {
+        c->blas = nullptr;
+        return fail(c, STBEM_EHIP, "rocBLAS handle");
+    }
+    if (rocblas_set_stream(c->blas, s) != rocblas_status_success) return fail(c, STBEM_EHIP, "rocBLAS stream");
+    const int ng = c->ng, nt = c->nt;
+    const double one = 1.0, zero = 0.0;
+    KTimer kt(c, trans ? "toeplitz_gemm_t<double>" : "toeplitz_gemm_n<double>", (double)causal_entries(c), s);
+    for (int d = 0; d < nt; ++d) {
+        const double* Ad = A + (long long)d * ng * ng;
+        const int cols = nt - d;
+        rocblas_status st;
+        if (!trans)
+            st = rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, ng, cols, ng, &one, Ad, ng,
+                               x, ng, d == 0 ? &zero : &one, y + (long long)d * ng, ng);
+        else
+            st = rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, ng, cols, ng, &one, Ad, ng,
+                               x + (long long)d * ng, ng, d == 0 ? &zero : &one, y, ng);
+        if (st != rocblas_status_success) return fail(c, STBEM_EHIP, "rocBLAS dgemm (lag %d): status %d", d, (int)st);
+    }
+    return 0;
+}
+
 // y = A x for packed causal storage (FP64, or hi+lo FP32 pair, or FP32)
 int packed_apply(stbem_ctx* c, const double* A, const float* hi, const float* lo, const float* a32, int trans,
                  const double* x, double* y, hipStream_t s)
 {
+    if (c->toep) {
+        if (!A) return fail(c, STBEM_EINVAL, "FP32 products need packed storage (block-Toeplitz mode is FP64 only)");
+        return toeplitz_apply(c, A, trans, x, y, s);
+    }
     int rc = ensure_part(c);
     if (rc) return rc;
     const int ng = c->ng;
@@ -1467,6 +1513,47 @@ int dense_apply(stbem_ctx* c, const double* M, int trans, const double* x, doubl
     }
     HIPCHK(c, hipGetLastError());
     return 0;
+}
+
+// y = M_h^0 u0 without storing M_h^0 (for meshes where the N x M_Omega
+// matrix does not fit): chunks of rows are computed by the per-row moment
+// kernels, gathered into a chunk buffer and applied, in row order.
+int m0_fused_apply(stbem_ctx* c, const double* u0, double* y, hipStream_t s)
+{
+    if (c->nv == 0) return fail(c, STBEM_EINVAL, "no Omega mesh for M0");
+    const long long per_row = (long long)c->ntri * 3 * (long long)sizeof(double) + (long long)c->nv * sizeof(double);
+    long long rows = (1LL << 30) / per_row;
+    rows = rows < 1 ? 1 : (rows > c->n ? c->n : rows);
+    double* scratch = (double*)dev_alloc(c, (size_t)(rows * c->ntri * 3 * sizeof(double)));
+    double* buf = (double*)dev_alloc(c, (size_t)(rows * c->nv * sizeof(double)));
+    if (!scratch || !buf) {
+        dev_free(c, scratch); dev_free(c, buf);
+        return fail(c, STBEM_ENOMEM, "M0 chunk buffers");
+    }
+    const int tchunk = (c->ntri + kWG - 1) / kWG, vchunk = (c->nv + kWG - 1) / kWG;
+    int rc = 0;
+    for (long long r0 = 0; r0 < c->n && !rc; r0 += rows) {
+        const long long nr = std::min(rows, c->n - r0);
+        const long long nf = r0 < c->ng ? std::min<long long>(nr, c->ng - r0) : 0, nl = nr - nf;
+        if (nf > 0) {
+            KTimer kt(c, "k_m0_tri<false, true>", (double)nf * c->ntri, s);
+            hipLaunchKernelGGL((k_m0_tri<false, true>), dim3((unsigned)(nf * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab,
+                               c->d_m0tab, c->m0ord, m0poly(c), r0, 0LL, tchunk, scratch);
+        }
+        if (nl > 0) {
+            KTimer kt(c, "k_m0_tri<false, false>", (double)nl * c->ntri, s);
+            hipLaunchKernelGGL((k_m0_tri<false, false>), dim3((unsigned)(nl * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab,
+                               c->d_m0tab, c->m0ord, m0poly(c), r0, nf, tchunk, scratch);
+        }
+        hipLaunchKernelGGL(k_m0_gather, dim3((unsigned)(nr * vchunk)), dim3(kWG), 0, s, mesh(c), (const int*)c->d_v2t_loc, 0LL,
+                           vchunk, (const double*)scratch, buf);
+        hipLaunchKernelGGL(k_dense_n, dim3((unsigned)((nr + 3) / 4)), dim3(kWG), 0, s, (const double*)buf, u0, y + r0, nr, c->nv);
+        if (hipGetLastError() != hipSuccess) rc = fail(c, STBEM_EHIP, "fused M0 kernels");
+    }
+    (void)hipStreamSynchronize(s);
+    dev_free(c, scratch);
+    dev_free(c, buf);
+    return rc;
 }
 
 // dot products of the nq vectors Q_q (stride ldq) with v, into h_dev[0..nq)
@@ -1660,8 +1747,35 @@ int stbem_destroy(stbem_ctx* c)
     for (void* p : own) if (p) (void)hipFree(p);
     for (int q = 0; q < 7; ++q) if (c->d_blist[q]) (void)hipFree(c->d_blist[q]);
     clear_timing(c);
+    if (c->blas) (void)rocblas_destroy_handle(c->blas);
     delete c;
     return STBEM_OK;
+}
+
+int stbem_set_toeplitz(stbem_ctx* c, int on)
+{
+    if (!c) return STBEM_EINVAL;
+    const bool want = on != 0;
+    if (want) {
+        const double h0 = c->t[1] - c->t[0];
+        for (int k = 1; k < c->nt; ++k)
+            if (std::fabs((c->t[k + 1] - c->t[k]) - h0) > 1e-12 * h0)
+                return fail(c, STBEM_EINVAL, "block-Toeplitz storage needs uniform time steps (step %d differs)", k);
+    }
+    if (want == c->toep) return STBEM_OK;
+    // the storage format changes: drop the causal operators and FP32 copies
+    (void)hipDeviceSynchronize();
+    const int slots[5] = {0, 1, 2, 4, 5};
+    for (int e = 0; e < 5; ++e) {
+        dev_free(c, c->mat[slots[e]]);
+        c->mat[slots[e]] = nullptr;
+        c->mat_bytes[slots[e]] = 0;
+    }
+    dev_free(c, c->v_hi); dev_free(c, c->v_lo); dev_free(c, c->d_32);
+    c->v_hi = c->v_lo = nullptr; c->d_32 = nullptr;
+    c->toep = want;
+    for (int q = 0; q < 7; ++q) if (c->d_blist[q]) { (void)hipFree(c->d_blist[q]); c->d_blist[q] = nullptr; }
+    return build_block_lists(c);
 }
 
 int stbem_set_timing(stbem_ctx* c, int on)
@@ -1808,7 +1922,7 @@ int stbem_rhs(stbem_ctx* c, const double* g, const double* u0, double* f, void* 
 {
     if (!c || !g || !f) return STBEM_EINVAL;
     if (!c->mat[1]) return fail(c, STBEM_ENOTASSEMBLED, "K_h not assembled");
-    if (u0 && !c->mat[3]) return fail(c, STBEM_ENOTASSEMBLED, "M_h^0 not assembled");
+    if (u0 && !c->mat[3] && c->nv == 0) return fail(c, STBEM_EINVAL, "u0 given but no Omega mesh");
     hipStream_t s = S(stream);
     double* tmp = (double*)dev_alloc(c, (size_t)c->n * sizeof(double));
     if (!tmp) return fail(c, STBEM_ENOMEM, "temporary vector");
@@ -1819,7 +1933,8 @@ int stbem_rhs(stbem_ctx* c, const double* g, const double* u0, double* f, void* 
                        (const double*)f);
     if (hipGetLastError() != hipSuccess) { rc = fail(c, STBEM_EHIP, "mass kernel"); goto done; }
     if (u0) {
-        if ((rc = dense_apply(c, c->mat[3], 0, u0, f, s))) goto done;
+        // M0 u0 from the stored matrix, or computed row chunk by row chunk
+        if ((rc = c->mat[3] ? dense_apply(c, c->mat[3], 0, u0, f, s) : m0_fused_apply(c, u0, f, s))) goto done;
         hipLaunchKernelGGL(k_axpby, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, 1.0, (const double*)tmp, -1.0, f);
     } else {
         hipLaunchKernelGGL(k_axpby, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, 1.0, (const double*)tmp, 0.0, f);
@@ -1976,6 +2091,7 @@ int true_relres(stbem_ctx* c, const SolveOp& o64, const double* f, const double*
 int stbem_prepare_ir(stbem_ctx* c, void* stream)
 {
     if (!c) return STBEM_EINVAL;
+    if (c->toep) return fail(c, STBEM_EINVAL, "FP32 refinement needs packed storage (block-Toeplitz mode is FP64 only)");
     if (!c->mat[0] || !c->mat[2]) return fail(c, STBEM_ENOTASSEMBLED, "FP32 storage needs V_h and D_h");
     hipStream_t s = S(stream);
     size_t fb = (size_t)c->packed * sizeof(float);

@@ -62,7 +62,11 @@ struct Geom {
     const double *vx, *vy;          // polygon vertices
     const double *ex, *ey, *len;    // unit tangent and length of segment i = [v_i, v_{i+1}]
     const double* t;                // nt + 1 time nodes
+    int toep;                       // 1: block (k, m) stored at its lag k - m (uniform steps)
 };
+
+// storage slot of block (k, m) with packed index b
+SDEV long long block_slot(const Geom& g, long long b, int k, int m) { return g.toep ? (long long)(k - m) : b; }
 
 // Quadrature orders chosen by the host per problem.
 constexpr int kNearClasses = 6;
