@@ -54,6 +54,7 @@ def lib():
         L.or_destroy.argtypes = [ctypes.c_void_p]
         L.or_entries.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ip, dp, ctypes.c_int]
         L.or_m0_rows.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ip, dp, ctypes.c_int]
+        L.or_potential.argtypes = [ctypes.c_void_p, ctypes.c_long, dp, dp, dp, dp, dp, ctypes.c_int]
         L.or_e1.restype = ctypes.c_double
         L.or_e1.argtypes = [ctypes.c_double]
         L.or_e1l.restype = ctypes.c_longdouble
@@ -150,6 +151,19 @@ class Oracle:
         rc = lib().or_m0_rows(self._h, int(bool(deriv)), rows.shape[0], _ip(rows), _dp(out), self.nthreads)
         if rc:
             raise ValueError(f"or_m0_rows failed ({rc})")
+        return out
+
+    def potential(self, pts, w, g, u0=None) -> np.ndarray:
+        """The three potentials of the representation formula (Sec. 1, eq. (2))
+        at points (x, y, t), t > 0: columns M~0 u0, V~ w, W g (u = c0 + c1 - c2)."""
+        pts = np.ascontiguousarray(np.asarray(pts, dtype=np.float64).reshape(-1, 3))
+        w = np.ascontiguousarray(w, dtype=np.float64); g = np.ascontiguousarray(g, dtype=np.float64)
+        u0a = np.ascontiguousarray(u0, dtype=np.float64) if u0 is not None else None
+        u0p = _dp(u0a) if u0a is not None else None
+        out = np.empty((pts.shape[0], 3), dtype=np.float64)
+        rc = lib().or_potential(self._h, pts.shape[0], _dp(pts), _dp(w), _dp(g), u0p, _dp(out), self.nthreads)
+        if rc:
+            raise ValueError(f"or_potential failed ({rc})")
         return out
 
     def m0(self, deriv: bool = False) -> np.ndarray:

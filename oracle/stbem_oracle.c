@@ -767,6 +767,102 @@ static void m0_triangle(const Prob* p, int k, int i, int t, int deriv, R* out)
     }
 }
 
+/* ------------------------------------------- representation formula
+ * u(x,t) = (M~0 u0)(x,t) + (V~ w)(x,t) - (W g)(x,t)     (Sec. 1, eq. (2))
+ * with the potentials of the discrete data, at points (x, t) of Q:
+ *   V~ w = sum_{m,j} w_mj int_{gamma_j} int_{tau_m, tau < t} k(x-y, t-tau)
+ *   W g  = sum_{m,n} g_mn int hat_n(y) int_{tau_m, tau < t} d_ny k(x-y, t-tau)
+ *   M~0 u0 = int_Omega U*(x-y, t) u0_h(y) dy
+ * k = U^* / alpha.  In the lag s = t - tau (s from s_lo = max(t - t_{m+1}, 0)
+ * to s_hi = t - t_m), with a = alpha r^2/4, the time integrals are the
+ * definitions integrated once in closed form:
+ *   int k ds = [E1(a/s_hi) - E1(a/s_lo)] / (4 pi)          (E1(a/0) = 0)
+ *   int d_ny k ds = (x-y).n_y / (2 pi r^2) [e^{-a/s_hi} - e^{-a/s_lo}]
+ * The space integrals are globally adaptive (segment split at the foot of
+ * x, triangle in collapsed coordinates).                                  */
+typedef struct { const Prob* pr; R x, y, slo, shi; int j; } PC;
+
+static void f_pot_seg(void* vc, R s, R* out)
+{
+    const PC* c = (const PC*)vc;
+    const Prob* p = c->pr;
+    R yx = p->px[c->j] + s * p->ex[c->j], yy = p->py[c->j] + s * p->ey[c->j];
+    R dx = c->x - yx, dy = c->y - yy, r2 = dx * dx + dy * dy;
+    R a = p->alpha * r2 / 4;
+    R sl = (e1l(a / c->shi) - (c->slo > 0 ? e1l(a / c->slo) : 0)) / (4 * PI_L);
+    R dn = dx * p->nx[c->j] + dy * p->ny[c->j];
+    R dl = dn / (2 * PI_L * r2) * (expl(-a / c->shi) - (c->slo > 0 ? expl(-a / c->slo) : 0));
+    R l1 = s / p->L[c->j];
+    out[0] = sl;                 /* single layer density 1 */
+    out[1] = dl * (1 - l1);      /* double layer, hat of vertex j */
+    out[2] = dl * l1;            /* double layer, hat of vertex j + 1 */
+}
+
+typedef struct { const Prob* pr; R x, y, t; R A[2], B[2], C[2], area2; R T[3][3]; } PT;
+
+/* collapsed map of the triangle: y = A + u (B - A) + u v (C - B), dy = u area2 du dv */
+static void f_pot_tri(void* vc, R u, R v, R* out)
+{
+    const PT* c = (const PT*)vc;
+    R yx = c->A[0] + u * (c->B[0] - c->A[0]) + u * v * (c->C[0] - c->B[0]);
+    R yy = c->A[1] + u * (c->B[1] - c->A[1]) + u * v * (c->C[1] - c->B[1]);
+    R dx = c->x - yx, dy = c->y - yy;
+    R al = c->pr->alpha;
+    R U = al / (4 * PI_L * c->t) * expl(-al * (dx * dx + dy * dy) / (4 * c->t)) * u * c->area2;
+    for (int q = 0; q < 3; ++q) out[q] = U * (c->T[q][0] + c->T[q][1] * yx + c->T[q][2] * yy);
+}
+
+/* out[0] = M~0 u0, out[1] = V~ w, out[2] = W g at (x, y, t) */
+static void potential(const Prob* p, R x, R y, R t, const double* w, const double* g, const double* u0, R* out)
+{
+    out[0] = out[1] = out[2] = 0;
+    for (int m = 0; m < p->nt && p->t[m] < t; ++m) {
+        PC c; c.pr = p; c.x = x; c.y = y;
+        c.shi = t - p->t[m];
+        c.slo = t - p->t[m + 1] > 0 ? t - p->t[m + 1] : 0;
+        for (int j = 0; j < p->ng; ++j) {
+            c.j = j;
+            R L = p->L[j];
+            R sf = (x - p->px[j]) * p->ex[j] + (y - p->py[j]) * p->ey[j];   /* foot of x */
+            R cuts[3] = {0, sf, L}; int nc = 3;
+            if (!(sf > 1e-12L * L && sf < L * (1 - 1e-12L))) { cuts[1] = L; nc = 2; }
+            R est[3] = {0, 0, 0}, mid[3];
+            for (int a = 0; a + 1 < nc; ++a) {
+                f_pot_seg(&c, 0.5L * (cuts[a] + cuts[a + 1]), mid);
+                for (int q = 0; q < 3; ++q) est[q] += fabsl(mid[q]) * (cuts[a + 1] - cuts[a]);
+            }
+            R mag = est[0] + est[1] + est[2];
+            R acc[3] = {0, 0, 0};
+            for (int a = 0; a + 1 < nc; ++a) gadapt1(f_pot_seg, &c, 3, cuts[a], cuts[a + 1], 1e-18L * mag + 1e-300L, acc);
+            int jn = j + 1 == p->ng ? 0 : j + 1;
+            out[1] += (R)w[m * p->ng + j] * acc[0];
+            out[2] += (R)g[m * p->ng + j] * acc[1] + (R)g[m * p->ng + jn] * acc[2];
+        }
+    }
+    if (!u0) return;
+    for (int tt = 0; tt < p->ntri; ++tt) {
+        PT c; c.pr = p; c.x = x; c.y = y; c.t = t;
+        R Vv[3][2];
+        for (int v = 0; v < 3; ++v) { Vv[v][0] = p->ox[p->tri[3 * tt + v]]; Vv[v][1] = p->oy[p->tri[3 * tt + v]]; }
+        R det = (Vv[1][0] - Vv[0][0]) * (Vv[2][1] - Vv[0][1]) - (Vv[1][1] - Vv[0][1]) * (Vv[2][0] - Vv[0][0]);
+        for (int v = 0; v < 3; ++v) {
+            const R* B = Vv[(v + 1) % 3]; const R* C = Vv[(v + 2) % 3];
+            c.T[v][0] = ((C[0] - B[0]) * (-B[1]) - (C[1] - B[1]) * (-B[0])) / det;
+            c.T[v][1] = (-(C[1] - B[1])) / det;
+            c.T[v][2] = (C[0] - B[0]) / det;
+        }
+        /* the vertex nearest to x is the collapsed corner A, so that a peak
+         * of the Gaussian near a vertex sits where the rule is dense */
+        int a0 = 0; R best = INFINITY;
+        for (int v = 0; v < 3; ++v) { R d2 = (Vv[v][0] - x) * (Vv[v][0] - x) + (Vv[v][1] - y) * (Vv[v][1] - y); if (d2 < best) { best = d2; a0 = v; } }
+        for (int q = 0; q < 2; ++q) { c.A[q] = Vv[a0][q]; c.B[q] = Vv[(a0 + 1) % 3][q]; c.C[q] = Vv[(a0 + 2) % 3][q]; }
+        c.area2 = fabsl(det);
+        R mom[3] = {0, 0, 0};
+        integrate2(f_pot_tri, &c, 3, 0, 1, 0, 1, 1e-17L, mom);
+        for (int v = 0; v < 3; ++v) out[0] += (R)u0[p->tri[3 * tt + v]] * mom[v];
+    }
+}
+
 /* ------------------------------------------------------------ C ABI */
 typedef struct { Prob* p; } or_problem;
 
@@ -823,6 +919,24 @@ int or_m0_rows(const or_problem* h, int deriv, long n, const int* rows, double* 
         free(acc);
     }
     free(mom);
+    return 0;
+}
+
+/* the potentials of eq. (2) at n points (x, y, t), 0 < t: out is n x 3
+ * (M~0 u0, V~ w, W g), so u = out0 + out1 - out2; u0 may be NULL */
+int or_potential(const or_problem* h, long n, const double* pts, const double* w, const double* g,
+                 const double* u0, double* out, int nthreads)
+{
+    if (!h || !w || !g) return -1;
+    const Prob* p = h->p;
+    for (long e = 0; e < n; ++e) if (!(pts[3 * e + 2] > 0)) return -2;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long e = 0; e < n; ++e) {
+        R r[3];
+        potential(p, pts[3 * e], pts[3 * e + 1], pts[3 * e + 2], w, g, u0, r);
+        for (int q = 0; q < 3; ++q) out[3 * e + q] = (double)r[q];
+    }
     return 0;
 }
 

@@ -269,3 +269,44 @@ def test_gmres_matches_block_forward_substitution():
     assert np.linalg.norm(wg - wd) / np.linalg.norm(wd) < 1e-12
     wn, itn, _ = o.solve_gmres(V, D, f, tol=1e-14, precondition=False)
     assert np.linalg.norm(wn - wd) / np.linalg.norm(wd) < 1e-12
+
+
+def _affine_data(wl, c0, c):
+    """Cauchy data of u = c0 + c.x (a stationary solution of alpha u_t = Lap u):
+    g nodal and constant in time, w = c.n per segment, u0 nodal; all exact in
+    the discrete spaces."""
+    bnd = wl.bnd_xy
+    d = np.roll(bnd, -1, axis=0) - bnd
+    L = np.hypot(d[:, 0], d[:, 1])
+    e = d / L[:, None]
+    nrm = np.stack([e[:, 1], -e[:, 0]], 1)
+    nt = wl.n_t
+    return np.tile(nrm @ c, nt), np.tile(c0 + bnd @ c, nt), c0 + wl.vtx_xy @ c
+
+
+@pytest.mark.parametrize("name", ["tiny", "lshape_small"])
+def test_representation_formula_reproduces_affine_solutions(name):
+    """Sec. 1, eq. (2): u = M~0 u0 + V~ w - W g holds for the exact Cauchy data
+    of any solution; for u = c0 + c.x those data are exact in the discrete
+    spaces, so the oracle's three potentials must return u at interior
+    points and times to rounding (a dropped 1/alpha, a wrong sign of the
+    double layer or of a time limit, or a missing hat would break it)."""
+    if name == "tiny":
+        wl = W.make("tiny")
+    else:
+        bnd = W.lshape_polygon(16)
+        t = W.uniform_times(5)
+        vx, tr = W.lshape_grid(6)
+        wl = W.Workload(name="ls", alpha=0.3, t_nodes=t, bnd_xy=bnd, vtx_xy=vx, tri=tr,
+                        kvec=np.array([1.0, 0.0]), g=None, u0=None, w_ref=None)
+    o = Oracle.from_workload(wl)
+    c0, c = 0.7, np.array([0.3, -1.1])
+    w, g, u0 = _affine_data(wl, c0, c)
+    pts = np.array([[0.25, 0.25, 1.0], [0.2, 0.7, 0.3], [0.4, 0.1, 0.05], [0.05, 0.3, 0.5], [0.3, 0.3, 0.01],
+                    [0.33, 0.4, 0.0625], [0.45, 0.45, 0.9]])
+    P = o.potential(pts, w, g, u0)
+    u = P[:, 0] + P[:, 1] - P[:, 2]
+    assert np.abs(u - (c0 + pts[:, :2] @ c)).max() <= 1e-14
+    # the constant u = 1: only the initial and the double-layer potential
+    P1 = o.potential(pts, 0 * w, 0 * g + 1, 0 * u0 + 1)
+    assert np.abs(P1[:, 0] - P1[:, 2] - 1).max() <= 1e-14
