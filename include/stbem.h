@@ -177,6 +177,20 @@ int stbem_grad_alpha(stbem_ctx* ctx, const double* lambda_dev, const double* w_d
  * device code (idx_dev: n quadruples (k, m, i, j) as int32; out_dev: n). */
 int stbem_entries(stbem_ctx* ctx, unsigned op, long long n, const int* idx_dev, double* out_dev, void* stream);
 
+/* The representation formula (Sec. 1, eq. (2)) at n points of Q:
+ *   u(x, t) = (M~0 u0)(x, t) + (V~ w)(x, t) - (W g)(x, t)
+ * for the discrete data w (X_h^{0,0} coefficients, e.g. a solution of
+ * stbem_solve), g (nodal x time element) and u0 (nodal, may be NULL: u0 = 0).
+ * pts_dev: n triples (x, y, t), x strictly inside the polygon, 0 < t <= T
+ * (checked on the host: the points are copied back, the stream is
+ * synchronised; STBEM_EINVAL otherwise).  out_dev: n triples (M~0 u0,
+ * V~ w, W g), so u = out0 + out1 - out2.  The time integrals are closed
+ * forms in E1 and exp; space integrals use Gauss rules on pieces graded
+ * towards the foot of the point (boundary) and on regularly refined
+ * triangles (initial potential). */
+int stbem_potential(stbem_ctx* ctx, long long n, const double* pts_dev, const double* w_dev, const double* g_dev,
+                    const double* u0_dev, double* out_dev, void* stream);
+
 /* Block-Toeplitz storage for uniform time steps (on = 1).  With equal steps
  * the block (k, m) of V_h, K_h, D_h and their alpha-derivatives depends on
  * k - m only (the time integrals depend on the lags), so only the N_I blocks

@@ -69,6 +69,7 @@ def load():
         "stbem_entries": (ctypes.c_int, [vp, ctypes.c_uint, ctypes.c_longlong, vp, vp, vp]),
         "stbem_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
         "stbem_set_toeplitz": (ctypes.c_int, [vp, ctypes.c_int]),
+        "stbem_potential": (ctypes.c_int, [vp, ctypes.c_longlong, vp, vp, vp, vp, vp, vp]),
         "stbem_kernel_times": (ctypes.c_int, [vp, ctypes.POINTER(stbem_kernel_time), ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
@@ -81,4 +82,4 @@ def load():
 EXPORTED = ["stbem_create", "stbem_destroy", "stbem_last_error", "stbem_set_allocator", "stbem_sizes",
             "stbem_assemble", "stbem_release", "stbem_matrix", "stbem_apply", "stbem_mass", "stbem_precondition", "stbem_rhs",
             "stbem_prepare_ir", "stbem_solve", "stbem_grad_alpha", "stbem_entries", "stbem_set_timing",
-            "stbem_kernel_times", "stbem_set_toeplitz"]
+            "stbem_kernel_times", "stbem_set_toeplitz", "stbem_potential"]

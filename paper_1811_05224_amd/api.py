@@ -178,10 +178,23 @@ class Context:
 
     def grad_alpha(self, lam, w, g, u0=None):
         out = self.vec(n=1)
-        self._check(self.lib.stbem_grad_alpha(self._h, _ptr(self.vec(lam)), _ptr(self.vec(w)), _ptr(self.vec(g)),
+        self._check(self.lib.stbem_grad_alpha(self._h, _ptr(self.vec(lam)), _ptr(w), _ptr(g),
                                               _ptr(self.vec(u0)) if u0 is not None else None, _ptr(out),
                                               self._stream()), "stbem_grad_alpha")
         return out
+
+    def potential(self, pts, w, g, u0=None):
+        """(M~0 u0, V~ w, W g) at points (x, y, t) of Q as an (n, 3) tensor; u = c0 + c1 - c2."""
+        pts = torch.as_tensor(np.asarray(pts, dtype=np.float64).reshape(-1, 3), device=self.device).contiguous()
+        out = self.vec(n=3 * pts.shape[0])
+        w, g = self.vec(w), self.vec(g)
+        u0t = self.vec(u0) if u0 is not None else None
+        if w.numel() != self.n or g.numel() != self.n or (u0t is not None and u0t.numel() != self.nv):
+            raise ValueError("w and g need N entries, u0 one per Omega vertex")
+        self._check(self.lib.stbem_potential(self._h, pts.shape[0], _ptr(pts), _ptr(w), _ptr(g),
+                                             _ptr(u0t) if u0t is not None else None, _ptr(out), self._stream()),
+                    "stbem_potential")
+        return out.view(-1, 3)
 
     def set_timing(self, on=True):
         self._check(self.lib.stbem_set_timing(self._h, 1 if on else 0), "stbem_set_timing")

@@ -706,6 +706,81 @@ __global__ __launch_bounds__(kWG) void k_m0_pow_apply(int ng, int nv, int nt, in
     }
 }
 
+// Representation formula (eq. (2)) at points (x, y, t): one workgroup per
+// point.  Boundary potentials: the lanes take the (time element, segment)
+// pairs with t_m < t in a fixed order; initial potential: the lanes take the
+// triangles.  Sums are reduced in LDS in a fixed tree order.
+__device__ __forceinline__ double block_reduce(double v, double* red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = kWG / 2; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kWG) void k_pot_bnd(Geom g, const Tables* __restrict__ Tg, Orders O,
+                                                 const double* __restrict__ pts, const double* __restrict__ w,
+                                                 const double* __restrict__ gd, int has_u0, double* __restrict__ out)
+{
+    __shared__ Tables T;
+    __shared__ double red[kWG];
+    {
+        const double* src = reinterpret_cast<const double*>(Tg);
+        double* dst = reinterpret_cast<double*>(&T);
+        for (int e = threadIdx.x; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
+    }
+    __syncthreads();
+    const long long p = blockIdx.x;
+    const double x = pts[3 * p], y = pts[3 * p + 1], t = pts[3 * p + 2];
+    int M = 0;
+    while (M < g.nt && g.t[M] < t) ++M;
+    double sl = 0.0, dl = 0.0;
+    for (int e = threadIdx.x; e < M * g.ng; e += kWG) {
+        const int m = e / g.ng, j = e % g.ng, jn = j + 1 == g.ng ? 0 : j + 1;
+        const double shi = t - g.t[m], slo = fmax(t - g.t[m + 1], 0.0);
+        const PotSeg r = pot_segment(T, O, g, j, x, y, slo, shi);
+        const long long o = (long long)m * g.ng;
+        sl += w[o + j] * r.sl;
+        dl += gd[o + j] * r.d0 + gd[o + jn] * r.d1;
+    }
+    sl = block_reduce(sl, red);
+    dl = block_reduce(dl, red);
+    if (threadIdx.x == 0) {
+        out[3 * p + 1] = sl;
+        out[3 * p + 2] = dl;
+        if (!has_u0) out[3 * p] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_pot_init(Geom g, Mesh2 mesh, const Tables* __restrict__ Tg, Orders O,
+                                                  const double* __restrict__ pts, const double* __restrict__ u0,
+                                                  double* __restrict__ out)
+{
+    __shared__ Tables T;
+    __shared__ double red[kWG];
+    {
+        const double* src = reinterpret_cast<const double*>(Tg);
+        double* dst = reinterpret_cast<double*>(&T);
+        for (int e = threadIdx.x; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
+    }
+    __syncthreads();
+    const long long p = blockIdx.x;
+    const double x = pts[3 * p], y = pts[3 * p + 1], t = pts[3 * p + 2];
+    double acc = 0.0;
+    for (int tri = threadIdx.x; tri < mesh.ntri; tri += kWG) {
+        double mom[3];
+        pot_triangle(T, O, g, mesh, tri, x, y, t, mom);
+        for (int v = 0; v < 3; ++v) acc += u0[mesh.tri[3 * tri + v]] * mom[v];
+    }
+    acc = block_reduce(acc, red);
+    if (threadIdx.x == 0) out[3 * p] = acc;
+}
+
 // ---------------------------------------------------------------- GEMV
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -1776,6 +1851,48 @@ int stbem_set_toeplitz(stbem_ctx* c, int on)
     c->toep = want;
     for (int q = 0; q < 7; ++q) if (c->d_blist[q]) { (void)hipFree(c->d_blist[q]); c->d_blist[q] = nullptr; }
     return build_block_lists(c);
+}
+
+int stbem_potential(stbem_ctx* c, long long npts, const double* pts, const double* w, const double* gd,
+                    const double* u0, double* out, void* stream)
+{
+    if (!c || npts < 0 || (npts > 0 && (!pts || !w || !gd || !out))) return STBEM_EINVAL;
+    if (u0 && c->nv == 0) return fail(c, STBEM_EINVAL, "u0 given but no Omega mesh");
+    if (npts == 0) return STBEM_OK;
+    if (npts > 0x7fffffffLL) return fail(c, STBEM_EINVAL, "too many points");
+    hipStream_t s = S(stream);
+    // validate on the host: 0 < t <= T and x strictly inside the polygon
+    std::vector<double> hp((size_t)npts * 3);
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipMemcpy(hp.data(), pts, hp.size() * sizeof(double), hipMemcpyDeviceToHost));
+    double lmin = 1e300;
+    for (int i = 0; i < c->ng; ++i) lmin = std::fmin(lmin, c->len[i]);
+    for (long long e = 0; e < npts; ++e) {
+        const double x = hp[3 * e], y = hp[3 * e + 1], t = hp[3 * e + 2];
+        if (!(t > 0.0) || !(t <= c->t[c->nt])) return fail(c, STBEM_EINVAL, "point %lld: t = %g outside (0, T]", e, t);
+        bool in = false;
+        double dmin = 1e300;
+        for (int i = 0; i < c->ng; ++i) {
+            const int j = i + 1 == c->ng ? 0 : i + 1;
+            const double ax = c->vx[i], ay = c->vy[i], bx = c->vx[j], by = c->vy[j];
+            if ((ay > y) != (by > y) && x < ax + (y - ay) * (bx - ax) / (by - ay)) in = !in;
+            double u = ((x - ax) * c->ex[i] + (y - ay) * c->ey[i]) / c->len[i];
+            u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
+            dmin = std::fmin(dmin, std::hypot(x - ax - u * (bx - ax), y - ay - u * (by - ay)));
+        }
+        if (!in || dmin <= 1e-12 * lmin) return fail(c, STBEM_EINVAL, "point %lld is not inside Omega", e);
+    }
+    {
+        KTimer kt(c, "k_pot_bnd", (double)npts, s);
+        hipLaunchKernelGGL(k_pot_bnd, dim3((unsigned)npts), dim3(kWG), 0, s, geom(c), c->d_tab, c->ord, pts, w, gd,
+                           u0 ? 1 : 0, out);
+    }
+    if (u0) {
+        KTimer kt(c, "k_pot_init", (double)npts, s);
+        hipLaunchKernelGGL(k_pot_init, dim3((unsigned)npts), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->ord, pts, u0, out);
+    }
+    HIPCHK(c, hipGetLastError());
+    return STBEM_OK;
 }
 
 int stbem_set_timing(stbem_ctx* c, int on)

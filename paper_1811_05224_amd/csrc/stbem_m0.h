@@ -270,4 +270,166 @@ SDEV void m0_tri_moments(const Tables& T, const M0Tables& D, const M0Orders& MO,
     m0_regular3(T, S, tr, qs, qs, [&](double r2) { return m0_kernel<DERIV>(g, k, r2); }, out);
 }
 
+// ------------------------------------------------ representation formula
+// Potentials of eq. (2) at a point (x, t) of Q.  In the lag s = t - tau,
+// s in [s_lo, s_hi] for a time element, with a = alpha r^2 / 4:
+//   single layer  int k ds    = [E1(a/s_hi) - E1(a/s_lo)] / (4 pi)
+//   double layer  int d_ny k ds = (x-y).n_y / (2 pi r^2) [e^{-a/s_hi} - e^{-a/s_lo}]
+// (E1(a/0) = 0, e^{-a/0} = 0).  The differences are formed without
+// cancellation: ln(s_hi/s_lo) + Ein(a/s_hi) - Ein(a/s_lo) while a/s_lo <= 2,
+// and e^{-a/s_hi} (-expm1(-a (1/s_lo - 1/s_hi))) for the exponentials.
+struct PotSeg { double sl, d0, d1; };   // single layer; double layer against the two hats
+
+SDEV void pot_kernels(double alpha, double r2, double dn, double slo, double shi, double& sl, double& dl)
+{
+    const double a = 0.25 * alpha * r2, zh = a / shi;
+    double eh;
+    if (slo <= 0.0) {
+        sl = e1x(zh, eh) * kInv4Pi;
+        dl = dn / (2.0 * kPi * r2) * eh;
+        return;
+    }
+    const double zl = a / slo;
+    if (zl <= 2.0) sl = (log(shi / slo) + ein(zh) - ein(zl)) * kInv4Pi;
+    else {
+        double el;
+        sl = (e1x(zh, eh) - e1x(zl, el)) * kInv4Pi;
+    }
+    eh = exp(-zh);
+    dl = dn / (2.0 * kPi * r2) * eh * (-expm1(-a * (1.0 / slo - 1.0 / shi)));
+}
+
+// Integrals over segment j for a point at distance d > 0 from it: the
+// segment is cut at the foot of the point into pieces whose lengths double
+// away from it (distance / length >= 1/2 on every piece), each with a Gauss
+// rule of the order the distance class and the slope of e^{-z} ask for.
+SDEV PotSeg pot_segment(const Tables& T, const Orders& O, const Geom& g, int j, double x, double y,
+                        double slo, double shi)
+{
+    PotSeg r = {0.0, 0.0, 0.0};
+    const double ax = g.vx[j], ay = g.vy[j], ex = g.ex[j], ey = g.ey[j], L = g.len[j];
+    const double nx = ey, ny = -ex;
+    double sf = (x - ax) * ex + (y - ay) * ey;
+    sf = sf < 0.0 ? 0.0 : (sf > L ? L : sf);
+    const double fx = ax + sf * ex - x, fy = ay + sf * ey - y;
+    const double d = sqrt(fx * fx + fy * fy);
+    const double w2 = 0.25 * g.alpha / (slo > 0.0 ? slo : shi);
+    for (int side = 0; side < 2; ++side) {
+        const double span = side ? L - sf : sf;          // from the foot towards one end
+        double s0 = 0.0, len = d > 1e-12 * L ? d : 1e-12 * L;
+        for (int piece = 0; piece < 64 && s0 < span; ++piece) {
+            double s1 = s0 + len;
+            s1 = s1 > span ? span : s1;
+            const double h = s1 - s0;
+            // distance of the piece from the point, and its class
+            const double dist = sqrt(d * d + s0 * s0), eta = dist / h;
+            int q = O.q_near[kNearClasses - 1];
+            for (int c = kNearClasses - 2; c >= 0; --c)
+                if (eta < O.eta_cut[c]) q = O.q_near[c];
+            int qz = q_slope(w2 * dist * dist, w2 * h * (2.0 * dist + h), O.q_tol, O.z_floor);
+            q = q > qz ? q : qz;
+            q = q > kMaxGL ? kMaxGL : q;
+            for (int a = 0; a < q; ++a) {
+                const double u = s0 + h * T.gl_x[q][a], wq = h * T.gl_w[q][a];
+                const double s = side ? sf + u : sf - u;     // arclength on the segment
+                const double dx = x - (ax + s * ex), dy = y - (ay + s * ey);
+                const double r2 = dx * dx + dy * dy;
+                double sl, dl;
+                pot_kernels(g.alpha, r2, dx * nx + dy * ny, slo, shi, sl, dl);
+                const double l1 = s / L;
+                r.sl += wq * sl;
+                r.d0 += wq * dl * (1.0 - l1);
+                r.d1 += wq * dl * l1;
+            }
+            s0 = s1;
+            len *= 2.0;
+        }
+    }
+    return r;
+}
+
+// Gauss-Legendre order for e^{-beta |x - y|^2} on a piece of size h at
+// distance >= dlo: the 2q-th derivative of a Gaussian of width beta^{-1/2}
+// grows like (2q)!/q! beta^q, so the remainder of the q-point rule is about
+// c_q (2q)!/q! (beta h^2)^q e^{dz} (c_q the Gauss remainder constant on
+// [0, 1]); the slope bound of q_slope covers pieces far on the tail.
+SDEV int q_gauss(double bh2, double zlo, double dz, double q_tol, double z_floor)
+{
+    const double lim = q_tol * exp(-dz) * (zlo > z_floor ? exp(zlo - z_floor) : 1.0);
+    double c = 1.0 / 24.0, gf = 2.0, pw = bh2;   // c_1, 2!/1!, (beta h^2)^1
+    int q = 1;
+    while (q < kMaxGL && c * gf * pw > lim) {
+        const double a = 2.0 * q + 1.0;
+        c *= (double)(q + 1) * (q + 1) * (q + 1) * (q + 1) * a / ((a + 2.0) * (a * (a + 1.0)) * (a * (a + 1.0)) * (a * (a + 1.0)));
+        gf *= 2.0 * a;
+        pw *= bh2;
+        ++q;
+    }
+    const int qs = q_slope(zlo, dz, q_tol, z_floor);
+    return q > qs ? q : qs;
+}
+
+// int_t U*(x - y, t) phi_v(y) dy for the three hats of triangle t: U* is a
+// Gaussian of width sqrt(4t/alpha); the triangle is refined regularly into
+// n^2 congruent triangles (n a power of two, at most 32) so that the change
+// of e^{-z} across one of them stays moderate, and each gets the collapsed
+// Gauss rule of the order the slope bound asks for (one more for the
+// collapsed direction).  Triangles whose distance makes the Gaussian below
+// e^{-60} of its peak contribute nothing.
+SDEV void pot_triangle(const Tables& T, const Orders& O, const Geom& g, const Mesh2& m, int tri, double x, double y,
+                       double t, double* mom)
+{
+    mom[0] = mom[1] = mom[2] = 0.0;
+    const Tri3 tr = load_tri3(m, tri);
+    const double P[3][2] = {{tr.ax, tr.ay}, {tr.bx, tr.by}, {tr.cx, tr.cy}};
+    // distance from the point to the triangle (0 inside)
+    double d2 = 1e300, diam2 = 0.0;
+    int sgn = 0;
+    for (int e = 0; e < 3; ++e) {
+        const double* A = P[e];
+        const double* B = P[e == 2 ? 0 : e + 1];
+        const double ex = B[0] - A[0], ey = B[1] - A[1], l2 = ex * ex + ey * ey;
+        double u = ((x - A[0]) * ex + (y - A[1]) * ey) / l2;
+        u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
+        const double dx = x - A[0] - u * ex, dy = y - A[1] - u * ey;
+        d2 = fmin(d2, dx * dx + dy * dy);
+        diam2 = fmax(diam2, l2);
+        sgn += (ex * (y - A[1]) - ey * (x - A[0])) >= 0.0 ? 1 : -1;
+    }
+    if (sgn == 3 || sgn == -3) d2 = 0.0;
+    const double w2 = 0.25 * g.alpha / t, size = sqrt(diam2), d = sqrt(d2);
+    if (w2 * d2 > 60.0) return;
+    int n = 1;
+    while (n < 32 && w2 * (size / n) * (2.0 * d + size / n) > 2.0) n *= 2;
+    const double c0 = g.alpha / (4.0 * kPi * t);
+    const double ux = (tr.bx - tr.ax) / n, uy = (tr.by - tr.ay) / n, vx = (tr.cx - tr.ax) / n, vy = (tr.cy - tr.ay) / n;
+    const double area2 = fabs(ux * vy - uy * vx);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; i + j < n; ++j)
+            for (int down = 0; down < 2; ++down) {
+                if (down && i + j > n - 2) continue;
+                // corners of the sub-triangle
+                double A0 = tr.ax + i * ux + j * vx, A1 = tr.ay + i * uy + j * vy;
+                double B0, B1, C0, C1;
+                if (!down) { B0 = A0 + ux; B1 = A1 + uy; C0 = A0 + vx; C1 = A1 + vy; }
+                else { B0 = A0 + ux + vx; B1 = A1 + uy + vy; C0 = A0 + vx; C1 = A1 + vy; A0 += ux; A1 += uy; }
+                const double cxm = (A0 + B0 + C0) / 3.0 - x, cym = (A1 + B1 + C1) / 3.0 - y;
+                const double hs = size / n, dc = fmax(0.0, sqrt(cxm * cxm + cym * cym) - hs);
+                if (w2 * dc * dc > 60.0) continue;
+                int q = q_gauss(w2 * hs * hs, w2 * dc * dc, w2 * hs * (2.0 * dc + hs), O.q_tol, O.z_floor) + 1;
+                q = q < 3 ? 3 : (q > kMaxGL ? kMaxGL : q);
+                const double e1x_ = B0 - A0, e1y_ = B1 - A1, e2x = C0 - B0, e2y = C1 - B1;
+                for (int a = 0; a < q; ++a) {
+                    const double u = T.gl_x[q][a], wu = T.gl_w[q][a] * u * area2;
+                    for (int b = 0; b < q; ++b) {
+                        const double v = T.gl_x[q][b], w = wu * T.gl_w[q][b];
+                        const double yx = A0 + u * e1x_ + u * v * e2x, yy = A1 + u * e1y_ + u * v * e2y;
+                        const double dx = x - yx, dy = y - yy;
+                        const double k = w * c0 * exp(-w2 * (dx * dx + dy * dy));
+                        for (int c = 0; c < 3; ++c) mom[c] += k * (tr.g0[c] + tr.gx[c] * yx + tr.gy[c] * yy);
+                    }
+                }
+            }
+}
+
 }  // namespace stbem
