@@ -139,24 +139,24 @@ __device__ __forceinline__ void far_pair(const Tables& T, const TimeBlock& tb, d
     for (int a = 0; a < Q; ++a) {
         const double sP = P[4] * T.gl_x[Q][a];
         const double xx = P[0] + sP * P[2], xy = P[1] + sP * P[3];
-        double z[Q], l0[Q], l1[Q], acc[Q], cum[Q], dn[Q];
+        double z[Q], l0[Q], l1[Q], acc[Q], dn[Q];
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
             const double sQ = Qs[4] * T.gl_x[Q][c];
             const double dx = xx - (Qs[0] + sQ * Qs[2]), dy = xy - (Qs[1] + sQ * Qs[3]);
             z[c] = 0.25 * al * (dx * dx + dy * dy) * tb.inv_dc;
             dn[c] = dx * nqx + dy * nqy;
-            l0[c] = 1.0; l1[c] = 1.0 - z[c]; acc[c] = tb.c[0]; cum[c] = 1.0;
+            l0[c] = 1.0; l1[c] = 1.0 - z[c];
+            acc[c] = NEED_V ? tb.st[0][11] : tb.st[0][6] + tb.st[0][7] * l1[c];
         }
         for (int n = 1; n < tb.nterm; ++n) {
-            const int j = 2 * n - 1;
-            const double cn = tb.c[n], r1 = tb.rinv[j + 1], r2 = tb.rinv[j + 2];
+            const double* st = tb.st[n];
 #pragma unroll
             for (int c = 0; c < Q; ++c) {
-                const double x2 = ((2.0 * j + 1.0 - z[c]) * l1[c] - j * l0[c]) * r1;
-                const double x3 = ((2.0 * j + 3.0 - z[c]) * x2 - (j + 1.0) * l1[c]) * r2;
-                if (NEED_V) acc[c] += cn * x2;
-                else { cum[c] += l1[c] + x2; acc[c] += cn * cum[c]; }
+                const double x2 = fma(fma(-st[1], z[c], st[0]), l1[c], -st[2] * l0[c]);
+                const double x3 = fma(fma(-st[4], z[c], st[3]), x2, -st[5] * l1[c]);
+                if (NEED_V) acc[c] = fma(st[11], x2, acc[c]);
+                else acc[c] = fma(st[7], x3, fma(st[6], x2, acc[c]));
                 l0[c] = x2; l1[c] = x3;
             }
         }
@@ -293,30 +293,26 @@ __device__ __forceinline__ void far_dpair(const Tables& T, const TimeBlock& tb, 
         const double xa = T.gl_x[Q][a];
         const double sP = P[4] * xa, wP = P[4] * T.gl_w[Q][a];
         const double xx = P[0] + sP * P[2], xy = P[1] + sP * P[3];
-        double z[Q], l0[Q], l1[Q], c1[Q], c2[Q], sd[Q], sk[Q], s2[Q], zt[Q];
+        double z[Q], l0[Q], l1[Q], sd[Q], sk[Q], s2[Q], zt[Q];
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
             const double sQ = Qs[4] * T.gl_x[Q][c];
             const double dx = xx - (Qs[0] + sQ * Qs[2]), dy = xy - (Qs[1] + sQ * Qs[3]);
             z[c] = 0.25 * al * (dx * dx + dy * dy) * tb.inv_dc;
             zt[c] = (dx * P[2] + dy * P[3]) * (dx * Qs[2] + dy * Qs[3]);
-            l0[c] = 1.0; l1[c] = 1.0 - z[c]; c1[c] = 1.0; c2[c] = 1.0;
-            sd[c] = tb.c[0] * l1[c]; sk[c] = tb.c[0]; s2[c] = tb.c[0];
+            l0[c] = 1.0; l1[c] = 1.0 - z[c];
+            const double* s0 = tb.st[0];
+            sd[c] = s0[10] * l1[c]; sk[c] = s0[6] + s0[7] * l1[c]; s2[c] = s0[8] + s0[9] * l1[c];
         }
         for (int n = 1; n < tb.nterm; ++n) {
-            const int j = 2 * n - 1;
-            const double cn_ = tb.c[n], r1 = tb.rinv[j + 1], r2 = tb.rinv[j + 2], f3 = 2.0 * n + 1.0;
+            const double* st = tb.st[n];
 #pragma unroll
             for (int c = 0; c < Q; ++c) {
-                const double x2 = ((2.0 * j + 1.0 - z[c]) * l1[c] - j * l0[c]) * r1;
-                const double x3 = ((2.0 * j + 3.0 - z[c]) * x2 - (j + 1.0) * l1[c]) * r2;
-                const double c1o = c1[c] + l1[c];
-                c2[c] += c1o;
-                c1[c] = c1o + x2;
-                c2[c] += c1[c];
-                sk[c] += cn_ * c1[c];
-                sd[c] += cn_ * f3 * x3;
-                s2[c] += cn_ * c2[c];
+                const double x2 = fma(fma(-st[1], z[c], st[0]), l1[c], -st[2] * l0[c]);
+                const double x3 = fma(fma(-st[4], z[c], st[3]), x2, -st[5] * l1[c]);
+                sk[c] = fma(st[7], x3, fma(st[6], x2, sk[c]));
+                s2[c] = fma(st[9], x3, fma(st[8], x2, s2[c]));
+                sd[c] = fma(st[10], x3, sd[c]);
                 l0[c] = x2; l1[c] = x3;
             }
         }

@@ -159,8 +159,14 @@ struct TimeBlock {
     int ndel;
     double dc, inv_dc;    // centre distance (separated)
     double w2;            // alpha / (4 smallest lag): z = w2 r^2 bounds a / delta
-    double c[kMaxTerms];  // mu_2n / dc^2n
-    double rinv[2 * kMaxTerms + 2];   // 1/n for the Laguerre recurrence
+    // Series step n (n >= 1 advances L_{2n-1} -> L_{2n} -> L_{2n+1}; n = 0
+    // holds the coefficients of L_0, L_1), with L_{j+1} = (A_j - B_j z) L_j - C_j L_{j-1}:
+    //   st[n][0..2] = A, B, C for j = 2n - 1      st[n][3..5] = A, B, C for j = 2n
+    //   st[n][6..7] = kc_{2n}, kc_{2n+1}          st[n][8..9] = hc_{2n}, hc_{2n+1}
+    //   st[n][10]   = (2n + 1) c_n                st[n][11]   = c_n
+    // where c_n = mu_2n / dc^2n and kc, hc are the coefficients of L_m in
+    // sum_n c_n L^(1)_2n and sum_n c_n L^(2)_2n (tail sums of c, see time_block).
+    alignas(16) double st[kMaxTerms][12];
 };
 
 // Build the time block (k, m), k >= m, from the node array.
@@ -200,17 +206,38 @@ SDEV void time_block(const Geom& g, int k, int m, TimeBlock& tb)
             return;
         }
         tb.ser = 1;
-        tb.rinv[0] = 0.0;
-        for (int r = 1; r < 2 * kMaxTerms + 2; ++r) tb.rinv[r] = 1.0 / r;
         // mu_2n/dc^2n = 2 dc^2 [p^{2n+2} - q^{2n+2}] / ((2n+1)(2n+2))
         double p2 = p * p, q2 = q * q, pp = p2, qq = q2;
         int n = 0;
         for (; n < kMaxTerms; ++n) {
-            tb.c[n] = 2.0 * dc * dc * (pp - qq) / ((2.0 * n + 1.0) * (2.0 * n + 2.0));
+            tb.st[n][11] = 2.0 * dc * dc * (pp - qq) / ((2.0 * n + 1.0) * (2.0 * n + 2.0));
             if (n > 0 && pp < 1e-19) { ++n; break; }
             pp *= p2; qq *= q2;
         }
         tb.nterm = n;
+        // L^(1)_2n = sum_{m <= 2n} L_m, so sum_n c_n L^(1)_2n = sum_m kc_m L_m with
+        // kc_m = sum_{2n >= m} c_n; likewise sum_n c_n L^(2)_2n = sum_m hc_m L_m,
+        // hc_m = sum_{2n >= m} (2n - m + 1) c_n, i.e. hc_m = hc_{m+1} + kc_m.  All
+        // terms are positive (p > |q|), so these tail sums do not cancel.
+        double kc = 0.0, hc = 0.0;
+        for (int e = n - 1; e >= 0; --e) {
+            const double cn = tb.st[e][11];
+            tb.st[e][7] = e + 1 < n ? kc : 0.0;     // kc_{2e+1}: n' >= e + 1
+            hc += tb.st[e][7];
+            tb.st[e][9] = e + 1 < n ? hc : 0.0;
+            kc += cn;                               // kc_{2e}: n' >= e
+            tb.st[e][6] = kc;
+            hc += kc;
+            tb.st[e][8] = hc;
+            tb.st[e][10] = (2.0 * e + 1.0) * cn;
+            for (int h = 0; h < 2; ++h) {
+                const int j = 2 * e - 1 + h;
+                const double b = j >= 0 ? 1.0 / (j + 1.0) : 0.0;
+                tb.st[e][3 * h] = (2.0 * j + 1.0) * b;
+                tb.st[e][3 * h + 1] = b;
+                tb.st[e][3 * h + 2] = j * b;
+            }
+        }
     }
     for (int s = 0; s < tb.ndel; ++s) tb.lnd[s] = log(tb.del[s]);
 }
@@ -227,21 +254,16 @@ SDEV SeriesVals series(const TimeBlock& tb, double a)
 {
     double z = a * tb.inv_dc, ez = exp(-z);
     double l0 = 1.0, l1 = 1.0 - z;          // L_0, L_1
-    double c1 = 1.0, c2 = 1.0;              // L^(1)_{2n}, L^(2)_{2n}
-    double sv = tb.c[0], sk = tb.c[0], sd = tb.c[0] * l1, s2 = tb.c[0];
+    const double* s0 = tb.st[0];
+    double sv = s0[11], sk = s0[6] + s0[7] * l1, sd = s0[10] * l1, s2 = s0[8] + s0[9] * l1;
     for (int n = 1; n < tb.nterm; ++n) {
-        int j = 2 * n - 1;                  // advance to L_{2n}, L_{2n+1}
-        double l2 = ((2.0 * j + 1.0 - z) * l1 - j * l0) * tb.rinv[j + 1];
-        double l3 = ((2.0 * j + 3.0 - z) * l2 - (j + 1.0) * l1) * tb.rinv[j + 2];
-        double c1o = c1 + l1;               // L^(1)_{2n-1}
-        if (NEED_H) c2 += c1o;              // L^(2)_{2n-1}
-        c1 = c1o + l2;                      // L^(1)_{2n}
-        if (NEED_H) c2 += c1;               // L^(2)_{2n}
-        double cn = tb.c[n];
-        if (NEED_V) sv += cn * l2;
-        if (NEED_K || NEED_H) sk += cn * c1;
-        if (NEED_D) sd += cn * (2.0 * n + 1.0) * l3;
-        if (NEED_H) s2 += cn * c2;
+        const double* st = tb.st[n];        // advance to L_{2n}, L_{2n+1}
+        const double l2 = fma(fma(-st[1], z, st[0]), l1, -st[2] * l0);
+        const double l3 = fma(fma(-st[4], z, st[3]), l2, -st[5] * l1);
+        if (NEED_V) sv = fma(st[11], l2, sv);
+        if (NEED_K || NEED_H) sk = fma(st[7], l3, fma(st[6], l2, sk));
+        if (NEED_D) sd = fma(st[10], l3, sd);
+        if (NEED_H) s2 = fma(st[9], l3, fma(st[8], l2, s2));
         l0 = l2; l1 = l3;
     }
     SeriesVals r;
