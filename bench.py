@@ -35,35 +35,23 @@ FP64_PEAK_TFLOPS = 78.6
 #   HBM bytes = 2 x FETCH_SIZE + WRITE_SIZE (KiB x 1024), the factors from a
 #   1 GiB device copy read by the same counters, profiles/counters_hbm_medium.md.
 # A kernel changed after its counters were taken has no entry here.
-FLOP_PER_UNIT = {'k_assemble_dfar<3>': 4899.3,
-    'k_assemble_vkfar<1, 4>': 2861.2,
-    'k_assemble_dnear': 36715.4,
+FLOP_PER_UNIT = {'k_assemble_dnear': 36715.4,
     'k_m0_tri<false, false>': 22827.6,
-    'k_assemble_dfar<4>': 16779.9,
     'k_m0_tri<false, true>': 78802.3,
-    'k_assemble_vkfar<1, 5>': 8421.0,
     'k_assemble<0>': 19182.9,
     'k_assemble_knear<1>': 12373.6,
-    'k_assemble_vkfar<0, 3>': 754.4,
     'k_m0_pow': 35571.0,
-    'k_assemble_vkfar<0, 4>': 2207.0,
     'k_m0_pow_gather': 6.0,
     'k_m0_pow_apply': 81.0,
     'k_m0_gather': 6.0}
 HBM_BYTES_PER_UNIT = {'k_gemv_n_vec<double>': 8.035,
-    'k_assemble_dfar<3>': 8.002,
-    'k_assemble_vkfar<1, 4>': 9.627,
     'k_assemble_dnear': 8.07,
     'k_m0_tri<false, false>': 24.099,
-    'k_assemble_dfar<4>': 8.006,
     'k_m0_tri<false, true>': 24.49,
     'k_gemv_n_vec<float>': 4.035,
-    'k_assemble_vkfar<1, 5>': 9.631,
     'k_assemble<0>': 8.049,
     'k_assemble_knear<1>': 9.659,
-    'k_assemble_vkfar<0, 3>': 8.002,
     'k_m0_pow': 888.5,
-    'k_assemble_vkfar<0, 4>': 8.006,
     'k_gemv_n_vec<float hi+lo>': 8.035,
     'k_m0_pow_gather': 70.92,
     'k_m0_pow_apply': 10.821,
@@ -122,11 +110,10 @@ def main():
         t = {}
         e0, e1, e2, e3, e4, e5, e6, e7 = (ev() for _ in range(8))
         e0.record(stream)
-        ctx.assemble(L.V)
+        ctx.assemble(L.V | L.D)       # one call: V_h's separated blocks come from D_h's far tiles
         e1.record(stream)
         ctx.assemble(L.K)
         e2.record(stream)
-        ctx.assemble(L.D)
         e3.record(stream)
         ctx.assemble(L.M0)
         e4.record(stream)
@@ -139,7 +126,7 @@ def main():
         e7.record(stream)
         torch.cuda.synchronize()
         if record is not None:
-            record.append({"V": e0.elapsed_time(e1), "K": e1.elapsed_time(e2), "D": e2.elapsed_time(e3),
+            record.append({"V+D": e0.elapsed_time(e1), "K": e1.elapsed_time(e2),
                            "M0": e3.elapsed_time(e4), "rhs": e4.elapsed_time(e5), "solve64": e5.elapsed_time(e6),
                            "solve32": e6.elapsed_time(e7), "i64": i64, "i32": i32})
         return f, w64, w32
@@ -159,7 +146,7 @@ def main():
     ctx.set_timing(False)
 
     entries = ctx.packed_entries            # per causal matrix
-    avg = {k: float(np.mean([r[k] for r in rec])) for k in ("V", "K", "D", "M0", "rhs", "solve64", "solve32")}
+    avg = {k: float(np.mean([r[k] for r in rec])) for k in ("V+D", "K", "M0", "rhs", "solve64", "solve32")}
     value = 3 * entries / (ms_per_step * 1e-3)
 
     # GEMV rate on V_h (HBM-bound), HIP events on the launch stream
@@ -194,8 +181,8 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: N_Gamma={ctx.ng}, N_I={ctx.nt}, N={ctx.n}, M_Omega={ctx.nv}, "
                                f"alpha={wl.alpha}, entries per causal matrix={entries}"},
-        "assembly_ms": {k: avg[k] for k in ("V", "K", "D", "M0")},
-        "assembly_entries_per_s": {k: entries / (avg[k] * 1e-3) for k in ("V", "K", "D")},
+        "assembly_ms": {k: avg[k] for k in ("V+D", "K", "M0")},
+        "assembly_entries_per_s": {"V+D": 2 * entries / (avg["V+D"] * 1e-3), "K": entries / (avg["K"] * 1e-3)},
         "rhs_ms": avg["rhs"],
         "solve_s_fp64": avg["solve64"] * 1e-3, "solve_s_fp32_refined": avg["solve32"] * 1e-3,
         "gmres_iters_fp64": rec[-1]["i64"].iters, "gmres_iters_fp32_inner_total": rec[-1]["i32"].iters,

@@ -281,28 +281,32 @@ constexpr int kDP = 2 * kTile + 2;     // pieces per tile side
 
 // four shape moments of the raw hypersingular kernel for one piece pair,
 // Q x Q Gauss nodes, the Q series of a row of nodes advanced together
-template <int Q>
+template <int Q, bool WV>
 __device__ __forceinline__ void far_dpair(const Tables& T, const TimeBlock& tb, double al,
-                                          const double* P, const double* Qs, double* mom)
+                                          const double* P, const double* Qs, double* mom, double* vmom)
 {
     const double cn = al * (P[5] * Qs[5] + P[6] * Qs[6]);
     const double tt = P[2] * Qs[2] + P[3] * Qs[3];
-    double m00 = 0, m01 = 0, m10 = 0, m11 = 0;
+    // kappa = e^{-z} (fd sd + fk sk + fh zt s2), constants of the pair folded
+    const double i1 = tb.inv_dc, i2 = i1 * i1, zf = 0.25 * al * i1;
+    const double fd = -cn * i2 * kInv4Pi, fk = 0.5 * al * tt * i2 * kInv4Pi, fh = -0.25 * al * al * i2 * i1 * kInv4Pi;
+    double m00 = 0, m01 = 0, m10 = 0, m11 = 0, mv = 0;
 #pragma unroll 1
     for (int a = 0; a < Q; ++a) {
         const double xa = T.gl_x[Q][a];
         const double sP = P[4] * xa, wP = P[4] * T.gl_w[Q][a];
         const double xx = P[0] + sP * P[2], xy = P[1] + sP * P[3];
-        double z[Q], l0[Q], l1[Q], sd[Q], sk[Q], s2[Q], zt[Q];
+        double z[Q], l0[Q], l1[Q], sd[Q], sk[Q], s2[Q], zt[Q], sv[Q];
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
             const double sQ = Qs[4] * T.gl_x[Q][c];
             const double dx = xx - (Qs[0] + sQ * Qs[2]), dy = xy - (Qs[1] + sQ * Qs[3]);
-            z[c] = 0.25 * al * (dx * dx + dy * dy) * tb.inv_dc;
-            zt[c] = (dx * P[2] + dy * P[3]) * (dx * Qs[2] + dy * Qs[3]);
+            z[c] = zf * (dx * dx + dy * dy);
+            zt[c] = fh * ((dx * P[2] + dy * P[3]) * (dx * Qs[2] + dy * Qs[3]));
             l0[c] = 1.0; l1[c] = 1.0 - z[c];
             const double* s0 = tb.st[0];
             sd[c] = s0[10] * l1[c]; sk[c] = s0[6] + s0[7] * l1[c]; s2[c] = s0[8] + s0[9] * l1[c];
+            if (WV) sv[c] = s0[11];
         }
         for (int n = 1; n < tb.nterm; ++n) {
             const double* st = tb.st[n];
@@ -313,40 +317,44 @@ __device__ __forceinline__ void far_dpair(const Tables& T, const TimeBlock& tb, 
                 sk[c] = fma(st[7], x3, fma(st[6], x2, sk[c]));
                 s2[c] = fma(st[9], x3, fma(st[8], x2, s2[c]));
                 sd[c] = fma(st[10], x3, sd[c]);
+                if (WV) sv[c] = fma(st[11], x2, sv[c]);
                 l0[c] = x2; l1[c] = x3;
             }
         }
-        double r0 = 0, r1s = 0;
-        const double i1 = tb.inv_dc, i2 = i1 * i1;
+        double r0 = 0, r1s = 0, rv = 0;
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
             const double e = exp(-z[c]);
-            const double dd = -e * i2 * kInv4Pi * sd[c];
-            const double va = -e * i2 * kInv4Pi * sk[c];
-            const double vaa = e * i2 * i1 * kInv4Pi * s2[c];
-            const double kap = cn * dd - (0.25 * al * al * vaa * zt[c] + 0.5 * al * va * tt);
-            const double xc = T.gl_x[Q][c];
-            const double w = Qs[4] * T.gl_w[Q][c] * kap;
-            r0 += w * (1.0 - xc);
-            r1s += w * xc;
+            const double kap = e * fma(zt[c], s2[c], fma(fk, sk[c], fd * sd[c]));
+            const double xc = T.gl_x[Q][c], wq = Qs[4] * T.gl_w[Q][c];
+            const double w = wq * kap;
+            r0 = fma(w, 1.0 - xc, r0);
+            r1s = fma(w, xc, r1s);
+            if (WV) rv = fma(wq * e, sv[c], rv);
         }
         m00 += wP * (1.0 - xa) * r0; m01 += wP * (1.0 - xa) * r1s;
         m10 += wP * xa * r0;         m11 += wP * xa * r1s;
+        if (WV) mv = fma(wP, rv, mv);
     }
     mom[0] = m00; mom[1] = m01; mom[2] = m10; mom[3] = m11;
+    if (WV) *vmom = mv * i1 * kInv4Pi;       // int int Delta F_V over the piece pair
 }
 
 
-template <int Q>
+// WV: V_h on the same blocks from the same piece pairs (its kernel Delta F_V
+// is one more series sum at the nodes D_h already evaluates): the 2 x 2 half
+// pieces of segments I0 + s and J0 + r are pieces 2s+1, 2s+2 and 2r+1, 2r+2 of
+// the tile, and V_h's tiles are the same symmetric 16 x 16 tiles.
+template <int Q, bool WV>
 __global__ __launch_bounds__(kWG) void k_assemble_dfar(Geom g, const Tables* __restrict__ Tg,
                                                        const int* __restrict__ blist, int tiles_1d,
-                                                       double* __restrict__ out64)
+                                                       double* __restrict__ out64, double* __restrict__ outv)
 {
-    __shared__ Tables T;
     __shared__ TimeBlock tb;
     __shared__ double mom[kDP][kDP][4];
     __shared__ double pc[2][kDP][7];       // ax ay ex ey len nx ny
     __shared__ double stage[kTile][kTile + 1];
+    const Tables& T = *Tg;                 // only the Q-point rule is read (uniform loads)
     const int tid = threadIdx.x;
     const long long tiles = (long long)tiles_1d * (tiles_1d + 1) / 2;
     const long long b = blist[blockIdx.x / tiles];
@@ -355,11 +363,6 @@ __global__ __launch_bounds__(kWG) void k_assemble_dfar(Geom g, const Tables* __r
     int k, m;
     block_of(b, k, m);
     if (tid == 0) time_block(g, k, m, tb);
-    {
-        const double* src = reinterpret_cast<const double*>(Tg);
-        double* dst = reinterpret_cast<double*>(&T);
-        for (int e = tid; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
-    }
     const int I0 = ti * kTile, J0 = tj * kTile;
     const int np = 2 * g.ng;
     if (tid < 2 * kDP) {
@@ -371,15 +374,31 @@ __global__ __launch_bounds__(kWG) void k_assemble_dfar(Geom g, const Tables* __r
         q[0] = P.ax; q[1] = P.ay; q[2] = P.ex; q[3] = P.ey; q[4] = P.len; q[5] = P.nx; q[6] = P.ny;
     }
     __syncthreads();
-    for (int e = tid; e < kDP * kDP; e += kWG) {
-        const int u = e / kDP, v = e % kDP;
-        far_dpair<Q>(T, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v]);
+    // lane (il, jl) takes the 2 x 2 pairs of pieces 2il+1, 2il+2 and 2jl+1,
+    // 2jl+2 (the halves of segments I0+il and J0+jl, which give V_h's entry),
+    // then lanes 0..131 one pair each on the border of the piece range
+    const int il = tid / kTile, jl = tid % kTile, i = I0 + il, j = J0 + jl;
+    double vsum = 0.0;
+#pragma unroll 1
+    for (int e = 0; e < 4; ++e) {
+        const int u = 2 * il + 1 + (e >> 1), v = 2 * jl + 1 + (e & 1);
+        double vm = 0.0;
+        far_dpair<Q, WV>(T, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v], &vm);
+        vsum += vm;
+    }
+    if (tid < 4 * kDP - 4) {
+        int u, v;
+        if (tid < kDP) { u = 0; v = tid; }
+        else if (tid < 2 * kDP) { u = kDP - 1; v = tid - kDP; }
+        else if (tid < 3 * kDP - 2) { u = tid - 2 * kDP + 1; v = 0; }
+        else { u = tid - (3 * kDP - 2) + 1; v = kDP - 1; }
+        double unused;
+        far_dpair<Q, false>(T, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v], &unused);
     }
     __syncthreads();
-    const int il = tid / kTile, jl = tid % kTile, i = I0 + il, j = J0 + jl;
-    const bool live = i < g.ng && j < g.ng;
+    const bool live = i < g.ng && j < g.ng, own = live && !mirrored(true, I0, J0, il, jl);
     double acc = 0.0;
-    if (live && !mirrored(true, I0, J0, il, jl)) {
+    if (own) {
         DualSupport si = dual_support(g, i), sj = dual_support(g, j);
         const int ui = 2 * il, vj = 2 * jl;
 #pragma unroll
@@ -393,7 +412,12 @@ __global__ __launch_bounds__(kWG) void k_assemble_dfar(Geom g, const Tables* __r
             }
         }
     }
-    store_tile(stage, true, acc, live, block_slot(g, b, k, m) * g.ng * g.ng, g.ng, I0, J0, il, jl, out64);
+    const long long boff = block_slot(g, b, k, m) * g.ng * g.ng;
+    store_tile(stage, true, acc, live, boff, g.ng, I0, J0, il, jl, out64);
+    if (WV) {
+        __syncthreads();          // the stage is reused
+        store_tile(stage, true, own ? vsum : 0.0, live, boff, g.ng, I0, J0, il, jl, outv);
+    }
 }
 
 // D_h on touching time elements (d <= 1, closed form in time): one workgroup
@@ -1075,6 +1099,7 @@ struct stbem_ctx {
     int nlist_touch[7] = {0, 0, 0, 0, 0, 0, 0};   // D_h: touching blocks for the tile kernel (list head)
     int nlist_gen[7] = {0, 0, 0, 0, 0, 0, 0};
     int nlist_far[7][9] = {};
+    bool vd_fusable = false;              // V_h and D_h have the same far-tile block lists
     // work
     double* part = nullptr;     // nblk * ng
     size_t part_bytes = 0;
@@ -1314,6 +1339,7 @@ int build_block_lists(stbem_ctx* c)
     g.ng = c->ng; g.nt = c->nt; g.alpha = c->alpha; g.t = c->t.data();
     g.vx = c->vx.data(); g.vy = c->vy.data(); g.ex = c->ex.data(); g.ey = c->ey.data(); g.len = c->len.data();
     const int ops[5] = {OP_V, OP_K, OP_D, OP_DV, OP_DK}, slots[5] = {0, 1, 2, 4, 5};
+    std::vector<int> far_lists[2];        // separated blocks of V_h and D_h
     TimeBlock tb;
     for (int e = 0; e < 5; ++e) {
         const int op = ops[e], slot = slots[e];
@@ -1335,7 +1361,10 @@ int build_block_lists(stbem_ctx* c)
         c->nlist_gen[slot] = (int)gen.size();
         int rc = upload(c, &c->d_blist[slot], all);
         if (rc) return rc;
+        if (slot == 0 || slot == 2) far_lists[slot / 2].assign(all.end() - (all.size() - touch.size() - gen.size()), all.end());
     }
+    c->vd_fusable = far_lists[0] == far_lists[1];
+    for (int q = 0; q < 9; ++q) c->vd_fusable = c->vd_fusable && c->nlist_far[0][q] == c->nlist_far[2][q];
     return 0;
 }
 
@@ -1383,7 +1412,7 @@ int m0_power_rows(stbem_ctx* c, bool deriv, double* o, hipStream_t s)
     return rc;
 }
 
-int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
+int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd)
 {
     int slot = op_slot(op);
     size_t bytes = (op == STBEM_M0 || op == STBEM_DM0) ? (size_t)c->n * c->nv * sizeof(double)
@@ -1402,6 +1431,7 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
         if (op == STBEM_K) launch_knear<OP_K>(c, 1, o, s);
         int rc = op == STBEM_V ? launch_assemble<OP_V>(c, o, s) : launch_assemble<OP_K>(c, o, s);
         if (rc) return rc;
+        if (op == STBEM_V && fuse_vd) return 0;      // the separated blocks come with D_h's far tiles
         return op == STBEM_V ? launch_far<OP_V>(c, 0, o, s) : launch_far<OP_K>(c, 1, o, s);
     }
     case STBEM_D: {
@@ -1422,14 +1452,24 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s)
                 const int n = std::min(step, c->nlist_far[2][q] - off);
                 dim3 gr((unsigned)(n * tiles)), blk(kWG);
                 const int* b2 = bl + off;
-                KTimer kt(c, kname("k_assemble_dfar", q).c_str(), (double)n * c->ng * c->ng, s);
-                switch (q) {
-                case 3: hipLaunchKernelGGL(k_assemble_dfar<3>, gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o); break;
-                case 4: hipLaunchKernelGGL(k_assemble_dfar<4>, gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o); break;
-                case 5: hipLaunchKernelGGL(k_assemble_dfar<5>, gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o); break;
-                case 6: hipLaunchKernelGGL(k_assemble_dfar<6>, gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o); break;
-                case 7: hipLaunchKernelGGL(k_assemble_dfar<7>, gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o); break;
-                default: hipLaunchKernelGGL(k_assemble_dfar<8>, gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o); break;
+                const std::string kn = kname("k_assemble_dfar", q);
+                KTimer kt(c, fuse_vd ? (kn.substr(0, kn.size() - 1) + ", V>").c_str() : kn.c_str(), (double)n * c->ng * c->ng, s);
+                double* ov = c->mat[0];
+                if (fuse_vd) switch (q) {
+                case 3: hipLaunchKernelGGL((k_assemble_dfar<3, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov); break;
+                case 4: hipLaunchKernelGGL((k_assemble_dfar<4, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov); break;
+                case 5: hipLaunchKernelGGL((k_assemble_dfar<5, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov); break;
+                case 6: hipLaunchKernelGGL((k_assemble_dfar<6, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov); break;
+                case 7: hipLaunchKernelGGL((k_assemble_dfar<7, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov); break;
+                default: hipLaunchKernelGGL((k_assemble_dfar<8, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov); break;
+                }
+                else switch (q) {
+                case 3: hipLaunchKernelGGL((k_assemble_dfar<3, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr); break;
+                case 4: hipLaunchKernelGGL((k_assemble_dfar<4, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr); break;
+                case 5: hipLaunchKernelGGL((k_assemble_dfar<5, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr); break;
+                case 6: hipLaunchKernelGGL((k_assemble_dfar<6, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr); break;
+                case 7: hipLaunchKernelGGL((k_assemble_dfar<7, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr); break;
+                default: hipLaunchKernelGGL((k_assemble_dfar<8, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr); break;
                 }
             }
             bl += c->nlist_far[2][q];
@@ -1949,9 +1989,12 @@ int stbem_assemble(stbem_ctx* c, unsigned mask, void* stream)
     if (!c) return STBEM_EINVAL;
     if (mask == 0 || (mask & ~127u)) return fail(c, STBEM_EINVAL, "bad operator mask %u", mask);
     const unsigned ops[7] = {STBEM_V, STBEM_K, STBEM_D, STBEM_M0, STBEM_DV, STBEM_DK, STBEM_DM0};
+    // V_h and D_h together: V_h's separated blocks are computed by D_h's far
+    // tiles (same block lists); V is assembled first, so its storage exists
+    const bool fuse = (mask & STBEM_V) && (mask & STBEM_D) && c->vd_fusable;
     for (unsigned op : ops)
         if (mask & op) {
-            int rc = assemble_one(c, op, S(stream));
+            int rc = assemble_one(c, op, S(stream), fuse);
             if (rc) return rc;
         }
     return STBEM_OK;
