@@ -119,8 +119,43 @@ __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restri
     __syncthreads();
     const int il = tid / kTile, jl = tid % kTile, I0 = ti * kTile, J0 = tj * kTile;
     const int i = I0 + il, j = J0 + jl;
-    const bool live = i < g.ng && j < g.ng;
-    double v = live && !mirrored(SYM, I0, J0, il, jl) ? entry<OP>(T, O, g, tb, qf, i, j) : 0.0;
+    const bool live = i < g.ng && j < g.ng, own = live && !mirrored(SYM, I0, J0, il, jl);
+    double v = 0.0;
+    if ((OP == OP_V || OP == OP_DV) && tb.d <= 1) {
+        // touching time elements: the rules differ widely in cost (singular
+        // rules for coincident and vertex-sharing segments, Gauss orders by
+        // distance class), so the tile's entries are handed to the lanes in
+        // order of cost and each wave meets one kind of work.  Every entry is
+        // still computed by one lane with the same arithmetic.
+        __shared__ int cnt[kMaxGL + 4];
+        __shared__ short work[kWG];
+        if (tid < kMaxGL + 4) cnt[tid] = 0;
+        __syncthreads();
+        int key = kMaxGL + 3;                                   // nothing to compute: last
+        if (own) {
+            const Piece P = seg_piece(g, i), Q = seg_piece(g, j);
+            const int rel = relation(P, Q);
+            key = rel == 1 ? 0 : rel >= 2 ? 1 : 2 + kMaxGL - q_touch(O, tb, P, Q, sep_ratio(P, Q), q_inc(OP));
+        }
+        const int rank = atomicAdd(&cnt[key], 1);
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int e = 0; e < kMaxGL + 4; ++e) { const int c = cnt[e]; cnt[e] = acc; acc += c; }
+        }
+        __syncthreads();
+        work[cnt[key] + rank] = (short)(own ? tid : -1);
+        __syncthreads();
+        const int e = work[tid];
+        double w = 0.0;
+        if (e >= 0) w = entry<OP>(T, O, g, tb, qf, I0 + e / kTile, J0 + e % kTile);
+        if (e >= 0) stage[e / kTile][e % kTile] = w;
+        __syncthreads();
+        v = own ? stage[il][jl] : 0.0;
+        __syncthreads();
+    } else if (own) {
+        v = entry<OP>(T, O, g, tb, qf, i, j);
+    }
     store_tile(stage, SYM, v, live, block_slot(g, b, k, m) * g.ng * g.ng, g.ng, I0, J0, il, jl, out64);
 }
 
@@ -346,7 +381,7 @@ __device__ __forceinline__ void far_dpair(const Tables& T, const TimeBlock& tb, 
 // pieces of segments I0 + s and J0 + r are pieces 2s+1, 2s+2 and 2r+1, 2r+2 of
 // the tile, and V_h's tiles are the same symmetric 16 x 16 tiles.
 template <int Q, bool WV>
-__global__ __launch_bounds__(kWG) void k_assemble_dfar(Geom g, const Tables* __restrict__ Tg,
+__global__ __launch_bounds__(kWG, (Q == 3 || (Q == 4 && !WV)) ? 3 : 1) void k_assemble_dfar(Geom g, const Tables* __restrict__ Tg,
                                                        const int* __restrict__ blist, int tiles_1d,
                                                        double* __restrict__ out64, double* __restrict__ outv)
 {
