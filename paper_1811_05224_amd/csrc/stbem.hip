@@ -641,10 +641,35 @@ __global__ __launch_bounds__(kWG) void k_m0_tri(Geom g, Mesh2 mesh, const Tables
     }
     __syncthreads();
     const long long lrow = lrow0 + blockIdx.x / nchunk;       // row within the chunk
-    const int t = (int)(blockIdx.x % nchunk) * kWG + threadIdx.x;
-    if (t >= mesh.ntri) return;
+    int t = (int)(blockIdx.x % nchunk) * kWG + threadIdx.x;
     const long long row = row0 + lrow;          // row = k * ng + i
     const int k = (int)(row / g.ng), i = (int)(row % g.ng);
+    if (FIRST) {
+        // the orders differ by a factor of up to 4^3 in nodes between near and
+        // far triangles of one segment: the workgroup's triangles are handed to
+        // the lanes in order of cost, so that each wave meets one kind of work
+        // (each triangle is still computed by one lane with the same arithmetic)
+        __shared__ int cnt[kMaxGL + 3];
+        __shared__ int work[kWG];
+        if (threadIdx.x < kMaxGL + 3) cnt[threadIdx.x] = 0;
+        __syncthreads();
+        int key = kMaxGL + 2;                                   // outside the mesh: last
+        if (t < mesh.ntri) {
+            const int q0 = m0_first_order(MO, g, seg_piece(g, i), load_tri3(mesh, t), 3);
+            key = q0 == 0 ? 0 : 1 + kMaxGL - q0;                // near pairs, then by order
+        }
+        const int rank = atomicAdd(&cnt[key], 1);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int e = 0; e < kMaxGL + 3; ++e) { const int c = cnt[e]; cnt[e] = acc; acc += c; }
+        }
+        __syncthreads();
+        work[cnt[key] + rank] = t;
+        __syncthreads();
+        t = work[threadIdx.x];
+    }
+    if (t >= mesh.ntri) return;
     // k >= 1: the kernel varies on the time scale sqrt(4 t_k / alpha); k = 0:
     // the order follows the distance of the triangle (m0_tri_moments)
     int qs = 3;

@@ -225,6 +225,27 @@ SDEV void seg_log_potential3(const M0Tables& D, const Piece& S, const Tri3& tr, 
 
 // the three moments int_{gamma_i} int_omega hat_v G_k ds dy of triangle t;
 // FIRST: rows of the first time element (k = 0, singular kernel), else k >= 1
+// First time element: the Gauss order of the regular rule for segment S and
+// triangle tr (0: the pair is near, eta < near_ratio, and takes the rule with
+// the logarithm split off).  The ln r singularity sits at distance eta * size;
+// the factor e^{-z}, z = alpha r^2 / (4 t_1), changes by dz along the elements.
+SDEV int m0_first_order(const M0Orders& MO, const Geom& g, const Piece& S, const Tri3& tr, int qs)
+{
+    Tri tt;
+    tt.ax = tr.ax; tt.ay = tr.ay; tt.bx = tr.bx; tt.by = tr.by; tt.cx = tr.cx; tt.cy = tr.cy;
+    const double dx1 = tr.bx - tr.ax, dy1 = tr.by - tr.ay, dx2 = tr.cx - tr.ax, dy2 = tr.cy - tr.ay;
+    const double diam = sqrt(fmax(fmax(dx1 * dx1 + dy1 * dy1, dx2 * dx2 + dy2 * dy2),
+                                  (dx2 - dx1) * (dx2 - dx1) + (dy2 - dy1) * (dy2 - dy1)));
+    const double size = fmax(diam, S.len);
+    const double eta = seg_tri_dist(S, tt) / size;
+    if (eta < MO.near_ratio) return 0;
+    const int qn = eta < 1.0 ? kMaxGL : eta < 2.0 ? 12 : eta < 4.0 ? 8 : eta < 8.0 ? 6 : eta < 16.0 ? 5 : 4;
+    const double w2 = 0.25 * g.alpha / g.t[1], rlo = eta * size;
+    const int qz = q_slope(w2 * rlo * rlo, w2 * size * (2.0 * rlo + size), MO.q_tol, MO.z_floor);
+    int q0 = qn > qz ? qn : qz;
+    return q0 > qs ? q0 : qs;
+}
+
 template <bool DERIV, bool FIRST>
 SDEV void m0_tri_moments(const Tables& T, const M0Tables& D, const M0Orders& MO, const Geom& g,
                          const Mesh2& m, const M0Poly& PP, int k, int i, int t, int qs, double* out)
@@ -232,14 +253,8 @@ SDEV void m0_tri_moments(const Tables& T, const M0Tables& D, const M0Orders& MO,
     Piece S = seg_piece(g, i);
     Tri3 tr = load_tri3(m, t);
     if (FIRST) {
-        Tri tt;
-        tt.ax = tr.ax; tt.ay = tr.ay; tt.bx = tr.bx; tt.by = tr.by; tt.cx = tr.cx; tt.cy = tr.cy;
-        double dx1 = tr.bx - tr.ax, dy1 = tr.by - tr.ay, dx2 = tr.cx - tr.ax, dy2 = tr.cy - tr.ay;
-        double diam = sqrt(fmax(fmax(dx1 * dx1 + dy1 * dy1, dx2 * dx2 + dy2 * dy2),
-                                (dx2 - dx1) * (dx2 - dx1) + (dy2 - dy1) * (dy2 - dy1)));
-        double size = fmax(diam, S.len);
-        double eta = seg_tri_dist(S, tt) / size;
-        if (eta < MO.near_ratio) {
+        const int q0 = m0_first_order(MO, g, S, tr, qs);
+        if (q0 == 0) {
             double sm[3], lg[3];
             m0_regular3(T, S, tr, MO.qs_near, MO.qt_near, [&](double r2) { return m0_smooth0<DERIV>(g, r2, 0.5 * log(r2)); }, sm);
             seg_log_potential3(D, S, tr, lg);
@@ -247,13 +262,6 @@ SDEV void m0_tri_moments(const Tables& T, const M0Tables& D, const M0Orders& MO,
             for (int v = 0; v < 3; ++v) out[v] = sm[v] - B * lg[v];
             return;
         }
-        // ln r singularity at distance eta * size; the factor e^{-z},
-        // z = alpha r^2 / (4 t_1), changes by dz along the elements
-        int qn = eta < 1.0 ? kMaxGL : eta < 2.0 ? 12 : eta < 4.0 ? 8 : eta < 8.0 ? 6 : eta < 16.0 ? 5 : 4;
-        const double w2 = 0.25 * g.alpha / g.t[1], rlo = eta * size;
-        const int qz = q_slope(w2 * rlo * rlo, w2 * size * (2.0 * rlo + size), MO.q_tol, MO.z_floor);
-        int q0 = qn > qz ? qn : qz;
-        q0 = q0 > qs ? q0 : qs;
         m0_regular3(T, S, tr, q0, q0, [&](double r2) { return m0_kernel<DERIV>(g, 0, r2); }, out);
         return;
     }
