@@ -473,6 +473,8 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
     __shared__ double mom[kDP][kDP][5];
     __shared__ unsigned char form[kTile][kTile];   // 0 by-parts, 1 raw, 2 outside the matrix
     __shared__ short list[kDP * kDP];              // pairs to compute, costly ones first
+    __shared__ unsigned char keys[kDP * kDP];      // cost class of each pair
+    __shared__ int cnt[kMaxGL + 3];
     __shared__ int nlist[2];
     __shared__ double stage[kTile][kTile + 1];
     const int tid = threadIdx.x;
@@ -521,28 +523,38 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
     if (inside) { si = dual_support(g, i); sj = dual_support(g, j); }
     double val = 0.0;
 
-    // Pairs a pass needs, compacted so that no lane idles on unneeded pairs;
-    // for the by-parts pass the singular pairs (many more nodes) go first so
-    // that they are spread over the lanes of the first round.  The order of
-    // the list does not change any result: each pair's moments are computed
-    // by one lane with the same arithmetic.
+    // Pairs a pass needs, compacted so that no lane idles on unneeded pairs
+    // and ordered by the cost of their rule (singular rules first, then by
+    // Gauss order), so that the waves of one round meet one kind of work.
+    // The order does not change any result: each pair's moments are
+    // computed by one lane with the same arithmetic.
     auto build_list = [&](int f) {
-        if (tid < 2) nlist[tid] = 0;
-        __syncthreads();
-        if (f == 0)
-            for (int e = tid; e < kDP * kDP; e += kWG) {
-                const int u = e / kDP, v = e % kDP;
-                if (needs(u, v, f) && relation(pc[0][u], pc[1][v])) list[atomicAdd(&nlist[0], 1)] = (short)e;
-            }
-        __syncthreads();
-        if (tid == 0) nlist[1] = nlist[0];
+        if (tid < kMaxGL + 3) cnt[tid] = 0;
         __syncthreads();
         for (int e = tid; e < kDP * kDP; e += kWG) {
             const int u = e / kDP, v = e % kDP;
-            if (needs(u, v, f) && !(f == 0 && relation(pc[0][u], pc[1][v]))) list[atomicAdd(&nlist[1], 1)] = (short)e;
+            int key = kMaxGL + 2;                      // not needed by this pass
+            if (needs(u, v, f)) {
+                const Piece& P = pc[0][u];
+                const Piece& Q = pc[1][v];
+                key = relation(P, Q) ? 0 : 1 + kMaxGL - q_touch(O, tb, P, Q, sep_ratio(P, Q), 0);
+                atomicAdd(&cnt[key], 1);
+            }
+            keys[e] = (unsigned char)key;
         }
         __syncthreads();
-        return nlist[1];
+        if (tid == 0) {
+            int acc = 0;
+            for (int c = 0; c < kMaxGL + 2; ++c) { const int n = cnt[c]; cnt[c] = acc; acc += n; }
+            nlist[0] = acc;
+        }
+        __syncthreads();
+        for (int e = tid; e < kDP * kDP; e += kWG) {
+            const int key = keys[e];
+            if (key < kMaxGL + 2) list[atomicAdd(&cnt[key], 1)] = (short)e;
+        }
+        __syncthreads();
+        return nlist[0];
     };
 
     // pass 1: raw-form entries
