@@ -656,19 +656,38 @@ __global__ __launch_bounds__(kWG) void k_m0_tri(Geom g, Mesh2 mesh, const Tables
     int t = (int)(blockIdx.x % nchunk) * kWG + threadIdx.x;
     const long long row = row0 + lrow;          // row = k * ng + i
     const int k = (int)(row / g.ng), i = (int)(row % g.ng);
-    if (FIRST) {
-        // the orders differ by a factor of up to 4^3 in nodes between near and
-        // far triangles of one segment: the workgroup's triangles are handed to
-        // the lanes in order of cost, so that each wave meets one kind of work
-        // (each triangle is still computed by one lane with the same arithmetic)
+    if (FIRST || PP.n[k] > 0) {
+        // The cost of a pair differs widely inside a row: in the first time
+        // element the orders (up to 4^3 in nodes between near and far
+        // triangles), in later ones the kernel (power series where
+        // a = alpha r^2/4 <= amax, two E1 values beyond).  The workgroup's
+        // triangles are handed to the lanes in order of cost, so that each
+        // wave meets one kind of work (each triangle is still computed by one
+        // lane with the same arithmetic).
         __shared__ int cnt[kMaxGL + 3];
         __shared__ int work[kWG];
         if (threadIdx.x < kMaxGL + 3) cnt[threadIdx.x] = 0;
         __syncthreads();
         int key = kMaxGL + 2;                                   // outside the mesh: last
         if (t < mesh.ntri) {
-            const int q0 = m0_first_order(MO, g, seg_piece(g, i), load_tri3(mesh, t), 3);
-            key = q0 == 0 ? 0 : 1 + kMaxGL - q0;                // near pairs, then by order
+            const Piece S = seg_piece(g, i);
+            const Tri3 tr = load_tri3(mesh, t);
+            if (FIRST) {
+                const int q0 = m0_first_order(MO, g, S, tr, 3);
+                key = q0 == 0 ? 0 : 1 + kMaxGL - q0;            // near pairs, then by order
+            } else {
+                Tri tt;
+                tt.ax = tr.ax; tt.ay = tr.ay; tt.bx = tr.bx; tt.by = tr.by; tt.cx = tr.cx; tt.cy = tr.cy;
+                const double dlo = seg_tri_dist(S, tt);
+                double dhi2 = 0.0;
+                const double vx[3] = {tr.ax, tr.bx, tr.cx}, vy[3] = {tr.ay, tr.by, tr.cy};
+                for (int e = 0; e < 2; ++e) {
+                    const double px = S.ax + e * S.len * S.ex, py = S.ay + e * S.len * S.ey;
+                    for (int v = 0; v < 3; ++v) dhi2 = fmax(dhi2, (vx[v] - px) * (vx[v] - px) + (vy[v] - py) * (vy[v] - py));
+                }
+                const double q4 = 0.25 * g.alpha, amax = PP.amax[k];
+                key = q4 * dlo * dlo > amax ? 0 : (q4 * dhi2 <= amax ? 2 : 1);   // E1 only, mixed, series only
+            }
         }
         const int rank = atomicAdd(&cnt[key], 1);
         __syncthreads();
