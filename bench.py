@@ -34,28 +34,38 @@ FP64_PEAK_TFLOPS = 78.6
 #   instructions (inactive lanes included), profiles/counters_fp64_medium.md;
 #   HBM bytes = 2 x FETCH_SIZE + WRITE_SIZE (KiB x 1024), the factors from a
 #   1 GiB device copy read by the same counters, profiles/counters_hbm_medium.md.
-# A kernel changed after its counters were taken has no entry here.
-FLOP_PER_UNIT = {'k_assemble_dnear': 36715.4,
-    'k_m0_tri<false, false>': 22827.6,
-    'k_m0_tri<false, true>': 78802.3,
-    'k_assemble<0>': 19182.9,
+# A kernel changed after its counters were taken has no entry here.  The
+# fused far tiles k_assemble_dfar<q, true> count D_h entries and write as
+# many V_h entries (16 B per unit).
+FLOP_PER_UNIT = {'k_assemble_dfar<3, true>': 4626.4,
+    'k_assemble_vkfar<1, 4>': 2524.6,
+    'k_assemble_dnear': 30883.7,
+    'k_m0_tri<false, false>': 20555.1,
+    'k_assemble_dfar<4, true>': 16307.9,
+    'k_m0_tri<false, true>': 61752.0,
     'k_assemble_knear<1>': 12373.6,
+    'k_assemble<0>': 10023.0,
+    'k_assemble_vkfar<1, 5>': 7730.4,
     'k_m0_pow': 35571.0,
     'k_m0_pow_gather': 6.0,
     'k_m0_pow_apply': 81.0,
     'k_m0_gather': 6.0}
 HBM_BYTES_PER_UNIT = {'k_gemv_n_vec<double>': 8.035,
-    'k_assemble_dnear': 8.07,
-    'k_m0_tri<false, false>': 24.099,
-    'k_m0_tri<false, true>': 24.49,
+    'k_assemble_dfar<3, true>': 16.002,
+    'k_assemble_vkfar<1, 4>': 9.627,
+    'k_assemble_dnear': 8.074,
+    'k_m0_tri<false, false>': 24.094,
+    'k_assemble_dfar<4, true>': 16.007,
     'k_gemv_n_vec<float>': 4.035,
-    'k_assemble<0>': 8.049,
+    'k_m0_tri<false, true>': 24.534,
     'k_assemble_knear<1>': 9.659,
+    'k_assemble<0>': 8.055,
+    'k_assemble_vkfar<1, 5>': 9.631,
     'k_m0_pow': 888.5,
     'k_gemv_n_vec<float hi+lo>': 8.035,
-    'k_m0_pow_gather': 70.92,
+    'k_m0_pow_gather': 70.272,
     'k_m0_pow_apply': 10.821,
-    'k_m0_gather': 67.238}
+    'k_m0_gather': 67.239}
 # bytes streamed per stored entry by the matrix-vector kernels
 GEMV_BYTES = {"k_gemv_n_vec<double>": 8, "k_gemv_t_vec<double>": 8, "k_gemv_n_vec<float hi+lo>": 8,
               "k_gemv_t_vec<float hi+lo>": 8, "k_gemv_n_vec<float>": 4, "k_gemv_t_vec<float>": 4}

@@ -1543,8 +1543,8 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd)
                 const int n = std::min(step, c->nlist_far[2][q] - off);
                 dim3 gr((unsigned)(n * tiles)), blk(kWG);
                 const int* b2 = bl + off;
-                const std::string kn = kname("k_assemble_dfar", q);
-                KTimer kt(c, fuse_vd ? (kn.substr(0, kn.size() - 1) + ", V>").c_str() : kn.c_str(), (double)n * c->ng * c->ng, s);
+                const std::string kn = std::string("k_assemble_dfar<") + std::to_string(q) + (fuse_vd ? ", true>" : ", false>");
+                KTimer kt(c, kn.c_str(), (double)n * c->ng * c->ng, s);
                 double* ov = c->mat[0];
                 if (fuse_vd) switch (q) {
                 case 3: hipLaunchKernelGGL((k_assemble_dfar<3, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov); break;
