@@ -1006,20 +1006,36 @@ __global__ __launch_bounds__(kWG) void k_gemv_t_vec(const T* __restrict__ A, con
 }
 
 // y[k][i] = sum_{m<=k} part[b(k,m)][i]  (trans: y[m][j] = sum_{k>=m} part[b(k,m)][j])
+// pass 2: y[(blk, i)] = sum of the partials of block row blk (column blk for
+// the transpose).  A workgroup takes 32 outputs; 8 lanes per output sum
+// fixed contiguous chunks of the partials, and the 8 chunk sums are added in
+// chunk order, so the result does not depend on the launch.
+constexpr int kRedSplit = 8, kRedOut = kWG / kRedSplit;
 __global__ __launch_bounds__(kWG) void k_gemv_reduce(const double* __restrict__ part, double* __restrict__ y,
                                                      int ng, int nt, int trans)
 {
-    long long e = (long long)blockIdx.x * kWG + threadIdx.x;
-    if (e >= (long long)ng * nt) return;
-    int blk = (int)(e / ng), i = (int)(e % ng);
+    __shared__ double red[kRedSplit][kRedOut];
+    const int seg = threadIdx.x / kRedOut, il = threadIdx.x % kRedOut;
+    const long long e = (long long)blockIdx.x * kRedOut + il;
     double s = 0.0;
-    if (!trans) {
-        const long long b0 = (long long)blk * (blk + 1) / 2;
-        for (int m = 0; m <= blk; ++m) s += part[(b0 + m) * ng + i];
-    } else {
-        for (int k = blk; k < nt; ++k) s += part[((long long)k * (k + 1) / 2 + blk) * ng + i];
+    if (e < (long long)ng * nt) {
+        const int blk = (int)(e / ng), i = (int)(e % ng);
+        const int lo = trans ? blk : 0, len = trans ? nt - blk : blk + 1;
+        const int a = lo + (int)((long long)len * seg / kRedSplit), b = lo + (int)((long long)len * (seg + 1) / kRedSplit);
+        if (!trans) {
+            const long long b0 = (long long)blk * (blk + 1) / 2;
+            for (int m = a; m < b; ++m) s += part[(b0 + m) * ng + i];
+        } else {
+            for (int k = a; k < b; ++k) s += part[((long long)k * (k + 1) / 2 + blk) * ng + i];
+        }
     }
-    y[e] = s;
+    red[seg][il] = s;
+    __syncthreads();
+    if (seg == 0 && e < (long long)ng * nt) {
+        double t = red[0][il];
+        for (int c = 1; c < kRedSplit; ++c) t += red[c][il];
+        y[e] = t;
+    }
 }
 
 // dense row-major M (rows x cols): y = M x (a wavefront per row)
@@ -1697,7 +1713,7 @@ int packed_apply(stbem_ctx* c, const double* A, const float* hi, const float* lo
     }
     HIPCHK(c, hipGetLastError());
     kt.stop();
-    hipLaunchKernelGGL(k_gemv_reduce, dim3(grid1(c->n)), dim3(kWG), 0, s, c->part, y, c->ng, c->nt, trans);
+    hipLaunchKernelGGL(k_gemv_reduce, dim3((unsigned)((c->n + kRedOut - 1) / kRedOut)), dim3(kWG), 0, s, c->part, y, c->ng, c->nt, trans);
     HIPCHK(c, hipGetLastError());
     return 0;
 }
