@@ -2256,7 +2256,7 @@ int gmres(const SolveOp& o, const double* f, double* w, double tol, int maxit, i
         dev_free(c, Q); dev_free(c, dw.part); dev_free(c, hdev); dev_free(c, v);
         return fail(c, STBEM_ENOMEM, "GMRES workspace (%d vectors of %lld)", maxit + 1, n);
     }
-    std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), gv(maxit + 1, 0.0), hh(maxit + 2);
+    std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), gv(maxit + 1, 0.0), hh(2 * (maxit + 2));
     int rc = 0, j = 0;
     double beta = 0.0;
     *iters = 0; *relres = 0.0;
@@ -2276,19 +2276,21 @@ int gmres(const SolveOp& o, const double* f, double* w, double tol, int maxit, i
     for (j = 0; j < maxit; ++j) {
         double* qj1 = Q + (long long)(j + 1) * ldq;
         if ((rc = op_apply(o, Q + (long long)j * ldq, v, s))) goto out;
-        // classical Gram-Schmidt, twice
+        // classical Gram-Schmidt, twice: the coefficients stay on the device
+        // for the subtraction (pass p at hdev + p (maxit + 1), the norm after
+        // them), so the host waits once per iteration
         for (int pass = 0; pass < 2; ++pass) {
-            if ((rc = dots(c, dw, Q, ldq, j + 1, v, hdev, s))) goto out;
-            hipLaunchKernelGGL(k_basis_sub, dim3(grid1(n)), dim3(kWG), 0, s, (const double*)Q, ldq, j + 1, (const double*)hdev, v, n);
-            HIPCHK(c, hipMemcpyAsync(hh.data(), hdev, (size_t)(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(c, hipStreamSynchronize(s));
-            for (int i = 0; i <= j; ++i) H[(size_t)j * (maxit + 1) + i] += hh[i];
+            double* hp = hdev + (size_t)pass * (maxit + 1);
+            if ((rc = dots(c, dw, Q, ldq, j + 1, v, hp, s))) goto out;
+            hipLaunchKernelGGL(k_basis_sub, dim3(grid1(n)), dim3(kWG), 0, s, (const double*)Q, ldq, j + 1, (const double*)hp, v, n);
         }
-        if ((rc = dots(c, dw, v, ldq, 1, v, hdev, s))) goto out;
-        HIPCHK(c, hipMemcpyAsync(hh.data(), hdev, sizeof(double), hipMemcpyDeviceToHost, s));
+        if ((rc = dots(c, dw, v, ldq, 1, v, hdev + (size_t)2 * (maxit + 1), s))) goto out;
+        HIPCHK(c, hipMemcpyAsync(hh.data(), hdev, (size_t)(2 * (maxit + 1) + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
+        for (int pass = 0; pass < 2; ++pass)
+            for (int i = 0; i <= j; ++i) H[(size_t)j * (maxit + 1) + i] += hh[(size_t)pass * (maxit + 1) + i];
         {
-            double hn = std::sqrt(hh[0]);
+            double hn = std::sqrt(hh[(size_t)2 * (maxit + 1)]);
             double* col = &H[(size_t)j * (maxit + 1)];
             col[j + 1] = hn;
             if (hn > 0.0)
