@@ -714,6 +714,48 @@ __global__ __launch_bounds__(kWG) void k_m0_tri(Geom g, Mesh2 mesh, const Tables
     o[0] = mom[0]; o[1] = mom[1]; o[2] = mom[2];
 }
 
+// M0 rows of time elements k0 .. k0+nk-1 (k0 >= 1) for one segment and a
+// chunk of triangles per workgroup: a lane takes one triangle for all these
+// rows, in runs of rows with the same rule (at most kM0Group at a time), so
+// that the E1 values at the shared time boundaries are computed once.
+template <bool DERIV>
+__global__ __launch_bounds__(kWG, 3) void k_m0_rows(Geom g, Mesh2 mesh, const Tables* __restrict__ Tg, M0Orders MO,
+                                                 M0Poly PP, long long row0, int k0, int nk, int nchunk,
+                                                 double* __restrict__ scratch)
+{
+    __shared__ Tables T;
+    {
+        const double* src = reinterpret_cast<const double*>(Tg);
+        double* dst = reinterpret_cast<double*>(&T);
+        for (int e = threadIdx.x; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
+    }
+    __syncthreads();
+    const int i = (int)(blockIdx.x / nchunk);
+    const int t = (int)(blockIdx.x % nchunk) * kWG + threadIdx.x;
+    if (t >= mesh.ntri) return;
+    const Piece S = seg_piece(g, i);
+    const Tri3 tr = load_tri3(mesh, t);
+    auto order = [&](int k) {
+        const int q = q_time(fmax(g.len[i], MO.omax), g.t[k], g.alpha) + 1;
+        return q < 4 ? 4 : q;
+    };
+    for (int kk = k0; kk < k0 + nk;) {
+        const int qs = order(kk);
+        int run = 1;
+        while (run < kM0Group && kk + run < k0 + nk && order(kk + run) == qs) ++run;
+        double mom[3 * kM0Group];
+        m0_rows_moments<DERIV>(T, g, PP, S, tr, kk, run, qs, mom);
+#pragma unroll
+        for (int r = 0; r < kM0Group; ++r) {
+            if (r < run) {
+                double* o = scratch + (((long long)(kk + r) * g.ng + i - row0) * mesh.ntri + t) * 3;
+                o[0] = mom[3 * r]; o[1] = mom[3 * r + 1]; o[2] = mom[3 * r + 2];
+            }
+        }
+        kk += run;
+    }
+}
+
 // pass 2: M0[row][j] = sum over the triangles of vertex j (fixed order)
 __global__ __launch_bounds__(kWG) void k_m0_gather(Mesh2 mesh, const int* __restrict__ v2t_loc, long long row0,
                                                    int nchunk, const double* __restrict__ scratch,
@@ -1588,33 +1630,33 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd)
     case STBEM_DK: launch_knear<OP_DK>(c, 5, o, s); return launch_assemble<OP_DK>(c, o, s);
     case STBEM_M0:
     case STBEM_DM0: {
-        // rows in chunks whose moment scratch stays below 1 GiB
+        // whole time rows in chunks whose moment scratch stays below 1 GiB:
+        // the first time element by the per-row kernel with the singular
+        // rules, the later rows below the power-series split by k_m0_rows
         long long per_row = (long long)c->ntri * 3 * (long long)sizeof(double);
-        long long rows = (1LL << 30) / (per_row > 0 ? per_row : 1);
-        rows = rows < 1 ? 1 : (rows > c->n ? c->n : rows);
-        double* scratch = (double*)dev_alloc(c, (size_t)(rows * per_row));
-        if (!scratch) return fail(c, STBEM_ENOMEM, "M0 scratch of %lld bytes", rows * per_row);
+        long long krows = (1LL << 30) / (per_row * c->ng > 0 ? per_row * c->ng : 1);
+        krows = krows < 1 ? 1 : (krows > c->m0_ksplit ? (c->m0_ksplit > 0 ? c->m0_ksplit : 1) : krows);
+        double* scratch = (double*)dev_alloc(c, (size_t)(krows * c->ng * per_row));
+        if (!scratch) return fail(c, STBEM_ENOMEM, "M0 scratch of %lld bytes", krows * c->ng * per_row);
         int tchunk = (c->ntri + kWG - 1) / kWG, vchunk = (c->nv + kWG - 1) / kWG;
         int rc = 0;
-        const long long nrow = (long long)c->m0_ksplit * c->ng;   // rows of the per-row kernels
-        for (long long r0 = 0; r0 < nrow && !rc; r0 += rows) {
-            long long nr = nrow - r0 < rows ? nrow - r0 : rows;
-            // rows r0 .. r0+nr: those of the first time element (row < ng) take
-            // the kernel with the singular rules, the others the regular one
-            long long nf = r0 < c->ng ? std::min<long long>(nr, c->ng - r0) : 0, nl = nr - nf;
-            if (nf > 0) {
-                KTimer kt(c, op == STBEM_M0 ? "k_m0_tri<false, true>" : "k_m0_tri<true, true>", (double)nf * c->ntri, s);
+        for (int kc0 = 0; kc0 < c->m0_ksplit && !rc; kc0 += (int)krows) {
+            const int kc1 = (int)std::min<long long>(kc0 + krows, c->m0_ksplit);
+            const long long r0 = (long long)kc0 * c->ng, nr = (long long)(kc1 - kc0) * c->ng;
+            if (kc0 == 0) {
+                KTimer kt(c, op == STBEM_M0 ? "k_m0_tri<false, true>" : "k_m0_tri<true, true>", (double)c->ng * c->ntri, s);
                 if (op == STBEM_M0)
-                    hipLaunchKernelGGL((k_m0_tri<false, true>), dim3((unsigned)(nf * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), r0, 0LL, tchunk, scratch);
+                    hipLaunchKernelGGL((k_m0_tri<false, true>), dim3((unsigned)(c->ng * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), 0LL, 0LL, tchunk, scratch);
                 else
-                    hipLaunchKernelGGL((k_m0_tri<true, true>), dim3((unsigned)(nf * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), r0, 0LL, tchunk, scratch);
+                    hipLaunchKernelGGL((k_m0_tri<true, true>), dim3((unsigned)(c->ng * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), 0LL, 0LL, tchunk, scratch);
             }
-            if (nl > 0) {
-                KTimer kt(c, op == STBEM_M0 ? "k_m0_tri<false, false>" : "k_m0_tri<true, false>", (double)nl * c->ntri, s);
+            const int k0 = kc0 > 0 ? kc0 : 1;
+            if (k0 < kc1) {
+                KTimer kt(c, op == STBEM_M0 ? "k_m0_rows<false>" : "k_m0_rows<true>", (double)(kc1 - k0) * c->ng * c->ntri, s);
                 if (op == STBEM_M0)
-                    hipLaunchKernelGGL((k_m0_tri<false, false>), dim3((unsigned)(nl * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), r0, nf, tchunk, scratch);
+                    hipLaunchKernelGGL((k_m0_rows<false>), dim3((unsigned)(c->ng * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->m0ord, m0poly(c), r0, k0, kc1 - k0, tchunk, scratch);
                 else
-                    hipLaunchKernelGGL((k_m0_tri<true, false>), dim3((unsigned)(nl * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), r0, nf, tchunk, scratch);
+                    hipLaunchKernelGGL((k_m0_rows<true>), dim3((unsigned)(c->ng * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->m0ord, m0poly(c), r0, k0, kc1 - k0, tchunk, scratch);
             }
             KTimer kt(c, "k_m0_gather", (double)nr * c->nv, s);
             hipLaunchKernelGGL(k_m0_gather, dim3((unsigned)(nr * vchunk)), dim3(kWG), 0, s, mesh(c), (const int*)c->d_v2t_loc, r0, vchunk, (const double*)scratch, o);

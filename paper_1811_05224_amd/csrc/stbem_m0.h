@@ -225,6 +225,92 @@ SDEV void seg_log_potential3(const M0Tables& D, const Piece& S, const Tri3& tr, 
 
 // the three moments int_{gamma_i} int_omega hat_v G_k ds dy of triangle t;
 // FIRST: rows of the first time element (k = 0, singular kernel), else k >= 1
+// Rows k0 .. k0+nr-1 (k0 >= 1, nr <= kM0Group) of one segment against one
+// triangle with one rule (qs on the segment, qs x qs collapsed on the
+// triangle), the rows evaluated together at every node: consecutive rows
+// share their time boundary t_k, so each E1 (or Ein) value at a node is
+// computed once instead of twice; rows inside their power-series range take
+// the series.  Row r's three moments go to out[3r .. 3r+2].  Every row gets
+// the same operations, in the same order, as with the per-row kernel.
+constexpr int kM0Group = 4;
+
+template <bool DERIV>
+SDEV void m0_row_values(const Geom& g, const M0Poly& PP, int k0, int nr, double r2, double* val)
+{
+    const double a = 0.25 * g.alpha * r2, sc = (DERIV ? 1.0 : g.alpha) * kInv4Pi;
+    double Eprev = 0.0, einprev = 0.0, xprev = 0.0;
+    int have = 0;                              // 1: E1 at t_k known, 2: Ein at t_k known
+#pragma unroll
+    for (int r = 0; r < kM0Group; ++r) {
+        if (r >= nr) continue;
+        const int k = k0 + r;
+        if (PP.n[k] > 0 && a <= PP.amax[k]) {
+            val[r] = sc * m0_poly((DERIV ? PP.cd : PP.c) + (long long)k * kPolyMax, PP.n[k], a);
+            have = 0;
+            continue;
+        }
+        const double t1 = g.t[k + 1], t0 = g.t[k];
+        const double z1 = a / t1, z0 = a / t0;
+        double dE, x1 = 0.0, x0 = 0.0;
+        if (z0 <= 2.0) {
+            const double e0 = have == 2 ? einprev : ein(z0);
+            const double e1v = ein(z1);
+            dE = log(t1 / t0) + e1v - e0;            // no ln a cancellation
+            if (DERIV) { x1 = exp(-z1); x0 = have == 2 ? xprev : exp(-z0); }
+            einprev = e1v; xprev = x1; have = 2;
+        } else {
+            double E0;
+            if (have == 1) { E0 = Eprev; x0 = xprev; }
+            else E0 = e1t<DERIV>(z0, x0);
+            const double E1v = e1t<DERIV>(z1, x1);
+            dE = E1v - E0;
+            Eprev = E1v; xprev = x1; have = 1;
+        }
+        val[r] = DERIV ? (dE - x1 + x0) * kInv4Pi : g.alpha * kInv4Pi * dE;
+    }
+}
+
+template <bool DERIV>
+SDEV void m0_rows_moments(const Tables& T, const Geom& g, const M0Poly& PP, const Piece& S, const Tri3& tr,
+                          int k0, int nr, int qs, double* out)
+{
+    const double e1x = tr.bx - tr.ax, e1y = tr.by - tr.ay, e2x = tr.cx - tr.ax, e2y = tr.cy - tr.ay;
+    const double area2 = fabs(e1x * e2y - e1y * e2x);
+    double o[kM0Group][3];
+#pragma unroll
+    for (int r = 0; r < kM0Group; ++r) o[r][0] = o[r][1] = o[r][2] = 0.0;
+    for (int a = 0; a < qs; ++a) {
+        const double u = T.gl_x[qs][a], wu = T.gl_w[qs][a] * (1.0 - u);
+        for (int b = 0; b < qs; ++b) {
+            const double v = T.gl_x[qs][b] * (1.0 - u), w = wu * T.gl_w[qs][b] * area2;
+            const double yx = tr.ax + u * e1x + v * e2x, yy = tr.ay + u * e1y + v * e2y;
+            double inner[kM0Group];
+#pragma unroll
+            for (int r = 0; r < kM0Group; ++r) inner[r] = 0.0;
+            for (int c = 0; c < qs; ++c) {
+                const double s = S.len * T.gl_x[qs][c];
+                const double dx = S.ax + s * S.ex - yx, dy = S.ay + s * S.ey - yy;
+                double val[kM0Group];
+                m0_row_values<DERIV>(g, PP, k0, nr, dx * dx + dy * dy, val);
+#pragma unroll
+                for (int r = 0; r < kM0Group; ++r)
+                    if (r < nr) inner[r] += T.gl_w[qs][c] * val[r];
+            }
+#pragma unroll
+            for (int r = 0; r < kM0Group; ++r) {
+                if (r >= nr) continue;
+                const double in = inner[r] * w;
+                o[r][0] += (1.0 - u - v) * in; o[r][1] += u * in; o[r][2] += v * in;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kM0Group; ++r) {
+        if (r >= nr) continue;
+        out[3 * r] = o[r][0] * S.len; out[3 * r + 1] = o[r][1] * S.len; out[3 * r + 2] = o[r][2] * S.len;
+    }
+}
+
 // First time element: the Gauss order of the regular rule for segment S and
 // triangle tr (0: the pair is near, eta < near_ratio, and takes the rule with
 // the logarithm split off).  The ln r singularity sits at distance eta * size;
