@@ -635,7 +635,7 @@ __global__ __launch_bounds__(kWG) void k_entries(Geom g, const Tables* __restric
 
 // M_h^0, pass 1: the three barycentric moments of every (row, triangle) pair
 // of a chunk of rows into scratch[row - row0][t][v].
-template <bool DERIV, bool FIRST>
+template <bool DERIV, bool FIRST, int PART = 0>
 __global__ __launch_bounds__(kWG) void k_m0_tri(Geom g, Mesh2 mesh, const Tables* __restrict__ Tg,
                                                 const M0Tables* __restrict__ Dg, M0Orders MO, M0Poly PP,
                                                 long long row0, long long lrow0, int nchunk,
@@ -701,6 +701,11 @@ __global__ __launch_bounds__(kWG) void k_m0_tri(Geom g, Mesh2 mesh, const Tables
         t = work[threadIdx.x];
     }
     if (t >= mesh.ntri) return;
+    if (FIRST && PART != 0) {
+        // one kind of pair per launch: the other kind is left to the other launch
+        const bool near = m0_first_order(MO, g, seg_piece(g, i), load_tri3(mesh, t), 3) == 0;
+        if (near != (PART == 2)) return;
+    }
     // k >= 1: the kernel varies on the time scale sqrt(4 t_k / alpha); k = 0:
     // the order follows the distance of the triangle (m0_tri_moments)
     int qs = 3;
@@ -709,7 +714,7 @@ __global__ __launch_bounds__(kWG) void k_m0_tri(Geom g, Mesh2 mesh, const Tables
         qs = qs < 4 ? 4 : qs;
     }
     double mom[3];
-    m0_tri_moments<DERIV, FIRST>(T, D, MO, g, mesh, PP, k, i, t, qs, mom);
+    m0_tri_moments<DERIV, FIRST, PART>(T, D, MO, g, mesh, PP, k, i, t, qs, mom);
     double* o = scratch + (lrow * mesh.ntri + t) * 3;
     o[0] = mom[0]; o[1] = mom[1]; o[2] = mom[2];
 }
@@ -1644,11 +1649,21 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd)
             const int kc1 = (int)std::min<long long>(kc0 + krows, c->m0_ksplit);
             const long long r0 = (long long)kc0 * c->ng, nr = (long long)(kc1 - kc0) * c->ng;
             if (kc0 == 0) {
-                KTimer kt(c, op == STBEM_M0 ? "k_m0_tri<false, true>" : "k_m0_tri<true, true>", (double)c->ng * c->ntri, s);
+                // the first time element in two launches: the pairs with the
+                // regular rule (few registers), then the near pairs
+                const dim3 gr((unsigned)(c->ng * tchunk));
+                {
+                    KTimer kt(c, op == STBEM_M0 ? "k_m0_tri<false, true, 1>" : "k_m0_tri<true, true, 1>", (double)c->ng * c->ntri, s);
+                    if (op == STBEM_M0)
+                        hipLaunchKernelGGL((k_m0_tri<false, true, 1>), gr, dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), 0LL, 0LL, tchunk, scratch);
+                    else
+                        hipLaunchKernelGGL((k_m0_tri<true, true, 1>), gr, dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), 0LL, 0LL, tchunk, scratch);
+                }
+                KTimer kt(c, op == STBEM_M0 ? "k_m0_tri<false, true, 2>" : "k_m0_tri<true, true, 2>", (double)c->ng * c->ntri, s);
                 if (op == STBEM_M0)
-                    hipLaunchKernelGGL((k_m0_tri<false, true>), dim3((unsigned)(c->ng * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), 0LL, 0LL, tchunk, scratch);
+                    hipLaunchKernelGGL((k_m0_tri<false, true, 2>), gr, dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), 0LL, 0LL, tchunk, scratch);
                 else
-                    hipLaunchKernelGGL((k_m0_tri<true, true>), dim3((unsigned)(c->ng * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), 0LL, 0LL, tchunk, scratch);
+                    hipLaunchKernelGGL((k_m0_tri<true, true, 2>), gr, dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab, c->d_m0tab, c->m0ord, m0poly(c), 0LL, 0LL, tchunk, scratch);
             }
             const int k0 = kc0 > 0 ? kc0 : 1;
             if (k0 < kc1) {

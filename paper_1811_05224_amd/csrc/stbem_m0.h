@@ -332,7 +332,10 @@ SDEV int m0_first_order(const M0Orders& MO, const Geom& g, const Piece& S, const
     return q0 > qs ? q0 : qs;
 }
 
-template <bool DERIV, bool FIRST>
+// PART (first time element only): 0 every pair, 1 the pairs with the
+// regular rule, 2 the near pairs; a launch for one kind leaves the other
+// kind's code out, which keeps the registers of the regular kind low
+template <bool DERIV, bool FIRST, int PART = 0>
 SDEV void m0_tri_moments(const Tables& T, const M0Tables& D, const M0Orders& MO, const Geom& g,
                          const Mesh2& m, const M0Poly& PP, int k, int i, int t, int qs, double* out)
 {
@@ -340,7 +343,7 @@ SDEV void m0_tri_moments(const Tables& T, const M0Tables& D, const M0Orders& MO,
     Tri3 tr = load_tri3(m, t);
     if (FIRST) {
         const int q0 = m0_first_order(MO, g, S, tr, qs);
-        if (q0 == 0) {
+        if (q0 == 0 && PART != 1) {
             double sm[3], lg[3];
             m0_regular3(T, S, tr, MO.qs_near, MO.qt_near, [&](double r2) { return m0_smooth0<DERIV>(g, r2, 0.5 * log(r2)); }, sm);
             seg_log_potential3(D, S, tr, lg);
@@ -348,7 +351,7 @@ SDEV void m0_tri_moments(const Tables& T, const M0Tables& D, const M0Orders& MO,
             for (int v = 0; v < 3; ++v) out[v] = sm[v] - B * lg[v];
             return;
         }
-        m0_regular3(T, S, tr, q0, q0, [&](double r2) { return m0_kernel<DERIV>(g, 0, r2); }, out);
+        if (PART != 2 && q0 > 0) m0_regular3(T, S, tr, q0, q0, [&](double r2) { return m0_kernel<DERIV>(g, 0, r2); }, out);
         return;
     }
     const int n = PP.n[k];
