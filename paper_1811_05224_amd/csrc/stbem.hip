@@ -463,14 +463,20 @@ __global__ __launch_bounds__(kWG, (Q == 3 || (Q == 4 && !WV)) ? 3 : 1) void k_as
 // integration by parts cancel only within one entry, so the choice is per
 // entry, never per pair).  The raw entries of the tile are done first, then,
 // if the tile has any, the by-parts entries, reusing the moment array.
+// WV: V_h's touching blocks from the same piece pairs (its kernel Delta F_V is
+// the curl-term moment of the by-parts pairs and one more sum at the nodes of
+// the raw pairs); V_h's entry (I0+s, J0+r) sums the pairs of pieces 2s+1,
+// 2s+2 and 2r+1, 2r+2, which D_h's entry (s, r) needs as well.
+template <bool WV>
 __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __restrict__ Tg, Orders O,
                                                         const int* __restrict__ blist, int tiles_1d,
-                                                        double* __restrict__ out64)
+                                                        double* __restrict__ out64, double* __restrict__ outv)
 {
     __shared__ Tables T;
     __shared__ TimeBlock tb;
     __shared__ Piece pc[2][kDP];
     __shared__ double mom[kDP][kDP][5];
+    __shared__ double vmom[WV ? kDP : 1][WV ? kDP : 1];   // int int Delta F_V per piece pair
     __shared__ unsigned char form[kTile][kTile];   // 0 by-parts, 1 raw, 2 outside the matrix
     __shared__ short list[kDP * kDP];              // pairs to compute, costly ones first
     __shared__ unsigned char keys[kDP * kDP];      // cost class of each pair
@@ -562,7 +568,7 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
         const int n = build_list(1);
         for (int e = tid; e < n; e += kWG) {
             const int u = list[e] / kDP, v = list[e] % kDP;
-            d_pair_raw(T, O, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v]);
+            d_pair_raw<WV>(T, O, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v], WV ? &vmom[WV ? u : 0][WV ? v : 0] : nullptr);
         }
     }
     __syncthreads();
@@ -590,6 +596,7 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
             for (int e = tid; e < n; e += kWG) {
                 const int u = list[e] / kDP, v = list[e] % kDP;
                 d_pair_bp(T, O, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v]);
+                if (WV) vmom[WV ? u : 0][WV ? v : 0] = mom[u][v][0];     // the curl-term moment is V's
             }
         }
         __syncthreads();
@@ -609,7 +616,18 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
             val = acc;
         }
     }
-    store_tile(stage, true, val, inside, block_slot(g, b, k, m) * g.ng * g.ng, g.ng, I0, J0, il, jl, out64);
+    const long long boff = block_slot(g, b, k, m) * g.ng * g.ng;
+    store_tile(stage, true, val, inside, boff, g.ng, I0, J0, il, jl, out64);
+    if (WV) {
+        double v = 0.0;
+        if (inside && !mir) {
+            const int u = 2 * il + 1, w = 2 * jl + 1;
+            v = vmom[WV ? u : 0][WV ? w : 0] + vmom[WV ? u : 0][WV ? w + 1 : 0] +
+                vmom[WV ? u + 1 : 0][WV ? w : 0] + vmom[WV ? u + 1 : 0][WV ? w + 1 : 0];
+        }
+        __syncthreads();          // the stage is reused
+        store_tile(stage, true, v, inside, boff, g.ng, I0, J0, il, jl, outv);
+    }
 }
 
 template <int OP>
@@ -1422,17 +1440,20 @@ inline int blocks_per_launch(long long tiles)
     return (int)(b > 0x7fffffff ? 0x7fffffff : (b < 1 ? 1 : b));
 }
 
+// generic kernel over the block list from its touching part (with_touch,
+// V_h assembled alone) or from its generic part
 template <int OP>
-int launch_assemble(stbem_ctx* c, double* o64, hipStream_t s)
+int launch_assemble(stbem_ctx* c, double* o64, hipStream_t s, bool with_touch = false)
 {
     const int slot = OP == OP_V ? 0 : OP == OP_K ? 1 : OP == OP_D ? 2 : OP == OP_DV ? 4 : 5;
     int t1 = (c->ng + kTile - 1) / kTile;
     const long long tiles = tiles_per_block(t1, sym_op(OP));
     Geom g = geom(c);
     const int step = blocks_per_launch(tiles);
-    for (int off = 0; off < c->nlist_gen[slot]; off += step) {
-        const int cnt = std::min(step, c->nlist_gen[slot] - off);
-        const int* bl = c->d_blist[slot] + c->nlist_touch[slot] + off;
+    const int first = with_touch ? 0 : c->nlist_touch[slot], count = c->nlist_gen[slot] + (with_touch ? c->nlist_touch[slot] : 0);
+    for (int off = 0; off < count; off += step) {
+        const int cnt = std::min(step, count - off);
+        const int* bl = c->d_blist[slot] + first + off;
         dim3 gr((unsigned)(cnt * tiles)), blk(kWG);
         KTimer kt(c, kname("k_assemble", OP).c_str(), (double)cnt * g.ng * g.ng, s);
         hipLaunchKernelGGL((k_assemble<OP>), gr, blk, 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64);
@@ -1503,7 +1524,7 @@ int build_block_lists(stbem_ctx* c)
                 int b = (int)((long long)k * (k + 1) / 2 + m);
                 time_block(g, k, m, tb);
                 int q = q_block(op, c->lmax, block_min_lag(g.t, k, m), g.alpha);
-                if ((op == OP_D || op == OP_K || op == OP_DK) && tb.d <= 1) touch.push_back(b);
+                if ((op == OP_V || op == OP_D || op == OP_K || op == OP_DK) && tb.d <= 1) touch.push_back(b);
                 else if (!tb.ser || op == OP_DV || op == OP_DK) gen.push_back(b);
                 else if (q >= 3 && q <= 8) far[q].push_back(b);
                 else gen.push_back(b);
@@ -1517,7 +1538,7 @@ int build_block_lists(stbem_ctx* c)
         if (rc) return rc;
         if (slot == 0 || slot == 2) far_lists[slot / 2].assign(all.end() - (all.size() - touch.size() - gen.size()), all.end());
     }
-    c->vd_fusable = far_lists[0] == far_lists[1];
+    c->vd_fusable = far_lists[0] == far_lists[1] && c->nlist_touch[0] == c->nlist_touch[2];
     for (int q = 0; q < 9; ++q) c->vd_fusable = c->vd_fusable && c->nlist_far[0][q] == c->nlist_far[2][q];
     return 0;
 }
@@ -1583,9 +1604,10 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd)
     case STBEM_V:
     case STBEM_K: {
         if (op == STBEM_K) launch_knear<OP_K>(c, 1, o, s);
-        int rc = op == STBEM_V ? launch_assemble<OP_V>(c, o, s) : launch_assemble<OP_K>(c, o, s);
+        // V_h with D_h: its touching and separated blocks come with D_h's tiles
+        int rc = op == STBEM_V ? launch_assemble<OP_V>(c, o, s, !fuse_vd) : launch_assemble<OP_K>(c, o, s);
         if (rc) return rc;
-        if (op == STBEM_V && fuse_vd) return 0;      // the separated blocks come with D_h's far tiles
+        if (op == STBEM_V && fuse_vd) return 0;
         return op == STBEM_V ? launch_far<OP_V>(c, 0, o, s) : launch_far<OP_K>(c, 1, o, s);
     }
     case STBEM_D: {
@@ -1594,9 +1616,13 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd)
         const int step = blocks_per_launch(tiles);
         for (int off = 0; off < c->nlist_touch[2]; off += step) {
             const int n = std::min(step, c->nlist_touch[2] - off);
-            KTimer kt(c, "k_assemble_dnear", (double)n * c->ng * c->ng, s);
-            hipLaunchKernelGGL(k_assemble_dnear, dim3((unsigned)(n * tiles)), dim3(kWG), 0, s, geom(c), c->d_tab, c->ord,
-                               (const int*)(c->d_blist[2] + off), t1, o);
+            KTimer kt(c, fuse_vd ? "k_assemble_dnear<true>" : "k_assemble_dnear<false>", (double)n * c->ng * c->ng, s);
+            if (fuse_vd)
+                hipLaunchKernelGGL(k_assemble_dnear<true>, dim3((unsigned)(n * tiles)), dim3(kWG), 0, s, geom(c), c->d_tab, c->ord,
+                                   (const int*)(c->d_blist[2] + off), t1, o, c->mat[0]);
+            else
+                hipLaunchKernelGGL(k_assemble_dnear<false>, dim3((unsigned)(n * tiles)), dim3(kWG), 0, s, geom(c), c->d_tab, c->ord,
+                                   (const int*)(c->d_blist[2] + off), t1, o, nullptr);
         }
         int rc = launch_assemble<OP_D>(c, o, s);
         if (rc) return rc;

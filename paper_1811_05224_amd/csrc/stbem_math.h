@@ -299,10 +299,11 @@ SDEV TouchVals touch(const TimeBlock& tb, double a, double alpha)
 
 // Touching time elements: D-type values with the a-derivatives of Delta F_V,
 //   d/da F_V = (E1(a/d) - d e^{-a/d}/a)/(4 pi),  d2/da2 F_V = d e^{-a/d}/(4 pi a^2).
-struct TouchH { double dd, va, vaa; };
+struct TouchH { double dd, va, vaa, v; };
+template <bool WV = false>      // WV: also Delta F_V from the same E1 values
 SDEV TouchH touch_h(const TimeBlock& tb, double a)
 {
-    TouchH r = {0, 0, 0};
+    TouchH r = {0, 0, 0, 0};
     double ia = 1.0 / a;
     for (int s = 0; s < tb.ndel; ++s) {
         double d = tb.del[s], z = a / d, sg = tb.sgn[s];
@@ -310,8 +311,10 @@ SDEV TouchH touch_h(const TimeBlock& tb, double a)
         r.dd += sg * E;
         r.va += sg * (E - x);
         r.vaa += sg * x * ia;
+        if (WV) r.v += sg * ((d + a) * E - d * ez);
     }
     r.dd *= kInv4Pi; r.va *= kInv4Pi; r.vaa *= kInv4Pi;
+    if (WV) r.v *= kInv4Pi;
     return r;
 }
 
@@ -667,15 +670,18 @@ struct DMomBP {
 
 // Raw-kernel form (pieces apart): moments of alpha n_P.n_Q Delta F_D minus the
 // tangential Hessian term t_P^T Hess t_Q of Delta F_V, against the same four
-// bilinear shapes.  Only the regular rule is used with it.
+// bilinear shapes.  Only the regular rule is used with it.  WV: m[4] also
+// takes int int Delta F_V (V_h's kernel) at the same nodes.
+template <bool WV = false>
 struct DMomRaw {
-    const TimeBlock& tb; double alpha, cn, tt, txx, txy, tyx, tyy, iLP, iLQ; double m[4];
+    const TimeBlock& tb; double alpha, cn, tt, txx, txy, tyx, tyy, iLP, iLQ; double m[5];
     SDEV DMomRaw(const TimeBlock& t, double al, const Piece& P, const Piece& Q)
         : tb(t), alpha(al), cn(al * (P.nx * Q.nx + P.ny * Q.ny)), tt(P.ex * Q.ex + P.ey * Q.ey),
-          txx(P.ex), txy(P.ey), tyx(Q.ex), tyy(Q.ey), iLP(1.0 / P.len), iLQ(1.0 / Q.len), m{0.0, 0.0, 0.0, 0.0} {}
+          txx(P.ex), txy(P.ey), tyx(Q.ex), tyy(Q.ey), iLP(1.0 / P.len), iLQ(1.0 / Q.len), m{0.0, 0.0, 0.0, 0.0, 0.0} {}
     SDEV void val(double w, double sP, double sQ, double dx, double dy, double r2)
     {
-        TouchH s = touch_h(tb, 0.25 * alpha * r2);
+        TouchH s = touch_h<WV>(tb, 0.25 * alpha * r2);
+        if (WV) m[4] += w * s.v;
         const double zt = (dx * txx + dy * txy) * (dx * tyx + dy * tyy);
         const double h = 0.25 * alpha * alpha * s.vaa * zt + 0.5 * alpha * s.va * tt;
         const double k = w * (cn * s.dd - h);
@@ -696,12 +702,14 @@ SDEV void d_pair_bp(const Tables& T, const Orders& O, const TimeBlock& tb, doubl
     for (int c = 1; c < 5; ++c) m[c] = cn * f.m[c];
 }
 
+template <bool WV = false>
 SDEV void d_pair_raw(const Tables& T, const Orders& O, const TimeBlock& tb, double alpha,
-                     const Piece& P, const Piece& Q, double* m)
+                     const Piece& P, const Piece& Q, double* m, double* vm = nullptr)
 {
-    DMomRaw f(tb, alpha, P, Q);
+    DMomRaw<WV> f(tb, alpha, P, Q);
     rule_regular(T, P, Q, q_touch(O, tb, P, Q, sep_ratio(P, Q), 0), f);
     for (int c = 0; c < 4; ++c) m[c] = f.m[c];
+    if (WV) *vm = f.m[4];
 }
 
 // separation of the supports of two dual hats (pieces P[0..3], Q[0..3]):

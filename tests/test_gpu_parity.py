@@ -70,9 +70,10 @@ def test_launch_timing_records(small):
     """The launch timing of the library reports every assembly kernel of a
     V_h + D_h + K_h assembly with its work units (matrix entries of the
     blocks it processed) and a positive event time; switching it off drops
-    the records.  Assembled together, V_h's separated blocks come from D_h's
-    far-tile launches (named "k_assemble_dfar<q, true>"), which count their D_h
-    entries; the V_h entries they write are the same number."""
+    the records.  Assembled together, V_h's blocks come from D_h's tile
+    launches (named "k_assemble_dfar<q, true>" and "k_assemble_dnear<true>"),
+    which count their D_h entries; the V_h entries they write are the same
+    number."""
     wl, o, c, L = small
     c.set_timing(True)
     c.assemble(L.V | L.K | L.D)
@@ -82,7 +83,8 @@ def test_launch_timing_records(small):
     entries = c.packed_entries
     by_op = {"V": ("k_assemble<0>", "k_assemble_vkfar<0,"), "K": ("k_assemble_knear<1>", "k_assemble<1>", "k_assemble_vkfar<1,"),
              "D": ("k_assemble_dnear", "k_assemble<2>", "k_assemble_dfar<")}
-    fused = sum(u for name, (n, ms, u) in rec.items() if name.startswith("k_assemble_dfar<") and name.endswith(", true>"))
+    fused = sum(u for name, (n, ms, u) in rec.items()
+                if name.startswith(("k_assemble_dfar<", "k_assemble_dnear<")) and name.endswith("true>"))
     assert fused > 0
     for op, prefixes in by_op.items():
         units = sum(u for name, (n, ms, u) in rec.items() if name.startswith(prefixes))
