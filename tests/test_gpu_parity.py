@@ -189,3 +189,27 @@ def test_tiny_solution(tiny):
     err = np.linalg.norm(w.cpu().numpy() - w_ref) / np.linalg.norm(w_ref)
     print("tiny solve iters", info.iters, "err vs oracle", err)
     assert err < 1e-10
+
+
+def test_assembled_alone_or_together(small):
+    """V_h and D_h assembled in one call share D_h's tiles (V_h's blocks come
+    from the same piece pairs); assembled alone each uses its own kernels.
+    Both ways must meet the oracle bar, and agree with each other to the
+    quadrature level; D_h's own arithmetic is the same either way."""
+    wl, o, c, L = small
+    import paper_1811_05224_amd as P
+    alone = {}
+    for code in (L.V, L.D):
+        ca = P.Context.from_workload(wl)
+        ca.assemble(code)
+        alone[code] = ca.packed(code).cpu().numpy()
+        ca.close()
+    for code, op in ((L.V, "V"), (L.D, "D")):
+        fused = c.packed(code).cpu().numpy()
+        ref = o.packed(op)
+        ea, ef = block_err(alone[code], ref).max(), block_err(fused, ref).max()
+        diff = np.abs(alone[code] - fused).max() / np.abs(fused).max()
+        print(op, "alone vs oracle", ea, "together vs oracle", ef, "alone vs together", diff)
+        assert ea <= TOL[op] and ef <= TOL[op]
+        assert diff <= 1e-13
+    assert np.array_equal(alone[L.V], np.transpose(alone[L.V], (0, 2, 1)))
