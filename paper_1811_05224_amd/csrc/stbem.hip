@@ -90,6 +90,18 @@ __device__ __forceinline__ void store_tile(double (*stage)[kTile + 1], bool sym,
 // of a diagonal tile
 __device__ __forceinline__ bool mirrored(bool sym, int I0, int J0, int il, int jl) { return sym && I0 == J0 && il > jl; }
 
+// time data of every causal block (k, m), by packed index, once per context:
+// the far-field tiles read it from global memory (uniform, scalar loads)
+// instead of having one lane of every workgroup build it
+__global__ __launch_bounds__(kWG) void k_time_blocks(Geom g, long long nb, TimeBlock* __restrict__ out)
+{
+    const long long b = (long long)blockIdx.x * kWG + threadIdx.x;
+    if (b >= nb) return;
+    int k, m;
+    block_of(b, k, m);
+    time_block(g, k, m, out[b]);
+}
+
 template <int OP>
 __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restrict__ Tg, Orders O,
                                                   double lmax, const int* __restrict__ blist, int tiles_1d,
@@ -215,11 +227,10 @@ __device__ __forceinline__ void far_pair(const Tables& T, const TimeBlock& tb, d
 template <int OP, int Q>
 __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __restrict__ Tg,
                                                         const int* __restrict__ blist, int tiles_i, int tiles_j,
-                                                        double* __restrict__ out64)
+                                                        double* __restrict__ out64, const TimeBlock* __restrict__ tbs)
 {
     constexpr bool SYM = OP == OP_V;
     __shared__ Tables T;
-    __shared__ TimeBlock tb;
     __shared__ double stage[kTile][kTile + 1];
     const int tid = threadIdx.x;
     const long long tiles = SYM ? (long long)tiles_i * (tiles_i + 1) / 2 : (long long)tiles_i * tiles_j;
@@ -229,7 +240,7 @@ __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __
     else { const int tile = (int)(blockIdx.x % tiles); ti = tile / tiles_j; tj = tile % tiles_j; }
     int k, m;
     block_of(b, k, m);
-    if (tid == 0) time_block(g, k, m, tb);
+    const TimeBlock& tb = tbs[b];
     {
         const double* src = reinterpret_cast<const double*>(Tg);
         double* dst = reinterpret_cast<double*>(&T);
@@ -383,9 +394,9 @@ __device__ __forceinline__ void far_dpair(const Tables& T, const TimeBlock& tb, 
 template <int Q, bool WV>
 __global__ __launch_bounds__(kWG, (Q == 3 || (Q == 4 && !WV)) ? 3 : 1) void k_assemble_dfar(Geom g, const Tables* __restrict__ Tg,
                                                        const int* __restrict__ blist, int tiles_1d,
-                                                       double* __restrict__ out64, double* __restrict__ outv)
+                                                       double* __restrict__ out64, double* __restrict__ outv,
+                                                       const TimeBlock* __restrict__ tbs)
 {
-    __shared__ TimeBlock tb;
     __shared__ double mom[kDP][kDP][4];
     __shared__ double pc[2][kDP][7];       // ax ay ex ey len nx ny
     __shared__ double stage[kTile][kTile + 1];
@@ -397,7 +408,7 @@ __global__ __launch_bounds__(kWG, (Q == 3 || (Q == 4 && !WV)) ? 3 : 1) void k_as
     tile_of((int)(blockIdx.x % tiles), tiles_1d, true, ti, tj);
     int k, m;
     block_of(b, k, m);
-    if (tid == 0) time_block(g, k, m, tb);
+    const TimeBlock& tb = tbs[b];
     const int I0 = ti * kTile, J0 = tj * kTile;
     const int np = 2 * g.ng;
     if (tid < 2 * kDP) {
@@ -1259,6 +1270,7 @@ struct stbem_ctx {
     int *d_m0n = nullptr, *d_v2t_loc = nullptr;
     int *d_tri = nullptr, *d_v2t_ptr = nullptr, *d_v2t = nullptr;
     Tables* d_tab = nullptr;
+    TimeBlock* d_tbs = nullptr;         // the time data of every causal block, by packed index
     M0Tables* d_m0tab = nullptr;
     Orders ord;
     M0Orders m0ord;
@@ -1487,7 +1499,7 @@ void launch_vkfar(stbem_ctx* c, int slot, const int* bl, int cnt, double* o, hip
         const int n = std::min(step, cnt - off);
         KTimer kt(c, kname("k_assemble_vkfar", OP, Q).c_str(), (double)n * c->ng * c->ng, s);
         hipLaunchKernelGGL((k_assemble_vkfar<OP, Q>), dim3((unsigned)(n * tiles)), dim3(kWG), 0, s, geom(c), c->d_tab,
-                           bl + off, ti, tj, o);
+                           bl + off, ti, tj, o, (const TimeBlock*)c->d_tbs);
     }
 }
 
@@ -1636,20 +1648,20 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd)
                 KTimer kt(c, kn.c_str(), (double)n * c->ng * c->ng, s);
                 double* ov = c->mat[0];
                 if (fuse_vd) switch (q) {
-                case 3: hipLaunchKernelGGL((k_assemble_dfar<3, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov); break;
-                case 4: hipLaunchKernelGGL((k_assemble_dfar<4, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov); break;
-                case 5: hipLaunchKernelGGL((k_assemble_dfar<5, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov); break;
-                case 6: hipLaunchKernelGGL((k_assemble_dfar<6, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov); break;
-                case 7: hipLaunchKernelGGL((k_assemble_dfar<7, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov); break;
-                default: hipLaunchKernelGGL((k_assemble_dfar<8, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov); break;
+                case 3: hipLaunchKernelGGL((k_assemble_dfar<3, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov, c->d_tbs); break;
+                case 4: hipLaunchKernelGGL((k_assemble_dfar<4, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov, c->d_tbs); break;
+                case 5: hipLaunchKernelGGL((k_assemble_dfar<5, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov, c->d_tbs); break;
+                case 6: hipLaunchKernelGGL((k_assemble_dfar<6, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov, c->d_tbs); break;
+                case 7: hipLaunchKernelGGL((k_assemble_dfar<7, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov, c->d_tbs); break;
+                default: hipLaunchKernelGGL((k_assemble_dfar<8, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov, c->d_tbs); break;
                 }
                 else switch (q) {
-                case 3: hipLaunchKernelGGL((k_assemble_dfar<3, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr); break;
-                case 4: hipLaunchKernelGGL((k_assemble_dfar<4, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr); break;
-                case 5: hipLaunchKernelGGL((k_assemble_dfar<5, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr); break;
-                case 6: hipLaunchKernelGGL((k_assemble_dfar<6, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr); break;
-                case 7: hipLaunchKernelGGL((k_assemble_dfar<7, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr); break;
-                default: hipLaunchKernelGGL((k_assemble_dfar<8, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr); break;
+                case 3: hipLaunchKernelGGL((k_assemble_dfar<3, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr, c->d_tbs); break;
+                case 4: hipLaunchKernelGGL((k_assemble_dfar<4, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr, c->d_tbs); break;
+                case 5: hipLaunchKernelGGL((k_assemble_dfar<5, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr, c->d_tbs); break;
+                case 6: hipLaunchKernelGGL((k_assemble_dfar<6, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr, c->d_tbs); break;
+                case 7: hipLaunchKernelGGL((k_assemble_dfar<7, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr, c->d_tbs); break;
+                default: hipLaunchKernelGGL((k_assemble_dfar<8, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr, c->d_tbs); break;
                 }
             }
             bl += c->nlist_far[2][q];
@@ -1974,6 +1986,16 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
         return STBEM_EHIP;
     }
     c->ord = default_orders();
+    {
+        const long long nb = (long long)c->nt * (c->nt + 1) / 2;
+        if (hipMalloc((void**)&c->d_tbs, (size_t)nb * sizeof(TimeBlock)) != hipSuccess) {
+            (void)hipGetLastError();
+            stbem_destroy(c);
+            return STBEM_ENOMEM;
+        }
+        hipLaunchKernelGGL(k_time_blocks, dim3((unsigned)((nb + kWG - 1) / kWG)), dim3(kWG), 0, 0, geom(c), nb, c->d_tbs);
+        if (hipDeviceSynchronize() != hipSuccess) { stbem_destroy(c); return STBEM_EHIP; }
+    }
     if ((rc = build_block_lists(c))) { stbem_destroy(c); return rc; }
     c->m0ord.qs_near = 12; c->m0ord.qt_near = 12; c->m0ord.near_ratio = 0.5;
     c->m0ord.q_tol = c->ord.q_tol; c->m0ord.z_floor = c->ord.z_floor;
@@ -2044,7 +2066,7 @@ int stbem_destroy(stbem_ctx* c)
     for (int s = 0; s < 7; ++s) dev_free(c, c->mat[s]);
     dev_free(c, c->v_hi); dev_free(c, c->v_lo); dev_free(c, c->d_32);
     void* own[] = {c->d_t, c->d_vx, c->d_vy, c->d_ex, c->d_ey, c->d_len, c->d_ox, c->d_oy, c->d_mt, c->d_m0c, c->d_m0cd, c->d_m0n, c->d_m0amax, c->d_v2t_loc,
-                   c->d_tri, c->d_v2t_ptr, c->d_v2t, c->d_tab, c->d_m0tab, c->part};
+                   c->d_tri, c->d_v2t_ptr, c->d_v2t, c->d_tab, c->d_m0tab, c->part, c->d_tbs};
     for (void* p : own) if (p) (void)hipFree(p);
     for (int q = 0; q < 7; ++q) if (c->d_blist[q]) (void)hipFree(c->d_blist[q]);
     clear_timing(c);
