@@ -230,7 +230,6 @@ __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __
                                                         double* __restrict__ out64, const TimeBlock* __restrict__ tbs)
 {
     constexpr bool SYM = OP == OP_V;
-    __shared__ Tables T;
     __shared__ double stage[kTile][kTile + 1];
     const int tid = threadIdx.x;
     const long long tiles = SYM ? (long long)tiles_i * (tiles_i + 1) / 2 : (long long)tiles_i * tiles_j;
@@ -241,12 +240,7 @@ __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __
     int k, m;
     block_of(b, k, m);
     const TimeBlock& tb = tbs[b];
-    {
-        const double* src = reinterpret_cast<const double*>(Tg);
-        double* dst = reinterpret_cast<double*>(&T);
-        for (int e = tid; e < (int)(sizeof(Tables) / sizeof(double)); e += kWG) dst[e] = src[e];
-    }
-    __syncthreads();
+    const Tables& T = *Tg;                 // only the Q-point rule is read (uniform loads)
     const int ty = tid / kTile, tx = tid % kTile;
     const int i = ti * kTile + ty;
     // V: column j = J0 + tx.  K: the tile covers segments J0-1 .. J0+14 and
