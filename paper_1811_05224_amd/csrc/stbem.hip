@@ -105,11 +105,10 @@ __global__ __launch_bounds__(kWG) void k_time_blocks(Geom g, long long nb, TimeB
 template <int OP>
 __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restrict__ Tg, Orders O,
                                                   double lmax, const int* __restrict__ blist, int tiles_1d,
-                                                  double* __restrict__ out64)
+                                                  double* __restrict__ out64, const TimeBlock* __restrict__ tbs)
 {
     constexpr bool SYM = sym_op(OP);
     __shared__ Tables T;
-    __shared__ TimeBlock tb;
     __shared__ int qf;
     __shared__ double stage[kTile][kTile + 1];
     const int tid = threadIdx.x;
@@ -124,10 +123,8 @@ __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restri
     tile_of((int)(blockIdx.x % tiles), tiles_1d, SYM, ti, tj);
     int k, m;
     block_of(b, k, m);
-    if (tid == 0) {
-        time_block(g, k, m, tb);
-        qf = q_block(OP, lmax, block_min_lag(g.t, k, m), g.alpha);
-    }
+    const TimeBlock& tb = tbs[b];
+    if (tid == 0) qf = q_block(OP, lmax, block_min_lag(g.t, k, m), g.alpha);
     __syncthreads();
     const int il = tid / kTile, jl = tid % kTile, I0 = ti * kTile, J0 = tj * kTile;
     const int i = I0 + il, j = J0 + jl;
@@ -1462,7 +1459,7 @@ int launch_assemble(stbem_ctx* c, double* o64, hipStream_t s, bool with_touch = 
         const int* bl = c->d_blist[slot] + first + off;
         dim3 gr((unsigned)(cnt * tiles)), blk(kWG);
         KTimer kt(c, kname("k_assemble", OP).c_str(), (double)cnt * g.ng * g.ng, s);
-        hipLaunchKernelGGL((k_assemble<OP>), gr, blk, 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64);
+        hipLaunchKernelGGL((k_assemble<OP>), gr, blk, 0, s, g, c->d_tab, c->ord, c->lmax, bl, t1, o64, (const TimeBlock*)c->d_tbs);
     }
     HIPCHK(c, hipGetLastError());
     return 0;
