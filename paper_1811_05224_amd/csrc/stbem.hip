@@ -3,10 +3,13 @@
 // Assembly (VALU-bound): one workgroup = one 16 x 16 tile of one causal
 // block (k, m), k >= m; the upper blocks are never launched, and for the
 // symmetric operators only the tiles on and above the block diagonal.  The
-// quadrature tables and the time-block data (lags, series moments) live in
-// LDS; lanes either compute one entry each or share piece-pair moments in LDS
-// across the entries of the tile, and the lanes of a row store consecutive
-// doubles.
+// time data of every block (lags, series coefficients) are built once per
+// context; the far-field tiles read them and their Gauss rule from global
+// memory (uniform, scalar loads), the touching-element tiles stage theirs in
+// LDS with the singular-rule tables.  Lanes either compute one entry each or
+// share piece-pair moments in LDS across the entries of the tile (V_h and D_h
+// assembled together share D_h's tiles), and the lanes of a row store
+// consecutive doubles.
 // GEMV (HBM-bound): pass 1 computes one partial vector per stored block
 // (8 rows per wavefront for A x, a lane per column for A^T x), pass 2 adds the
 // partials of a block row (or column) in a fixed order, so results are
