@@ -759,7 +759,42 @@ __global__ __launch_bounds__(kWG, 3) void k_m0_rows(Geom g, Mesh2 mesh, const Ta
     }
     __syncthreads();
     const int i = (int)(blockIdx.x / nchunk);
-    const int t = (int)(blockIdx.x % nchunk) * kWG + threadIdx.x;
+    int t = (int)(blockIdx.x % nchunk) * kWG + threadIdx.x;
+    {
+        // the triangles are handed to the lanes in order of cost: the number
+        // of rows that need E1 values (the others take the power series)
+        constexpr int kKeys = 34;
+        __shared__ int cnt[kKeys];
+        __shared__ int work[kWG];
+        if (threadIdx.x < kKeys) cnt[threadIdx.x] = 0;
+        __syncthreads();
+        int key = kKeys - 1;                                    // outside the mesh: last
+        if (t < mesh.ntri) {
+            const Piece S0 = seg_piece(g, i);
+            const Tri3 t3 = load_tri3(mesh, t);
+            double dhi2 = 0.0;
+            const double vx[3] = {t3.ax, t3.bx, t3.cx}, vy[3] = {t3.ay, t3.by, t3.cy};
+            for (int e = 0; e < 2; ++e) {
+                const double px = S0.ax + e * S0.len * S0.ex, py = S0.ay + e * S0.len * S0.ey;
+                for (int v = 0; v < 3; ++v) dhi2 = fmax(dhi2, (vx[v] - px) * (vx[v] - px) + (vy[v] - py) * (vy[v] - py));
+            }
+            const double ahi = 0.25 * g.alpha * dhi2;
+            int ne = 0;
+            for (int k = k0; k < k0 + nk; ++k) ne += (PP.n[k] == 0 || ahi > PP.amax[k]) ? 1 : 0;
+            key = nk - ne;                                      // most E1 rows first
+            key = key > kKeys - 2 ? kKeys - 2 : key;
+        }
+        const int rank = atomicAdd(&cnt[key], 1);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int e = 0; e < kKeys; ++e) { const int c = cnt[e]; cnt[e] = acc; acc += c; }
+        }
+        __syncthreads();
+        work[cnt[key] + rank] = t;
+        __syncthreads();
+        t = work[threadIdx.x];
+    }
     if (t >= mesh.ntri) return;
     const Piece S = seg_piece(g, i);
     const Tri3 tr = load_tri3(mesh, t);
