@@ -38,12 +38,12 @@ FP64_PEAK_TFLOPS = 78.6
 # fused tiles k_assemble_dfar<q, true> and k_assemble_dnear<true> count D_h
 # entries and write as many V_h entries (16 B per unit).
 FLOP_PER_UNIT = {'k_assemble_dfar<3, true>': 4555.6,
-    'k_assemble_dnear<true>': 31402.4,
-    'k_m0_rows<false>': 17914.0,
+    'k_assemble_dnear<true>': 31402.0,
+    'k_m0_rows<false>': 16233.1,
     'k_assemble_vkfar<1, 4>': 2399.4,
     'k_assemble_dfar<4, true>': 16174.2,
     'k_assemble_knear<1>': 12373.6,
-    'k_m0_tri<false, true, 1>': 58335.2,
+    'k_m0_tri<false, true, 1>': 58332.9,
     'k_assemble_vkfar<1, 5>': 7447.3,
     'k_m0_pow': 35571.0,
     'k_m0_tri<false, true, 2>': 4523.3,
@@ -52,20 +52,20 @@ FLOP_PER_UNIT = {'k_assemble_dfar<3, true>': 4555.6,
     'k_m0_gather': 6.0}
 HBM_BYTES_PER_UNIT = {'k_gemv_n_vec<double>': 8.035,
     'k_assemble_dfar<3, true>': 16.188,
-    'k_assemble_dnear<true>': 16.087,
-    'k_m0_rows<false>': 24.046,
+    'k_assemble_dnear<true>': 16.088,
+    'k_m0_rows<false>': 24.179,
     'k_assemble_vkfar<1, 4>': 9.805,
     'k_assemble_dfar<4, true>': 16.414,
     'k_gemv_n_vec<float>': 4.035,
-    'k_assemble_knear<1>': 9.658,
-    'k_m0_tri<false, true, 1>': 24.354,
+    'k_assemble_knear<1>': 9.659,
+    'k_m0_tri<false, true, 1>': 24.353,
     'k_assemble_vkfar<1, 5>': 10.03,
     'k_m0_pow': 888.5,
     'k_m0_tri<false, true, 2>': 0.478,
     'k_gemv_n_vec<float hi+lo>': 8.035,
-    'k_m0_pow_gather': 70.347,
-    'k_m0_pow_apply': 10.822,
-    'k_m0_gather': 67.253}
+    'k_m0_pow_gather': 70.042,
+    'k_m0_pow_apply': 10.821,
+    'k_m0_gather': 67.234}
 # bytes streamed per stored entry by the matrix-vector kernels
 GEMV_BYTES = {"k_gemv_n_vec<double>": 8, "k_gemv_t_vec<double>": 8, "k_gemv_n_vec<float hi+lo>": 8,
               "k_gemv_t_vec<float hi+lo>": 8, "k_gemv_n_vec<float>": 4, "k_gemv_t_vec<float>": 4}
