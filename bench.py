@@ -94,8 +94,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is a design "
-              "note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding over several GPUs "
+              "is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     import workloads as W

@@ -81,3 +81,13 @@ def test_null_context_rejected():
     assert lib.stbem_set_timing(None, 1) == -1
     assert lib.stbem_kernel_times(None, None, 0) == -1
     assert lib.stbem_destroy(None) == 0
+
+
+def test_bench_refuses_several_gpus():
+    """The benchmark runs on one GPU; asked for more it stops with a message
+    (before touching any device)."""
+    import subprocess, sys, os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode != 0 and "one GPU only" in r.stderr and r.stdout == ""
