@@ -405,11 +405,15 @@ SDEV PotSeg pot_segment(const Tables& T, const Orders& O, const Geom& g, int j, 
 {
     PotSeg r = {0.0, 0.0, 0.0};
     const double ax = g.vx[j], ay = g.vy[j], ex = g.ex[j], ey = g.ey[j], L = g.len[j];
-    const double nx = ey, ny = -ex;
-    double sf = (x - ax) * ex + (y - ay) * ey;
-    sf = sf < 0.0 ? 0.0 : (sf > L ? L : sf);
-    const double fx = ax + sf * ex - x, fy = ay + sf * ey - y;
-    const double d = sqrt(fx * fx + fy * fy);
+    // the point in the segment's frame: x - a = pt e + pn n (n = (ey, -ex));
+    // at a node y = a + s e, x - y = (pt - s) e + pn n with pt - s formed
+    // from the offset to the foot, so r^2 and (x - y).n keep their relative
+    // accuracy however close the point is to the segment
+    const double px = x - ax, py = y - ay;
+    const double pt = px * ex + py * ey, pn = px * ey - py * ex;
+    const double sf = pt < 0.0 ? 0.0 : (pt > L ? L : pt);
+    const double dt0 = pt - sf;                          // 0 when the foot is inside
+    const double d = sqrt(dt0 * dt0 + pn * pn);
     const double w2 = 0.25 * g.alpha / (slo > 0.0 ? slo : shi);
     for (int side = 0; side < 2; ++side) {
         const double span = side ? L - sf : sf;          // from the foot towards one end
@@ -429,10 +433,10 @@ SDEV PotSeg pot_segment(const Tables& T, const Orders& O, const Geom& g, int j, 
             for (int a = 0; a < q; ++a) {
                 const double u = s0 + h * T.gl_x[q][a], wq = h * T.gl_w[q][a];
                 const double s = side ? sf + u : sf - u;     // arclength on the segment
-                const double dx = x - (ax + s * ex), dy = y - (ay + s * ey);
-                const double r2 = dx * dx + dy * dy;
+                const double dt = side ? dt0 - u : dt0 + u;   // (x - y).e
+                const double r2 = dt * dt + pn * pn;
                 double sl, dl;
-                pot_kernels(g.alpha, r2, dx * nx + dy * ny, slo, shi, sl, dl);
+                pot_kernels(g.alpha, r2, pn, slo, shi, sl, dl);
                 const double l1 = s / L;
                 r.sl += wq * sl;
                 r.d0 += wq * dl * (1.0 - l1);

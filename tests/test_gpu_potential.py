@@ -115,3 +115,25 @@ def test_points_outside_rejected():
             c.potential(bad, w, g)
     assert c.potential(np.zeros((0, 3)), w, g).shape == (0, 3)
     c.close()
+
+
+def test_points_very_close_to_the_boundary():
+    """Points 1e-6 and 1e-9 from a side and from a corner, at a time node and
+    between nodes: the graded pieces at the foot of the point keep the
+    boundary potentials at the oracle's accuracy (the kernels are nearly
+    singular there)."""
+    import paper_1811_05224_amd as P
+    wl = W.make("tiny")
+    o = Oracle.from_workload(wl)
+    c = P.Context.from_workload(wl)
+    rng = np.random.default_rng(9)
+    w, g, u0 = rng.standard_normal(c.n), rng.standard_normal(c.n), rng.standard_normal(c.nv)
+    xy = [(0.5, 1e-6), (1e-9, 0.37), (1e-6, 1e-6), (0.999999, 0.5)]
+    pts = np.array([(x, y, t) for (x, y) in xy for t in (0.25, 0.3, 1.0)])
+    got = c.potential(pts, w, g, u0).cpu().numpy()
+    ref = o.potential(pts, w, g, u0)
+    scale = o.potential(pts, np.abs(w), np.abs(g), np.abs(u0))
+    e = np.abs(got - ref) / np.maximum(np.abs(ref), np.abs(scale))
+    print("max error near the boundary per column", e.max(axis=0))
+    assert e.max() <= 1e-12
+    c.close()
