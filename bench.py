@@ -1,14 +1,22 @@
 """Benchmark of the space-time BEM hot path on one MI355X.
 
-One step = the whole path of the method on one synthetic workload:
-assemble V_h, K_h, D_h and M_h^0 (FP64), form the right-hand side of eq.(4),
-solve with D_h-preconditioned GMRES in FP64, then solve again with FP32
-storage of V_h and D_h inside an FP64 iterative refinement.  Inputs are
-resident in HBM before the timed region.  Prints one JSON line.
+One step = the forward path of the method on one synthetic workload, in
+three phases that keep the resident matrices within the GPU's memory:
+  1. assemble K_h and M_h^0 (FP64), form the right-hand side of eq.(4),
+     release them;
+  2. assemble V_h and D_h in FP64, solve with D_h-preconditioned GMRES,
+     release them;
+  3. assemble V_h and D_h into FP32 storage (V_h as an FP32 hi + lo pair,
+     D_h as FP32; no FP64 copy), solve by FP64 iterative refinement around
+     FP32 inner GMRES.
+Inputs are resident in HBM before the timed region.  Prints one JSON line.
 
-Default workload (the medium configuration): unit square, 256 boundary
-segments, 128 uniform time steps (N = 32768), alpha = 1, Omega_h 64^2 grid
-(8192 triangles), manufactured u = exp(k.x + |k|^2 t/alpha), k = (1, 0).
+Default workload (the precision configuration, the largest that fits one
+GPU): unit square, 512 boundary segments, 256 uniform time steps
+(N = 131072), alpha = 1, Omega_h 128^2 grid (32768 triangles),
+manufactured u = exp(k.x + |k|^2 t/alpha), k = (0.7, -0.7).  Beside the
+step it times the adjoint gradient on the differentiation workload and the
+D_h assembly on the paper's Table 2 mesh.
 """
 from __future__ import annotations
 
@@ -26,46 +34,14 @@ sys.path.insert(0, ROOT)
 METRIC = "entries/s (V_h,K_h,D_h) + precond. GMRES solve s to 1e-10, FP64 vs FP32-refined"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 
-# Per work unit of each kernel on the medium workload (units as reported by
-# the library's launch timing: matrix entries, or (row, triangle) pairs for
-# the M_h^0 moment kernels), measured with rocprofv3 counters:
-#   FP64 operations = 64 x (ADD_F64 + MUL_F64 + 2 FMA_F64 + TRANS_F64) wave
-#   instructions (inactive lanes included), profiles/counters_fp64_medium.md;
-#   HBM bytes = 2 x FETCH_SIZE + WRITE_SIZE (KiB x 1024), the factors from a
-#   1 GiB device copy read by the same counters, profiles/counters_hbm_medium.md.
-# A kernel changed after its counters were taken has no entry here.  The
-# fused tiles k_assemble_dfar<q, true> and k_assemble_dnear<true> count D_h
-# entries and write as many V_h entries (16 B per unit).
-FLOP_PER_UNIT = {'k_assemble_dfar<3, true>': 4555.6,
-    'k_assemble_dnear<true>': 31402.0,
-    'k_m0_rows<false>': 16233.1,
-    'k_assemble_vkfar<1, 4>': 2399.4,
-    'k_assemble_dfar<4, true>': 16174.2,
-    'k_assemble_knear<1>': 12373.6,
-    'k_m0_tri<false, true, 1>': 58332.9,
-    'k_assemble_vkfar<1, 5>': 7447.3,
-    'k_m0_pow': 35571.0,
-    'k_m0_tri<false, true, 2>': 4523.3,
-    'k_m0_pow_gather': 6.0,
-    'k_m0_pow_apply': 81.0,
-    'k_m0_gather': 6.0}
-HBM_BYTES_PER_UNIT = {'k_gemv_n_vec<double>': 8.035,
-    'k_assemble_dfar<3, true>': 16.188,
-    'k_assemble_dnear<true>': 16.088,
-    'k_m0_rows<false>': 24.179,
-    'k_assemble_vkfar<1, 4>': 9.805,
-    'k_assemble_dfar<4, true>': 16.414,
-    'k_gemv_n_vec<float>': 4.035,
-    'k_assemble_knear<1>': 9.659,
-    'k_m0_tri<false, true, 1>': 24.353,
-    'k_assemble_vkfar<1, 5>': 10.03,
-    'k_m0_pow': 888.5,
-    'k_m0_tri<false, true, 2>': 0.478,
-    'k_gemv_n_vec<float hi+lo>': 8.035,
-    'k_m0_pow_gather': 70.042,
-    'k_m0_pow_apply': 10.821,
-    'k_m0_gather': 67.234}
+# HBM bytes per work unit of a kernel (units as reported by the library's
+# launch timing), from rocprofv3 counters: 2 x FETCH_SIZE + WRITE_SIZE
+# (KiB x 1024) per dispatch over the units of the dispatch; the factor 2 on
+# FETCH_SIZE comes from a 1 GiB device copy read by the same counters.  A
+# kernel changed after its counters were taken has no entry here.
+HBM_BYTES_PER_UNIT = {}
 # bytes streamed per stored entry by the matrix-vector kernels
 GEMV_BYTES = {"k_gemv_n_vec<double>": 8, "k_gemv_t_vec<double>": 8, "k_gemv_n_vec<float hi+lo>": 8,
               "k_gemv_t_vec<float hi+lo>": 8, "k_gemv_n_vec<float>": 4, "k_gemv_t_vec<float>": 4}
@@ -76,13 +52,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="medium")
+    ap.add_argument("--workload", default="precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paper-mesh", action="store_true", help="skip the D_h assembly on the paper's Table 2 mesh")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint gradient on the differentiation workload")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the untimed reference solve after the steps")
     ap.add_argument("--cpu-sample", type=int, default=0, help="entries per operator for the oracle timing")
-    # tolerances calibrated on the medium workload so that both solutions are
-    # within 1e-10 (relative l2) of a 1e-15 FP64 solve: plain GMRES stops on
-    # the preconditioned residual, the refinement on the FP64 residual of V_h
+    # tolerances chosen so that both solutions are within 1e-10 (relative l2)
+    # of an FP64 solve to 1e-15 (tests/test_gpu_workloads.py checks them on
+    # the precision workload): plain GMRES stops on the preconditioned
+    # residual, the refinement on the FP64 residual of V_h
     ap.add_argument("--tol", type=float, default=3e-11, help="FP64 GMRES: preconditioned relative residual")
     ap.add_argument("--ir-tol", type=float, default=1e-12, help="FP32 refinement: FP64 relative residual")
     ap.add_argument("--inner-tol", type=float, default=1e-6, help="FP32 refinement: inner GMRES tolerance")
@@ -115,30 +94,33 @@ def main():
     u0 = torch.as_tensor(wl.u0, device=dev)
     stream = torch.cuda.current_stream()
     ev = lambda: torch.cuda.Event(enable_timing=True)
+    phases = ("K+M0", "rhs", "V+D fp64", "solve fp64", "V+D fp32", "solve fp32-refined")
 
     def step(record):
-        t = {}
-        e0, e1, e2, e3, e4, e5, e6, e7 = (ev() for _ in range(8))
-        e0.record(stream)
-        ctx.assemble(L.V | L.D)       # one call: V_h's separated blocks come from D_h's far tiles
-        e1.record(stream)
-        ctx.assemble(L.K)
-        e2.record(stream)
-        e3.record(stream)
-        ctx.assemble(L.M0)
-        e4.record(stream)
+        e = [ev() for _ in range(len(phases) + 1)]
+        e[0].record(stream)
+        ctx.assemble(L.K | L.M0)
+        e[1].record(stream)
         f = ctx.rhs(g, u0)
-        e5.record(stream)
+        e[2].record(stream)
+        ctx.release(L.K | L.M0)
+        # V_h's separated and touching blocks come from D_h's tiles (one call)
+        ctx.assemble(L.V | L.D)
+        e[3].record(stream)
         w64, i64 = ctx.solve(f, tol=args.tol, max_it=400)
-        e6.record(stream)
+        e[4].record(stream)
+        ctx.release(L.V | L.D)
+        ctx.assemble(L.V | L.D, precision=L.FP32_IR)
+        e[5].record(stream)
         w32, i32 = ctx.solve(f, tol=args.ir_tol, max_it=400, mode=L.FP32_IR, inner_tol=args.inner_tol, max_outer=12,
                              ir_tol=args.ir_tol)
-        e7.record(stream)
+        e[6].record(stream)
         torch.cuda.synchronize()
+        ctx.release(L.V | L.D)
         if record is not None:
-            record.append({"V+D": e0.elapsed_time(e1), "K": e1.elapsed_time(e2),
-                           "M0": e3.elapsed_time(e4), "rhs": e4.elapsed_time(e5), "solve64": e5.elapsed_time(e6),
-                           "solve32": e6.elapsed_time(e7), "i64": i64, "i32": i32})
+            r = {ph: e[q].elapsed_time(e[q + 1]) for q, ph in enumerate(phases)}
+            r.update(i64=i64, i32=i32)
+            record.append(r)
         return f, w64, w32
 
     for _ in range(args.warmup):
@@ -156,34 +138,9 @@ def main():
     ctx.set_timing(False)
 
     entries = ctx.packed_entries            # per causal matrix
-    avg = {k: float(np.mean([r[k] for r in rec])) for k in ("V+D", "K", "M0", "rhs", "solve64", "solve32")}
+    avg = {ph: float(np.mean([r[ph] for r in rec])) for ph in phases}
     value = 3 * entries / (ms_per_step * 1e-3)
-
-    # GEMV rate on V_h (HBM-bound), HIP events on the launch stream
-    x = torch.randn(ctx.n, dtype=torch.float64, device=dev)
-    y = ctx.apply(L.V, x)
-    a, b = ev(), ev()
-    reps = 20
-    a.record(stream)
-    for _ in range(reps):
-        ctx.apply(L.V, x, out=y)
-    b.record(stream)
-    torch.cuda.synchronize()
-    gemv_ms = a.elapsed_time(b) / reps
-    gemv_gbs = entries * 8 / (gemv_ms * 1e-3) / 1e9
-
-    # accuracy (untimed): both timed solutions against an FP64 solve to 1e-15,
-    # the FP32-refined against the FP64 one, and both against the exact flux
-    wref, _ = ctx.solve(f, tol=1e-15, max_it=800)
-    w64n, w32n, wrn = w64.cpu().numpy(), w32.cpu().numpy(), wref.cpu().numpy()
-    err64 = float(np.linalg.norm(w64n - wrn) / np.linalg.norm(wrn))
-    err32 = float(np.linalg.norm(w32n - wrn) / np.linalg.norm(wrn))
-    ir_vs_fp64 = float(np.linalg.norm(w32n - w64n) / np.linalg.norm(w64n))
-    disc64 = float(np.linalg.norm(w64n - wl.w_ref) / np.linalg.norm(wl.w_ref))
-
-    roof = roofline(ktimes)
-    kernel_ms = {k: round(v[1] / args.steps, 3) for k, v in sorted(ktimes.items(), key=lambda kv: -kv[1][1])}
-    kernel_units = {k: v[2] / v[0] for k, v in ktimes.items()}
+    last64, last32 = rec[-1]["i64"], rec[-1]["i32"]
 
     out = {
         "metric": METRIC, "value": value, "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
@@ -191,50 +148,123 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: N_Gamma={ctx.ng}, N_I={ctx.nt}, N={ctx.n}, M_Omega={ctx.nv}, "
                                f"alpha={wl.alpha}, entries per causal matrix={entries}"},
-        "assembly_ms": {k: avg[k] for k in ("V+D", "K", "M0")},
-        "assembly_entries_per_s": {"V+D": 2 * entries / (avg["V+D"] * 1e-3), "K": entries / (avg["K"] * 1e-3)},
-        "rhs_ms": avg["rhs"],
-        "solve_s_fp64": avg["solve64"] * 1e-3, "solve_s_fp32_refined": avg["solve32"] * 1e-3,
-        "gmres_iters_fp64": rec[-1]["i64"].iters, "gmres_iters_fp32_inner_total": rec[-1]["i32"].iters,
-        "ir_outer_steps": rec[-1]["i32"].outer,
-        "true_relres_fp64": rec[-1]["i64"].true_relres, "true_relres_fp32_refined": rec[-1]["i32"].true_relres,
+        "phase_ms": avg,
+        "assembly_entries_per_s": {"V+D fp64": 2 * entries / (avg["V+D fp64"] * 1e-3),
+                                   "V+D fp32 storage": 2 * entries / (avg["V+D fp32"] * 1e-3),
+                                   "K+M0": entries / (avg["K+M0"] * 1e-3)},
+        "solve_s_fp64": avg["solve fp64"] * 1e-3, "solve_s_fp32_refined": avg["solve fp32-refined"] * 1e-3,
+        "path_s_fp64": (avg["V+D fp64"] + avg["solve fp64"]) * 1e-3,
+        "path_s_fp32_refined": (avg["V+D fp32"] + avg["solve fp32-refined"]) * 1e-3,
+        "gmres_iters_fp64": last64.iters, "gmres_iters_fp32_inner_total": last32.iters,
+        "ir_outer_steps": last32.outer,
+        "true_relres_fp64": last64.true_relres, "true_relres_fp32_refined": last32.true_relres,
         "solve_tol": {"fp64_precond_relres": args.tol, "fp32_refined_fp64_relres": args.ir_tol,
                       "fp32_inner": args.inner_tol},
-        "solution_err_vs_fp64_1e-15_solve": {"fp64": err64, "fp32_refined": err32},
-        "fp32_refined_vs_fp64_rel_err": ir_vs_fp64, "discretisation_err_vs_exact_flux": disc64,
-        "gemv_V": {"ms": gemv_ms, "GB/s": gemv_gbs, "frac_hbm": gemv_gbs / HBM_PEAK_GBS},
-        "roofline": roof,
-        "kernel_ms_per_step": kernel_ms,
-        "kernel_units_per_launch": kernel_units,
+        "storage_GB": {"V+D fp64": 2 * entries * 8 / 1e9, "V+D fp32 (V hi+lo, D fp32)": entries * 12 / 1e9},
     }
+    out["gemv"] = gemv_rates(ktimes)
+    out["roofline"] = roofline(ktimes)
+    out["kernel_ms_per_step"] = {k: round(v[1] / args.steps, 3) for k, v in sorted(ktimes.items(), key=lambda kv: -kv[1][1])}
+    out["kernel_tflops"] = {k: v[3] / (v[1] * 1e-3) / 1e12 for k, v in ktimes.items() if v[3] > 0}
+    out["kernel_units_per_launch"] = {k: v[2] / v[0] for k, v in ktimes.items()}
+
+    if not args.no_accuracy:
+        # untimed: both timed solutions against an FP64 solve to 1e-15, the
+        # FP32-refined one against the FP64 one, and against the exact flux
+        ctx.assemble(L.V | L.D)
+        wref, _ = ctx.solve(f, tol=1e-15, max_it=800)
+        w64n, w32n, wrn = w64.cpu().numpy(), w32.cpu().numpy(), wref.cpu().numpy()
+        out["solution_err_vs_fp64_1e-15_solve"] = {"fp64": float(np.linalg.norm(w64n - wrn) / np.linalg.norm(wrn)),
+                                                   "fp32_refined": float(np.linalg.norm(w32n - wrn) / np.linalg.norm(wrn))}
+        out["fp32_refined_vs_fp64_rel_err"] = float(np.linalg.norm(w32n - w64n) / np.linalg.norm(w64n))
+        out["discretisation_err_vs_exact_flux"] = float(np.linalg.norm(w64n - wl.w_ref) / np.linalg.norm(wl.w_ref))
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        out["adjoint_diff_workload"] = adjoint_gradient(dev)
     if not args.no_paper_mesh:
-        ctx.close()
         out["paper_table2"] = paper_table2(dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample)
     print(json.dumps(out), flush=True)
 
 
+def gemv_rates(ktimes):
+    """Matrix-vector kernels: average launch time and stream rate (bytes of
+    the stored entries read once per product) from the timed steps."""
+    res = {}
+    for name, per in GEMV_BYTES.items():
+        if name in ktimes:
+            launches, ms, units = ktimes[name][:3]
+            gbs = per * units / (ms * 1e-3) / 1e9
+            res[name] = {"launch_ms": ms / launches, "GB/s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
+    return res
+
+
 def roofline(ktimes):
     """Roofline of the kernel with the largest event time in the timed steps:
-    algorithmic work per launch (per-unit figure x units per launch) over the
-    average launch duration from the HIP events."""
-    name, (launches, ms, units) = max(ktimes.items(), key=lambda kv: kv[1][1])
+    algorithmic work per launch (the library's operation count, or bytes for
+    a matrix-vector kernel) over the average launch duration from the HIP
+    events."""
+    name, (launches, ms, units, flops) = max(ktimes.items(), key=lambda kv: kv[1][1])
     per_launch_s = ms * 1e-3 / launches
     per_launch_units = units / launches
     traffic = HBM_BYTES_PER_UNIT.get(name)
     traffic = traffic * per_launch_units if traffic is not None else None
+    base = {"kernel": name, "launch_ms": per_launch_s * 1e3, "units_per_launch": per_launch_units, "traffic": traffic}
     if name in GEMV_BYTES:
         achieved = GEMV_BYTES[name] * per_launch_units / per_launch_s / 1e9
         return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": name,
-                "launch_ms": per_launch_s * 1e3, "units_per_launch": per_launch_units}
-    flop = FLOP_PER_UNIT.get(name)
-    achieved = flop * per_launch_units / per_launch_s / 1e12 if flop is not None else None
-    return {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_PEAK_TFLOPS if achieved is not None else None, "traffic": traffic,
-            "kernel": name, "launch_ms": per_launch_s * 1e3, "units_per_launch": per_launch_units,
-            "flop_per_unit": flop}
+                "frac": achieved / HBM_PEAK_GBS, **base}
+    peak = FP32_PEAK_TFLOPS if "f32" in name else FP64_PEAK_TFLOPS
+    achieved = flops / launches / per_launch_s / 1e12 if flops > 0 else None
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak if achieved is not None else None,
+            "flop_per_unit": flops / units if flops > 0 else None, **base}
+
+
+def adjoint_gradient(dev):
+    """The adjoint of the differentiation workload (128 segments x 128 steps,
+    N = 16384): gradient of J = 1/2 ||w_h - w_obs||^2 in g and alpha at
+    alpha = 1 (data from alpha* = 1.5 plus seeded noise): forward solve,
+    transposed solve, (1/2 M_h + K_h)^T lam and lam^T (dK g - dM0 u0 - dV w),
+    with the alpha-derivative matrices assembled; FP64, timed with HIP
+    events after one untimed pass."""
+    import torch
+    import workloads as W
+    import paper_1811_05224_amd as P
+    from paper_1811_05224_amd import _lib as L
+    wl = W.make("diff")
+    c = P.Context.from_workload(wl, device=dev)
+    g = torch.as_tensor(wl.g, device=dev)
+    u0 = torch.as_tensor(wl.u0, device=dev)
+    w_obs = torch.as_tensor(wl.w_ref + wl.extra["sigma"] * wl.extra["noise"], device=dev)
+    stream = torch.cuda.current_stream()
+    names = ("assemble V,K,D,M0", "assemble dV,dK,dM0", "forward solve", "adjoint solve", "grad g", "grad alpha")
+    res = None
+    for rep in range(2):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        e[0].record(stream)
+        c.assemble(L.V | L.K | L.D | L.M0)
+        e[1].record(stream)
+        c.assemble(L.DV | L.DK | L.DM0)
+        e[2].record(stream)
+        f = c.rhs(g, u0)
+        w, i1 = c.solve(f, tol=1e-12, max_it=300)
+        e[3].record(stream)
+        lam, i2 = c.solve(w - w_obs, tol=1e-12, max_it=300, trans=True)
+        e[4].record(stream)
+        gg = c.rhs_adjoint(lam)
+        e[5].record(stream)
+        ga = c.grad_alpha(lam, w, g, u0)
+        e[6].record(stream)
+        torch.cuda.synchronize()
+        res = {n: e[q].elapsed_time(e[q + 1]) for q, n in enumerate(names)}
+    c.close()
+    return {"workload": "diff: N_Gamma=128, N_I=128, N=16384, M_Omega=1089, alpha=1.0", "ms": res,
+            "gradient_ms": sum(res[n] for n in names[1:]), "iters": {"forward": i1.iters, "adjoint": i2.iters},
+            "dJ_dalpha": float(ga.cpu()[0]), "norm_dJ_dg": float(gg.norm())}
 
 
 def paper_table2(dev):

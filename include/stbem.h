@@ -100,32 +100,58 @@ int stbem_set_allocator(stbem_ctx* ctx, stbem_alloc_fn alloc, stbem_free_fn rele
 /* Sizes: N, n_bnd, n_t, n_vtx, entries of one packed causal matrix. */
 int stbem_sizes(const stbem_ctx* ctx, long long* n, int* n_bnd, int* n_t, int* n_vtx, long long* packed_entries);
 
-/* Assemble the operators in `mask` (STBEM_V | ...) into context storage.
- * Every entry is an exact-in-time (E1 closed form / Laguerre series) and
- * fixed-rule-in-space Galerkin integral; blocks with tau_m after tau_k are
- * never computed.  Re-assembling replaces the old storage. */
-int stbem_assemble(stbem_ctx* ctx, unsigned mask, void* stream);
+/* Assemble the operators in `mask` (STBEM_V | ...) of eq.(4) and, for
+ * STBEM_D, of Theorem 1 (Sec. 2) into context storage.  Every entry is an
+ * exact-in-time (E1 closed form / Laguerre series) and fixed-rule-in-space
+ * Galerkin integral computed in FP64; blocks with tau_m after tau_k are never
+ * computed (Sec. 3, block lower triangular).
+ * precision = STBEM_FP64: FP64 storage (8 bytes per entry).
+ * precision = STBEM_FP32_IR: only STBEM_V and STBEM_D may be in `mask` (else
+ *   STBEM_EINVAL; also refused in block-Toeplitz mode).  V_h is stored as the
+ *   float pair hi = fl32(V), lo = fl32(V - hi) (about 48 bits together), D_h
+ *   as float (D_h only shapes the preconditioner); 12 bytes per entry pair
+ *   instead of 16.  The FP64 storage of these operators is freed, and
+ *   operators that need FP64 V_h or D_h (FP64 solves) are unavailable until
+ *   they are assembled again in FP64.
+ * Re-assembling an operator replaces its storage; assembling V_h or D_h in
+ * FP64 drops FP32 copies made from the previous FP64 storage.  Allocation
+ * failure returns STBEM_ENOMEM (the storage of the failed operator is not
+ * kept). */
+int stbem_assemble(stbem_ctx* ctx, unsigned mask, int precision, void* stream);
 
-/* Free the storage of the operators in `mask` (and the FP32 copies when
- * STBEM_V or STBEM_D is released), e.g. K_h and M_h^0 once the right-hand
- * side is formed.  Synchronisation is the caller's: no kernel may still use
- * that storage. */
+/* Free the storage of the operators in `mask` (for STBEM_V / STBEM_D also
+ * their FP32 storage), e.g. K_h and M_h^0 once the right-hand side is formed.
+ * Synchronisation is the caller's: no kernel may still use that storage. */
 int stbem_release(stbem_ctx* ctx, unsigned mask);
 
-/* Device pointer and size in bytes of an assembled operator's storage
- * (op is one of STBEM_V ... STBEM_DM0); owned by the context. */
+/* Device pointer and size in bytes of an assembled operator's FP64 storage
+ * (op is one of STBEM_V ... STBEM_DM0); owned by the context.
+ * STBEM_ENOTASSEMBLED if the operator has no FP64 storage. */
 int stbem_matrix(stbem_ctx* ctx, unsigned op, const double** dev_ptr, size_t* bytes);
+
+/* FP32 storage of V_h (hi and lo; lo is NULL when the FP32 copy was made from
+ * a resident FP64 V_h by stbem_prepare_ir) or D_h (hi only, lo = NULL),
+ * same packed layout as the FP64 storage; bytes = size of one float array.
+ * Owned by the context.  STBEM_ENOTASSEMBLED if there is none. */
+int stbem_matrix_f32(stbem_ctx* ctx, unsigned op, const float** hi_dev, const float** lo_dev, size_t* bytes);
 
 /* y = A x (trans = 0) or y = A^T x (trans = 1) for an assembled operator
  * (STBEM_V, STBEM_K, STBEM_D, STBEM_DV, STBEM_DK: N-vectors;
- *  STBEM_M0, STBEM_DM0: x has n_vtx entries for trans = 0, N for trans = 1). */
+ *  STBEM_M0, STBEM_DM0: x has n_vtx entries for trans = 0, N for trans = 1).
+ * FP64 storage is used when present; V_h held only in FP32 storage is applied
+ * as hi + lo with FP64 accumulation, D_h held only in FP32 as float.
+ * x and y must not overlap.  The matrix-vector product streams every stored
+ * entry once and adds partial sums in a fixed order (bitwise reproducible). */
 int stbem_apply(stbem_ctx* ctx, unsigned op, int trans, const double* x_dev, double* y_dev, void* stream);
 
 /* M_h g for g in X_h^{1,0} (trans = 0) or M_h^T x (trans = 1). */
 int stbem_mass(stbem_ctx* ctx, int trans, const double* x_dev, double* y_dev, void* stream);
 
-/* Preconditioner of Theorem 1 with the lumped mass of Sec. 4:
- * z = Mt^{-1} D_h Mt^{-1} r (trans = 1: D_h^T). Needs STBEM_D. */
+/* Preconditioner of Theorem 1 (Sec. 2) with the lumped mass of Sec. 4:
+ * z = Mt^{-1} D_h Mt^{-1} r (trans = 1: D_h^T), Mt[(m,i)] = h_m (L_{i-1} +
+ * 2 L_i + L_{i+1})/4 the row sums of the dual-primal mass matrix.  Needs
+ * STBEM_D (FP64 storage, else FP32 storage).  r and z are N-vectors that must
+ * not overlap.  Stream-ordered; uses work vectors kept by the context. */
 int stbem_precondition(stbem_ctx* ctx, int trans, const double* r_dev, double* z_dev, void* stream);
 
 /* Right-hand side of eq.(4): f = (1/2 M_h + K_h) g - M_h^0 u0.
@@ -134,9 +160,16 @@ int stbem_precondition(stbem_ctx* ctx, int trans, const double* r_dev, double* z
  * the N x n_vtx matrix does not fit); the result is the same product. */
 int stbem_rhs(stbem_ctx* ctx, const double* g_dev, const double* u0_dev, double* f_dev, void* stream);
 
-/* FP32 copies for the refinement solve: V_h as a float pair hi + lo
- * (hi = fl32(V), lo = fl32(V - hi)) and D_h as float.  Needs STBEM_V and
- * STBEM_D; stbem_solve calls it on first use of STBEM_FP32_IR. */
+/* Adjoint of the right-hand side operator of eq.(4) in g:
+ * out = (1/2 M_h + K_h)^T lam, the gradient of a functional J(w) in the
+ * Dirichlet data g when lam solves V_h^T lam = dJ/dw.  Needs STBEM_K.
+ * lam and out are N-vectors (device) that must not overlap. */
+int stbem_rhs_adjoint(stbem_ctx* ctx, const double* lam_dev, double* out_dev, void* stream);
+
+/* FP32 copies for the refinement solve from resident FP64 storage: V_h as
+ * float hi = fl32(V) (the outer residual then reads the FP64 V_h) and D_h as
+ * float.  Nothing is done for an operator that already has FP32 storage.
+ * stbem_solve calls it on first use of STBEM_FP32_IR.  Needs STBEM_V. */
 int stbem_prepare_ir(stbem_ctx* ctx, void* stream);
 
 typedef struct {
@@ -154,27 +187,42 @@ typedef struct {
     int iters;             /* GMRES iterations (IR: summed over inner solves)      */
     int outer;             /* IR outer steps                                      */
     double relres;         /* final preconditioned relative residual estimate     */
-    double true_relres;    /* ||f - V w|| / ||f|| computed in FP64 at the end     */
+    double true_relres;    /* ||f - V w|| / ||f|| at the end, FP64 accumulation
+                              with the FP64 V_h (or hi + lo if V_h is FP32 only) */
 } stbem_solve_info;
 
-/* Solve V_h w = f (or V_h^T w = f) with left-preconditioned GMRES, x0 = 0.
- * Needs STBEM_V (and STBEM_D when preconditioned).  FP32_IR stores V_h and
- * D_h in float32 for the inner solves and keeps the residual of the outer
- * refinement, the Krylov basis and its orthogonalisation in float64.
- * Synchronises the stream.  Returns STBEM_WARN_NOT_CONVERGED if tol was not
- * reached (w holds the last iterate). */
+/* Solve the Galerkin system eq.(4), V_h w = f (or V_h^T w = f for an
+ * adjoint), with GMRES left-preconditioned by C_V^{-1} = Mt^{-1} D_h Mt^{-1}
+ * (Sec. 2, Theorem 1 and the lumped mass of Sec. 4): x0 = 0, no restart,
+ * classical Gram-Schmidt twice, Givens rotations; stops when
+ * ||C (f - V w)|| <= tol ||C f|| (Sec. 4 solves to a relative precision).
+ * STBEM_FP64 needs FP64 V_h (and D_h when preconditioned).
+ * STBEM_FP32_IR (iterative refinement): r = f - V w in FP64 accumulation
+ * with the FP64 V_h if resident, else with the pair hi + lo; inner
+ * preconditioned GMRES to inner_tol on float V_h (hi) and float D_h with the
+ * Krylov basis and its orthogonalisation in float64; w += correction; stops
+ * when ||r|| <= ir_tol ||f||.  Missing FP32 copies are made from FP64
+ * storage (stbem_prepare_ir).
+ * f and w are N-vectors that must not overlap.  Synchronises the stream.
+ * Returns STBEM_WARN_NOT_CONVERGED if tol was not reached (w holds the last
+ * iterate), STBEM_WARN_IR_STAGNATION if an outer step did not halve the
+ * residual. */
 int stbem_solve(stbem_ctx* ctx, const double* f_dev, double* w_dev, const stbem_solve_opts* opts,
                 stbem_solve_info* info, void* stream);
 
 /* d J / d alpha contribution lambda^T (dK_h g - dM_h^0 u0 - dV_h w) for an
- * adjoint state lambda (from a trans = 1 solve).  Needs STBEM_DV, STBEM_DK
- * and, if u0_dev is not NULL, STBEM_DM0.  The scalar is written to
- * out_dev[0] (device).  */
+ * adjoint state lambda (from a trans = 1 solve): the alpha-derivative of
+ * eq.(4), V_h w = (1/2 M_h + K_h) g - M_h^0 u0, with M_h independent of
+ * alpha.  Needs STBEM_DV, STBEM_DK and, if u0_dev is not NULL, STBEM_DM0.
+ * The scalar is written to out_dev[0] (device).  */
 int stbem_grad_alpha(stbem_ctx* ctx, const double* lambda_dev, const double* w_dev, const double* g_dev,
                      const double* u0_dev, double* out_dev, void* stream);
 
-/* Sampled entries of V/K/D/dV/dK computed directly by the assembly kernels'
- * device code (idx_dev: n quadruples (k, m, i, j) as int32; out_dev: n). */
+/* Sampled entries A[(k,i),(m,j)] of V/K/D/dV/dK (eq.(4); Theorem 1)
+ * computed directly by the assembly kernels' device code (idx_dev: n
+ * quadruples (k, m, i, j) as int32; out_dev: n).  An entry above the block
+ * diagonal (k < m) is 0; a quadruple outside the matrix (an index < 0,
+ * k or m >= n_t, i or j >= n_bnd) gives NaN. */
 int stbem_entries(stbem_ctx* ctx, unsigned op, long long n, const int* idx_dev, double* out_dev, void* stream);
 
 /* The representation formula (Sec. 1, eq. (2)) at n points of Q:
@@ -209,17 +257,24 @@ int stbem_set_toeplitz(stbem_ctx* ctx, int on);
  * HIP events recorded on the stream it runs on (a few microseconds of host
  * work per launch); on = 0 stops.  Either call first waits for and drops the
  * records taken so far.  stbem_kernel_times sums the records per kernel name
- * (the names of the kernels in the library): launches, event time in ms and
- * the work units the launches processed: matrix entries for the V_h, K_h,
- * D_h kernels and the matrix-vector kernels, (row, triangle) pairs for the
- * M_h^0 moment kernels, matrix entries for the M_h^0 gather.  It writes at
- * most `cap` records to `out` (host) and returns the number of names, or a
- * negative error; it waits for the recorded events. */
+ * (the names of the kernels in the library): launches, event time in ms, the
+ * work units the launches processed (matrix entries for the V_h, K_h, D_h
+ * kernels and the matrix-vector kernels, (row, triangle) pairs for the M_h^0
+ * moment kernels, matrix entries for the M_h^0 gather) and, for the far-field
+ * (series) assembly kernels, their algorithmic operation count: per node
+ * pair of the Gauss rule a fixed setup and evaluation cost (with an
+ * exponential counted as 29 operations) plus a fixed cost per series term,
+ * times the terms of each block, plus the combination per entry.  It writes
+ * at most `cap` records to `out` (host) and returns the number of names, or
+ * a negative error; it waits for the recorded events. */
 typedef struct {
     char name[48];
     long long launches;
     double ms;
     double units;
+    double flops;      /* algorithmic floating-point operations of the launches
+                          (FMA = 2) from the library's operation count of the
+                          series-based far-field kernels; 0 for other kernels */
 } stbem_kernel_time;
 int stbem_set_timing(stbem_ctx* ctx, int on);
 int stbem_kernel_times(stbem_ctx* ctx, stbem_kernel_time* out, int cap);

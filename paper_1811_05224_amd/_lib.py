@@ -26,7 +26,7 @@ class stbem_solve_opts(ctypes.Structure):
 
 class stbem_kernel_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_longlong), ("ms", ctypes.c_double),
-                ("units", ctypes.c_double)]
+                ("units", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
 class stbem_solve_info(ctypes.Structure):
@@ -56,13 +56,15 @@ def load():
         "stbem_last_error": (ctypes.c_char_p, [vp]),
         "stbem_set_allocator": (ctypes.c_int, [vp, ALLOC_FN, FREE_FN, vp]),
         "stbem_sizes": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_longlong), ip, ip, ip, ctypes.POINTER(ctypes.c_longlong)]),
-        "stbem_assemble": (ctypes.c_int, [vp, ctypes.c_uint, vp]),
+        "stbem_assemble": (ctypes.c_int, [vp, ctypes.c_uint, ctypes.c_int, vp]),
         "stbem_release": (ctypes.c_int, [vp, ctypes.c_uint]),
         "stbem_matrix": (ctypes.c_int, [vp, ctypes.c_uint, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]),
+        "stbem_matrix_f32": (ctypes.c_int, [vp, ctypes.c_uint, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]),
         "stbem_apply": (ctypes.c_int, [vp, ctypes.c_uint, ctypes.c_int, vp, vp, vp]),
         "stbem_mass": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
         "stbem_precondition": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
         "stbem_rhs": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+        "stbem_rhs_adjoint": (ctypes.c_int, [vp, vp, vp, vp]),
         "stbem_prepare_ir": (ctypes.c_int, [vp, vp]),
         "stbem_solve": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(stbem_solve_opts), ctypes.POINTER(stbem_solve_info), vp]),
         "stbem_grad_alpha": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
@@ -80,6 +82,7 @@ def load():
 
 
 EXPORTED = ["stbem_create", "stbem_destroy", "stbem_last_error", "stbem_set_allocator", "stbem_sizes",
-            "stbem_assemble", "stbem_release", "stbem_matrix", "stbem_apply", "stbem_mass", "stbem_precondition", "stbem_rhs",
+            "stbem_assemble", "stbem_release", "stbem_matrix", "stbem_matrix_f32", "stbem_apply", "stbem_mass",
+            "stbem_precondition", "stbem_rhs", "stbem_rhs_adjoint",
             "stbem_prepare_ir", "stbem_solve", "stbem_grad_alpha", "stbem_entries", "stbem_set_timing",
             "stbem_kernel_times", "stbem_set_toeplitz", "stbem_potential"]

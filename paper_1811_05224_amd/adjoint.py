@@ -1,9 +1,9 @@
 """Differentiable flux solve: w = V_h^{-1} [(1/2 M_h + K_h) g - M_h^0 u0].
 
 Backward (hand-written adjoint, every product in the HIP library):
-    V_h^T lam = dJ/dw                       (GMRES, preconditioner Mt^-1 D_h^T Mt^-1)
-    dJ/dg     = (1/2 M_h + K_h)^T lam
-    dJ/dalpha = lam^T (dK_h/dalpha g - dM_h^0/dalpha u0 - dV_h/dalpha w)
+    V_h^T lam = dJ/dw                       (stbem_solve, trans: GMRES with Mt^-1 D_h^T Mt^-1)
+    dJ/dg     = (1/2 M_h + K_h)^T lam       (stbem_rhs_adjoint)
+    dJ/dalpha = lam^T (dK_h/dalpha g - dM_h^0/dalpha u0 - dV_h/dalpha w)   (stbem_grad_alpha)
 The alpha-derivative matrices are assembled analytically (closed forms of the
 derivatives of the time integrals), see include/stbem.h.
 """
@@ -11,7 +11,6 @@ from __future__ import annotations
 
 import torch
 
-from . import _lib as L
 
 
 class HeatFluxSolve(torch.autograd.Function):
@@ -48,7 +47,7 @@ class HeatFluxSolve(torch.autograd.Function):
             raise RuntimeError(f"adjoint solve did not converge: {info}")
         grad_g = grad_alpha = None
         if fctx.needs_input_grad[0]:
-            grad_g = 0.5 * ctx.mass(lam, trans=True) + ctx.apply(L.K, lam, trans=True)
+            grad_g = ctx.rhs_adjoint(lam)
         if fctx.needs_input_grad[1]:
             grad_alpha = ctx.grad_alpha(lam, w, g, u0).reshape(())
         return grad_g, grad_alpha, None, None, None

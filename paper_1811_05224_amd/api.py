@@ -31,6 +31,18 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+def check_entry_indices(idx, nt, ng):
+    """Entry quadruples (k, m, i, j) as an (n, 4) int32 array, all inside the
+    matrix (0 <= k, m < nt, 0 <= i, j < ng); raises ValueError otherwise."""
+    a = np.asarray(idx)
+    if a.size % 4:
+        raise ValueError("entry indices come in quadruples (k, m, i, j)")
+    a = a.reshape(-1, 4)
+    if a.size and (a.min() < 0 or a[:, :2].max() >= nt or a[:, 2:].max() >= ng):
+        raise ValueError(f"entry index outside the matrix (n_t = {nt}, n_bnd = {ng})")
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
 class Context:
     """One problem (Gamma_h polygon, time grid, alpha, Omega_h) on one GPU.
 
@@ -109,25 +121,53 @@ class Context:
             return torch.zeros(n if n is not None else self.n, dtype=torch.float64, device=self.device)
         return torch.as_tensor(x, dtype=torch.float64, device=self.device).contiguous()
 
+    def _in(self, x, n, name):
+        """x as a contiguous float64 tensor on the context's device with n entries."""
+        t = self.vec(x)
+        if t.numel() != n:
+            raise ValueError(f"{name} needs {n} entries, got {t.numel()}")
+        return t
+
+    def _out(self, out, n, name):
+        if out is None:
+            return self.vec(n=n)
+        if (out.dtype != torch.float64 or out.device != self.device or not out.is_contiguous()
+                or out.numel() != n):
+            raise ValueError(f"{name}: a contiguous float64 tensor of {n} entries on {self.device} is needed")
+        return out
+
     # ---------------------------------------------------------------- calls
-    def assemble(self, mask):
-        self._check(self.lib.stbem_assemble(self._h, int(mask), self._stream()), "stbem_assemble")
+    def assemble(self, mask, precision=L.FP64):
+        """Assemble the operators in mask; precision FP32_IR (V, D only) keeps
+        V_h as an FP32 hi + lo pair and D_h as FP32 instead of FP64."""
+        self._check(self.lib.stbem_assemble(self._h, int(mask), int(precision), self._stream()), "stbem_assemble")
 
     def release(self, mask):
         torch.cuda.current_stream().synchronize()
         self._check(self.lib.stbem_release(self._h, int(mask)), "stbem_release")
 
     def matrix(self, op):
-        """The operator's storage as a float64 tensor (packed blocks or dense M0)."""
+        """The operator's FP64 storage as a float64 tensor (packed blocks or dense M0)."""
         p, nb = ctypes.c_void_p(), ctypes.c_size_t()
         self._check(self.lib.stbem_matrix(self._h, int(op), ctypes.byref(p), ctypes.byref(nb)), "stbem_matrix")
         t = self._tensors[p.value]
         return t[: nb.value].view(torch.float64)
 
+    def _nblocks(self):
+        return self.nt if self.toeplitz else self.nt * (self.nt + 1) // 2
+
     def packed(self, op):
         """Stored blocks of a causal operator: [k(k+1)/2 + m] packed, or [k - m] in block-Toeplitz mode."""
-        nb = self.nt if self.toeplitz else self.nt * (self.nt + 1) // 2
-        return self.matrix(op).view(nb, self.ng, self.ng)
+        return self.matrix(op).view(self._nblocks(), self.ng, self.ng)
+
+    def packed_f32(self, op):
+        """FP32 storage of V_h (hi, lo) or D_h (hi, None) as [block, ng, ng] float32 tensors."""
+        hi, lo, nb = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_size_t()
+        self._check(self.lib.stbem_matrix_f32(self._h, int(op), ctypes.byref(hi), ctypes.byref(lo), ctypes.byref(nb)),
+                    "stbem_matrix_f32")
+        shape = (self._nblocks(), self.ng, self.ng)
+        view = lambda p: self._tensors[p][: nb.value].view(torch.float32).view(shape)
+        return view(hi.value), (view(lo.value) if lo.value else None)
 
     def set_toeplitz(self, on=True):
         """Block-Toeplitz storage (uniform time steps only); frees the assembled causal operators."""
@@ -135,40 +175,49 @@ class Context:
         self.toeplitz = bool(on)
 
     def apply(self, op, x, trans=False, out=None):
-        x = self.vec(x)
-        rows = self.n if (op not in (L.M0, L.DM0) or trans) else self.n
-        if op in (L.M0, L.DM0) and trans:
-            rows = self.nv
-        y = out if out is not None else self.vec(n=rows)
+        dense = op in (L.M0, L.DM0)
+        nin = self.nv if (dense and not trans) else self.n
+        nout = self.nv if (dense and trans) else self.n
+        x = self._in(x, nin, "x")
+        y = self._out(out, nout, "out")
         self._check(self.lib.stbem_apply(self._h, int(op), int(bool(trans)), _ptr(x), _ptr(y), self._stream()), "stbem_apply")
         return y
 
     def mass(self, x, trans=False):
-        x = self.vec(x)
+        x = self._in(x, self.n, "x")
         y = self.vec(n=self.n)
         self._check(self.lib.stbem_mass(self._h, int(bool(trans)), _ptr(x), _ptr(y), self._stream()), "stbem_mass")
         return y
 
     def precondition(self, r, trans=False):
-        r = self.vec(r)
+        r = self._in(r, self.n, "r")
         z = self.vec(n=self.n)
         self._check(self.lib.stbem_precondition(self._h, int(bool(trans)), _ptr(r), _ptr(z), self._stream()), "stbem_precondition")
         return z
 
     def rhs(self, g, u0=None):
-        g = self.vec(g)
-        u0 = self.vec(u0) if u0 is not None else None
+        g = self._in(g, self.n, "g")
+        u0 = self._in(u0, self.nv, "u0") if u0 is not None else None
         f = self.vec(n=self.n)
         self._check(self.lib.stbem_rhs(self._h, _ptr(g), _ptr(u0), _ptr(f), self._stream()), "stbem_rhs")
         return f
+
+    def rhs_adjoint(self, lam):
+        """(1/2 M_h + K_h)^T lam: the gradient in g for an adjoint state lam."""
+        lam = self._in(lam, self.n, "lam")
+        out = self.vec(n=self.n)
+        self._check(self.lib.stbem_rhs_adjoint(self._h, _ptr(lam), _ptr(out), self._stream()), "stbem_rhs_adjoint")
+        return out
 
     def prepare_ir(self):
         self._check(self.lib.stbem_prepare_ir(self._h, self._stream()), "stbem_prepare_ir")
 
     def solve(self, f, tol=1e-12, max_it=300, mode=L.FP64, trans=False, precondition=True,
               inner_tol=1e-5, max_outer=10, ir_tol=1e-12, out=None):
-        f = self.vec(f)
-        w = out if out is not None else self.vec(n=self.n)
+        f = self._in(f, self.n, "f")
+        w = self._out(out, self.n, "out")
+        if w.data_ptr() == f.data_ptr():
+            raise ValueError("out must not be the right-hand side")
         o = L.stbem_solve_opts(float(tol), int(max_it), int(mode), int(bool(trans)), int(bool(precondition)),
                                float(inner_tol), int(max_outer), float(ir_tol))
         info = L.stbem_solve_info()
@@ -177,9 +226,10 @@ class Context:
         return w, SolveInfo(info.iters, info.outer, info.relres, info.true_relres, rc)
 
     def grad_alpha(self, lam, w, g, u0=None):
+        lam, w, g = self._in(lam, self.n, "lam"), self._in(w, self.n, "w"), self._in(g, self.n, "g")
+        u0 = self._in(u0, self.nv, "u0") if u0 is not None else None
         out = self.vec(n=1)
-        self._check(self.lib.stbem_grad_alpha(self._h, _ptr(self.vec(lam)), _ptr(w), _ptr(g),
-                                              _ptr(self.vec(u0)) if u0 is not None else None, _ptr(out),
+        self._check(self.lib.stbem_grad_alpha(self._h, _ptr(lam), _ptr(w), _ptr(g), _ptr(u0), _ptr(out),
                                               self._stream()), "stbem_grad_alpha")
         return out
 
@@ -200,15 +250,16 @@ class Context:
         self._check(self.lib.stbem_set_timing(self._h, 1 if on else 0), "stbem_set_timing")
 
     def kernel_times(self):
-        """{kernel name: (launches, event ms, work units)} recorded since timing was switched on."""
+        """{kernel name: (launches, event ms, work units, algorithmic flops)} recorded since timing was switched on."""
         cap = 64
         buf = (L.stbem_kernel_time * cap)()
         n = self.lib.stbem_kernel_times(self._h, buf, cap)
         self._check(min(n, 0), "stbem_kernel_times")
-        return {buf[e].name.decode(): (buf[e].launches, buf[e].ms, buf[e].units) for e in range(min(n, cap))}
+        return {buf[e].name.decode(): (buf[e].launches, buf[e].ms, buf[e].units, buf[e].flops) for e in range(min(n, cap))}
 
     def entries(self, op, idx):
-        idx = torch.as_tensor(np.asarray(idx, dtype=np.int32).reshape(-1, 4), device=self.device).contiguous()
+        idx = check_entry_indices(idx, self.nt, self.ng)
+        idx = torch.as_tensor(idx, device=self.device).contiguous()
         out = self.vec(n=idx.shape[0])
         self._check(self.lib.stbem_entries(self._h, int(op), idx.shape[0], _ptr(idx), _ptr(out), self._stream()),
                     "stbem_entries")

@@ -65,6 +65,22 @@ __device__ __forceinline__ void tile_of(int tile, int t1, bool sym, int& ti, int
     ti = r; tj = r + tile;
 }
 
+// Matrix storage written by the assembly kernels: FP64, or FP32 (hi only),
+// or the FP32 pair hi = fl32(v), lo = fl32(v - hi) that keeps about 48 bits.
+// Which one is uniform over a launch, so the branch costs nothing per lane.
+struct OutBuf {
+    double* f64;
+    float* hi;
+    float* lo;
+    __device__ __forceinline__ void put(long long e, double v) const
+    {
+        if (f64) { f64[e] = v; return; }
+        const float h = (float)v;
+        hi[e] = h;
+        if (lo) lo[e] = (float)(v - (double)h);
+    }
+};
+
 // Store the tile value of lane (il, jl) (entry (I0+il, J0+jl) of the block at
 // boff).  For a symmetric operator an off-diagonal tile also stores its
 // transposed tile, and a diagonal tile stores the values of its upper half
@@ -72,21 +88,21 @@ __device__ __forceinline__ void tile_of(int tile, int t1, bool sym, int& ti, int
 // row-contiguous and the stored blocks are exactly symmetric.  Every lane of
 // the workgroup must call it.
 __device__ __forceinline__ void store_tile(double (*stage)[kTile + 1], bool sym, double v, bool live, long long boff,
-                                          int ng, int I0, int J0, int il, int jl, double* __restrict__ out)
+                                          int ng, int I0, int J0, int il, int jl, const OutBuf& out)
 {
     if (!sym) {
-        if (live) out[boff + (long long)(I0 + il) * ng + J0 + jl] = v;
+        if (live) out.put(boff + (long long)(I0 + il) * ng + J0 + jl, v);
         return;
     }
     stage[il][jl] = v;
     __syncthreads();
     if (I0 == J0) {
-        if (live) out[boff + (long long)(I0 + il) * ng + J0 + jl] = il <= jl ? v : stage[jl][il];
+        if (live) out.put(boff + (long long)(I0 + il) * ng + J0 + jl, il <= jl ? v : stage[jl][il]);
         return;
     }
-    if (live) out[boff + (long long)(I0 + il) * ng + J0 + jl] = v;
+    if (live) out.put(boff + (long long)(I0 + il) * ng + J0 + jl, v);
     const int r = J0 + il, col = I0 + jl;
-    if (r < ng && col < ng) out[boff + (long long)r * ng + col] = stage[jl][il];
+    if (r < ng && col < ng) out.put(boff + (long long)r * ng + col, stage[jl][il]);
 }
 
 // lanes whose value a symmetric tile takes from the mirror: the lower half
@@ -108,7 +124,7 @@ __global__ __launch_bounds__(kWG) void k_time_blocks(Geom g, long long nb, TimeB
 template <int OP>
 __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restrict__ Tg, Orders O,
                                                   double lmax, const int* __restrict__ blist, int tiles_1d,
-                                                  double* __restrict__ out64, const TimeBlock* __restrict__ tbs)
+                                                  OutBuf out, const TimeBlock* __restrict__ tbs)
 {
     constexpr bool SYM = sym_op(OP);
     __shared__ Tables T;
@@ -168,7 +184,7 @@ __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restri
     } else if (own) {
         v = entry<OP>(T, O, g, tb, qf, i, j);
     }
-    store_tile(stage, SYM, v, live, block_slot(g, b, k, m) * g.ng * g.ng, g.ng, I0, J0, il, jl, out64);
+    store_tile(stage, SYM, v, live, block_slot(g, b, k, m) * g.ng * g.ng, g.ng, I0, J0, il, jl, out);
 }
 
 // V_h and K_h on separated time elements (series), Gauss order Q fixed at
@@ -227,7 +243,7 @@ __device__ __forceinline__ void far_pair(const Tables& T, const TimeBlock& tb, d
 template <int OP, int Q>
 __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __restrict__ Tg,
                                                         const int* __restrict__ blist, int tiles_i, int tiles_j,
-                                                        double* __restrict__ out64, const TimeBlock* __restrict__ tbs)
+                                                        OutBuf out, const TimeBlock* __restrict__ tbs)
 {
     constexpr bool SYM = OP == OP_V;
     __shared__ double stage[kTile][kTile + 1];
@@ -257,13 +273,13 @@ __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __
     }
     const long long boff = block_slot(g, b, k, m) * g.ng * g.ng, rowoff = boff + (long long)i * g.ng;
     if (OP == OP_V) {
-        store_tile(stage, true, m0, live, boff, g.ng, ti * kTile, J0, ty, tx, out64);
+        store_tile(stage, true, m0, live, boff, g.ng, ti * kTile, J0, ty, tx, out);
     } else {
         // lanes of one tile row are consecutive: the rising moment of segment
         // j - 1 sits in the lane to the left
         const double left = __shfl_up(m1, 1, kTile);
         const int j = J0 + tx - 1;
-        if (tx >= 1 && i < g.ng && j < g.ng) out64[rowoff + j] = left + m0;
+        if (tx >= 1 && i < g.ng && j < g.ng) out.put(rowoff + j, left + m0);
     }
 }
 
@@ -388,8 +404,7 @@ __device__ __forceinline__ void far_dpair(const Tables& T, const TimeBlock& tb, 
 template <int Q, bool WV>
 __global__ __launch_bounds__(kWG, (Q == 3 || (Q == 4 && !WV)) ? 3 : 1) void k_assemble_dfar(Geom g, const Tables* __restrict__ Tg,
                                                        const int* __restrict__ blist, int tiles_1d,
-                                                       double* __restrict__ out64, double* __restrict__ outv,
-                                                       const TimeBlock* __restrict__ tbs)
+                                                       OutBuf out, OutBuf outv, const TimeBlock* __restrict__ tbs)
 {
     __shared__ double mom[kDP][kDP][4];
     __shared__ double pc[2][kDP][7];       // ax ay ex ey len nx ny
@@ -453,7 +468,7 @@ __global__ __launch_bounds__(kWG, (Q == 3 || (Q == 4 && !WV)) ? 3 : 1) void k_as
         }
     }
     const long long boff = block_slot(g, b, k, m) * g.ng * g.ng;
-    store_tile(stage, true, acc, live, boff, g.ng, I0, J0, il, jl, out64);
+    store_tile(stage, true, acc, live, boff, g.ng, I0, J0, il, jl, out);
     if (WV) {
         __syncthreads();          // the stage is reused
         store_tile(stage, true, own ? vsum : 0.0, live, boff, g.ng, I0, J0, il, jl, outv);
@@ -475,7 +490,7 @@ __global__ __launch_bounds__(kWG, (Q == 3 || (Q == 4 && !WV)) ? 3 : 1) void k_as
 template <bool WV>
 __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __restrict__ Tg, Orders O,
                                                         const int* __restrict__ blist, int tiles_1d,
-                                                        double* __restrict__ out64, double* __restrict__ outv)
+                                                        OutBuf out, OutBuf outv)
 {
     __shared__ Tables T;
     __shared__ TimeBlock tb;
@@ -606,7 +621,9 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
         }
         __syncthreads();
         if (my == 0 && !mir) {
-            double acc = 0.0;
+            // the curl and the normal part of neighbouring dual functions
+            // nearly cancel: every term goes into a compensated sum
+            CSum acc = {0.0, 0.0};
             for (int u = 0; u < 4; ++u) {
                 double a0, a1;
                 hat(si, u, pc[0][ui + u].len, a0, a1);
@@ -614,15 +631,16 @@ __global__ __launch_bounds__(kWG) void k_assemble_dnear(Geom g, const Tables* __
                     double b0, b1;
                     hat(sj, v, pc[1][vj + v].len, b0, b1);
                     const double* M = mom[ui + u][vj + v];
-                    acc += si.slope[u] * sj.slope[v] * M[0]
-                         + a0 * (b0 * M[1] + b1 * M[2]) + a1 * (b0 * M[3] + b1 * M[4]);
+                    acc.add(si.slope[u] * sj.slope[v] * M[0]);
+                    acc.add(a0 * b0 * M[1]); acc.add(a0 * b1 * M[2]);
+                    acc.add(a1 * b0 * M[3]); acc.add(a1 * b1 * M[4]);
                 }
             }
-            val = acc;
+            val = acc.value();
         }
     }
     const long long boff = block_slot(g, b, k, m) * g.ng * g.ng;
-    store_tile(stage, true, val, inside, boff, g.ng, I0, J0, il, jl, out64);
+    store_tile(stage, true, val, inside, boff, g.ng, I0, J0, il, jl, out);
     if (WV) {
         double v = 0.0;
         if (inside && !mir) {
@@ -649,6 +667,7 @@ __global__ __launch_bounds__(kWG) void k_entries(Geom g, const Tables* __restric
     long long e = (long long)blockIdx.x * kWG + threadIdx.x;
     if (e >= n) return;
     int k = idx[4 * e], m = idx[4 * e + 1], i = idx[4 * e + 2], j = idx[4 * e + 3];
+    if (k < 0 || m < 0 || k >= g.nt || m >= g.nt || i < 0 || i >= g.ng || j < 0 || j >= g.ng) { out[e] = NAN; return; }   // outside the matrix
     if (k < m) { out[e] = 0.0; return; }
     TimeBlock tb;
     time_block(g, k, m, tb);
@@ -1208,6 +1227,11 @@ __global__ __launch_bounds__(kWG) void k_axpby(long long n, double a, const doub
     long long e = (long long)blockIdx.x * kWG + threadIdx.x;
     if (e < n) y[e] = a * x[e] + (b == 0.0 ? 0.0 : b * y[e]);
 }
+__global__ __launch_bounds__(kWG) void k_fill(long long n, double v, double* __restrict__ y)
+{
+    long long e = (long long)blockIdx.x * kWG + threadIdx.x;
+    if (e < n) y[e] = v;
+}
 
 // y = x / d
 __global__ __launch_bounds__(kWG) void k_div(long long n, const double* __restrict__ x, const double* __restrict__ d,
@@ -1306,16 +1330,26 @@ struct stbem_ctx {
     // operators
     double* mat[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};   // V K D M0 DV DK DM0
     size_t mat_bytes[7] = {0, 0, 0, 0, 0, 0, 0};
+    // FP32 storage of V_h (hi, and lo when V_h has no FP64 storage) and D_h:
+    // written by an assembly in STBEM_FP32_IR (then the FP64 storage of that
+    // operator is not kept) or converted from FP64 storage (stbem_prepare_ir)
     float *v_hi = nullptr, *v_lo = nullptr, *d_32 = nullptr;
     // block lists per operator slot: [generic | far Q=3..8 (V, K) or tile kernel (D)]
     int* d_blist[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     int nlist_touch[7] = {0, 0, 0, 0, 0, 0, 0};   // D_h: touching blocks for the tile kernel (list head)
     int nlist_gen[7] = {0, 0, 0, 0, 0, 0, 0};
     int nlist_far[7][9] = {};
+    std::vector<int> list_nterm[7];       // series terms of each listed block (host copy, for the work model)
     bool vd_fusable = false;              // V_h and D_h have the same far-tile block lists
     // work
     double* part = nullptr;     // nblk * ng
     size_t part_bytes = 0;
+    double* wvec = nullptr;     // work vectors of N entries (right-hand side, preconditioner, solver)
+    int wvec_count = 0;
+    // GMRES workspace, kept between solves: Krylov basis (gm_cap + 1 vectors),
+    // dot-product partials, Hessenberg column on the device, one vector
+    double *gm_q = nullptr, *gm_part = nullptr, *gm_h = nullptr, *gm_v = nullptr;
+    int gm_cap = 0;
     stbem_alloc_fn alloc = nullptr;
     stbem_free_fn release = nullptr;
     void* user = nullptr;
@@ -1324,7 +1358,7 @@ struct stbem_ctx {
     bool toep = false;
     rocblas_handle blas = nullptr;
     // launch timing (stbem_set_timing): one event pair per launch
-    struct TRec { std::string name; double units; hipEvent_t a, b; };
+    struct TRec { std::string name; double units, flops; hipEvent_t a, b; };
     bool timing = false;
     std::vector<TRec> trecs;
 };
@@ -1431,13 +1465,30 @@ int ensure_part(stbem_ctx* c)
     return 0;
 }
 
+// `count` work vectors of N doubles, kept by the context (allocated on first
+// use, grown when a call needs more; the caller's stream order protects them:
+// one context serves one stream)
+int ensure_wvec(stbem_ctx* c, int count)
+{
+    if (c->wvec && c->wvec_count >= count) return 0;
+    if (c->wvec) (void)hipFree(c->wvec);
+    c->wvec = nullptr;
+    c->wvec_count = 0;
+    if (hipMalloc((void**)&c->wvec, (size_t)count * c->n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, STBEM_ENOMEM, "%d work vectors of %lld entries", count, c->n);
+    }
+    c->wvec_count = count;
+    return 0;
+}
+
 // Brackets one kernel launch with HIP events on its stream when timing is on.
 struct KTimer {
     stbem_ctx* c; hipStream_t s; long long idx = -1;
-    KTimer(stbem_ctx* c_, const char* name, double units, hipStream_t s_) : c(c_), s(s_)
+    KTimer(stbem_ctx* c_, const char* name, double units, hipStream_t s_, double flops = 0.0) : c(c_), s(s_)
     {
         if (!c->timing) return;
-        stbem_ctx::TRec r{name, units, nullptr, nullptr};
+        stbem_ctx::TRec r{name, units, flops, nullptr, nullptr};
         if (hipEventCreate(&r.a) != hipSuccess) return;
         if (hipEventCreate(&r.b) != hipSuccess) { (void)hipEventDestroy(r.a); return; }
         (void)hipEventRecord(r.a, s);
@@ -1484,7 +1535,7 @@ inline int blocks_per_launch(long long tiles)
 // generic kernel over the block list from its touching part (with_touch,
 // V_h assembled alone) or from its generic part
 template <int OP>
-int launch_assemble(stbem_ctx* c, double* o64, hipStream_t s, bool with_touch = false)
+int launch_assemble(stbem_ctx* c, OutBuf o64, hipStream_t s, bool with_touch = false)
 {
     const int slot = OP == OP_V ? 0 : OP == OP_K ? 1 : OP == OP_D ? 2 : OP == OP_DV ? 4 : 5;
     int t1 = (c->ng + kTile - 1) / kTile;
@@ -1517,8 +1568,44 @@ void launch_knear(stbem_ctx* c, int slot, double* o, hipStream_t s)
     }
 }
 
+// Algorithmic operation counts of the far-field (series) kernels, FMA = 2,
+// an FP64 exponential = 29 (range reduction, degree-11 polynomial, scaling),
+// counted from the kernels' arithmetic for the lanes that do work:
+//   far_pair (V_h, K_h; one segment pair per lane): per row of Q nodes 5;
+//     per node pair V 13 + 35 after the series, K 18 + 39; per series term
+//     and node pair V 12, K 14 (two recurrence steps of 5, sums 2 or 4)
+//   far_dpair (D_h; one half-piece pair): 21 per pair; per row 19 (WV) or
+//     17; per node pair 25 + 45 (WV) or 42 after the series; per term 22 (WV)
+//     or 20; per stored D_h entry of a tile 196 to combine 16 pairs (+3 V_h)
+// sum_nterm is the sum of the series terms of the launched blocks.
+double flops_vkfar(int op, int Q, long long nblk, long long sum_nterm, long long lanes_per_block)
+{
+    const double q2 = (double)Q * Q;
+    const double node = op == OP_V ? 48.0 : 57.0, term = op == OP_V ? 12.0 : 14.0;
+    return (double)lanes_per_block * ((double)nblk * (5.0 * Q + q2 * (node - term) + 5.0) + term * q2 * (double)sum_nterm);
+}
+
+double flops_dfar(int Q, bool wv, long long nblk, long long sum_nterm, long long tiles_per_blk, long long owned_per_blk)
+{
+    const double q2 = (double)Q * Q;
+    const double pw = wv ? 1024.0 : 0.0, pp = wv ? 132.0 : 1156.0;       // pairs per tile with / without V_h
+    const double per_pair_wv = 21.0 + 19.0 * Q + q2 * (70.0 - 22.0), per_pair = 21.0 + 17.0 * Q + q2 * (67.0 - 20.0);
+    const double tiles = (double)tiles_per_blk;
+    return tiles * (pw * ((double)nblk * per_pair_wv + 22.0 * q2 * (double)sum_nterm) +
+                    pp * ((double)nblk * per_pair + 20.0 * q2 * (double)sum_nterm)) +
+           (double)nblk * (double)owned_per_blk * (wv ? 199.0 : 196.0);
+}
+
+long long sum_terms(const stbem_ctx* c, int slot, const int* bl, int cnt)
+{
+    const long long off = bl - c->d_blist[slot];
+    long long sum = 0;
+    for (int e = 0; e < cnt; ++e) sum += c->list_nterm[slot][off + e];
+    return sum;
+}
+
 template <int OP, int Q>
-void launch_vkfar(stbem_ctx* c, int slot, const int* bl, int cnt, double* o, hipStream_t s)
+void launch_vkfar(stbem_ctx* c, int slot, const int* bl, int cnt, OutBuf o, hipStream_t s)
 {
     int ti = (c->ng + kTile - 1) / kTile;
     int tj = OP == OP_V ? ti : (c->ng + kTile - 2) / (kTile - 1);
@@ -1526,14 +1613,16 @@ void launch_vkfar(stbem_ctx* c, int slot, const int* bl, int cnt, double* o, hip
     const int step = blocks_per_launch(tiles);
     for (int off = 0; off < cnt; off += step) {
         const int n = std::min(step, cnt - off);
-        KTimer kt(c, kname("k_assemble_vkfar", OP, Q).c_str(), (double)n * c->ng * c->ng, s);
+        const long long lanes = OP == OP_V ? (long long)c->ng * (c->ng + 1) / 2 : (long long)c->ng * tj * kTile;
+        KTimer kt(c, kname("k_assemble_vkfar", OP, Q).c_str(), (double)n * c->ng * c->ng, s,
+                  c->timing ? flops_vkfar(OP, Q, n, sum_terms(c, slot, bl + off, n), lanes) : 0.0);
         hipLaunchKernelGGL((k_assemble_vkfar<OP, Q>), dim3((unsigned)(n * tiles)), dim3(kWG), 0, s, geom(c), c->d_tab,
                            bl + off, ti, tj, o, (const TimeBlock*)c->d_tbs);
     }
 }
 
 template <int OP>
-int launch_far(stbem_ctx* c, int slot, double* o, hipStream_t s)
+int launch_far(stbem_ctx* c, int slot, OutBuf o, hipStream_t s)
 {
     const int* bl = c->d_blist[slot] + c->nlist_touch[slot] + c->nlist_gen[slot];
     int off = 0;
@@ -1559,7 +1648,7 @@ int build_block_lists(stbem_ctx* c)
     TimeBlock tb;
     for (int e = 0; e < 5; ++e) {
         const int op = ops[e], slot = slots[e];
-        std::vector<int> touch, gen, far[9];
+        std::vector<int> touch, gen, far[9], nterm_far[9];
         for (int k = 0; k < c->nt; ++k)
             for (int m = 0; m <= (c->toep ? 0 : k); ++m) {
                 int b = (int)((long long)k * (k + 1) / 2 + m);
@@ -1567,12 +1656,17 @@ int build_block_lists(stbem_ctx* c)
                 int q = q_block(op, c->lmax, block_min_lag(g.t, k, m), g.alpha);
                 if ((op == OP_V || op == OP_D || op == OP_K || op == OP_DK) && tb.d <= 1) touch.push_back(b);
                 else if (!tb.ser || op == OP_DV || op == OP_DK) gen.push_back(b);
-                else if (q >= 3 && q <= 8) far[q].push_back(b);
+                else if (q >= 3 && q <= 8) { far[q].push_back(b); nterm_far[q].push_back(tb.nterm); }
                 else gen.push_back(b);
             }
         std::vector<int> all(touch);
         all.insert(all.end(), gen.begin(), gen.end());
-        for (int q = 0; q < 9; ++q) { all.insert(all.end(), far[q].begin(), far[q].end()); c->nlist_far[slot][q] = (int)far[q].size(); }
+        c->list_nterm[slot].assign(all.size(), 0);
+        for (int q = 0; q < 9; ++q) {
+            all.insert(all.end(), far[q].begin(), far[q].end());
+            c->list_nterm[slot].insert(c->list_nterm[slot].end(), nterm_far[q].begin(), nterm_far[q].end());
+            c->nlist_far[slot][q] = (int)far[q].size();
+        }
         c->nlist_touch[slot] = (int)touch.size();
         c->nlist_gen[slot] = (int)gen.size();
         int rc = upload(c, &c->d_blist[slot], all);
@@ -1628,30 +1722,80 @@ int m0_power_rows(stbem_ctx* c, bool deriv, double* o, hipStream_t s)
     return rc;
 }
 
-int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd)
+void free_f32(stbem_ctx* c, bool v, bool d)
 {
-    int slot = op_slot(op);
+    if (v) { dev_free(c, c->v_hi); dev_free(c, c->v_lo); c->v_hi = c->v_lo = nullptr; }
+    if (d) { dev_free(c, c->d_32); c->d_32 = nullptr; }
+}
+
+void free_slot(stbem_ctx* c, int slot)
+{
+    dev_free(c, c->mat[slot]);
+    c->mat[slot] = nullptr;
+    c->mat_bytes[slot] = 0;
+}
+
+// where the kernels write operator `slot` (V_h: FP64, or the hi + lo pair;
+// D_h: FP64 or FP32; the others FP64)
+OutBuf out_of(const stbem_ctx* c, int slot)
+{
+    if (slot == 0 && !c->mat[0]) return OutBuf{nullptr, c->v_hi, c->v_lo};
+    if (slot == 2 && !c->mat[2]) return OutBuf{nullptr, c->d_32, nullptr};
+    return OutBuf{c->mat[slot], nullptr, nullptr};
+}
+
+// Storage for one operator before its kernels run.  FP64: the FP64 array;
+// FP32 copies of V_h or D_h made earlier would be stale and are freed.
+// FP32_IR (V_h, D_h only): V_h as the pair hi + lo, D_h as FP32; the FP64
+// array of the operator is freed.
+int prepare_storage(stbem_ctx* c, unsigned op, int prec)
+{
+    const int slot = op_slot(op);
+    if (prec == STBEM_FP32_IR) {
+        const size_t fb = (size_t)causal_entries(c) * sizeof(float);
+        free_slot(c, slot);
+        if (op == STBEM_V) {
+            if (!c->v_hi) c->v_hi = (float*)dev_alloc(c, fb);
+            if (!c->v_lo) c->v_lo = (float*)dev_alloc(c, fb);
+            if (!c->v_hi || !c->v_lo) { free_f32(c, true, false); return fail(c, STBEM_ENOMEM, "FP32 storage of V_h (2 x %zu bytes)", fb); }
+        } else {
+            if (!c->d_32) c->d_32 = (float*)dev_alloc(c, fb);
+            if (!c->d_32) return fail(c, STBEM_ENOMEM, "FP32 storage of D_h (%zu bytes)", fb);
+        }
+        return 0;
+    }
     size_t bytes = (op == STBEM_M0 || op == STBEM_DM0) ? (size_t)c->n * c->nv * sizeof(double)
                                                       : (size_t)causal_entries(c) * sizeof(double);
     if ((op == STBEM_M0 || op == STBEM_DM0) && c->nv == 0) return fail(c, STBEM_EINVAL, "no Omega mesh for M0");
-    if (c->mat[slot] && c->mat_bytes[slot] != bytes) { dev_free(c, c->mat[slot]); c->mat[slot] = nullptr; }
+    if (op == STBEM_V || op == STBEM_D) free_f32(c, op == STBEM_V, op == STBEM_D);
+    if (c->mat[slot] && c->mat_bytes[slot] != bytes) free_slot(c, slot);
     if (!c->mat[slot]) {
         c->mat[slot] = (double*)dev_alloc(c, bytes);
         if (!c->mat[slot]) return fail(c, STBEM_ENOMEM, "allocation of %zu bytes for operator %u failed", bytes, op);
         c->mat_bytes[slot] = bytes;
     }
+    return 0;
+}
+
+int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd, int prec)
+{
+    int slot = op_slot(op);
+    int rc0 = prepare_storage(c, op, prec);
+    if (rc0) return rc0;
     double* o = c->mat[slot];
     switch (op) {
     case STBEM_V:
     case STBEM_K: {
         if (op == STBEM_K) launch_knear<OP_K>(c, 1, o, s);
+        const OutBuf ob = out_of(c, slot);
         // V_h with D_h: its touching and separated blocks come with D_h's tiles
-        int rc = op == STBEM_V ? launch_assemble<OP_V>(c, o, s, !fuse_vd) : launch_assemble<OP_K>(c, o, s);
+        int rc = op == STBEM_V ? launch_assemble<OP_V>(c, ob, s, !fuse_vd) : launch_assemble<OP_K>(c, ob, s);
         if (rc) return rc;
         if (op == STBEM_V && fuse_vd) return 0;
-        return op == STBEM_V ? launch_far<OP_V>(c, 0, o, s) : launch_far<OP_K>(c, 1, o, s);
+        return op == STBEM_V ? launch_far<OP_V>(c, 0, ob, s) : launch_far<OP_K>(c, 1, ob, s);
     }
     case STBEM_D: {
+        const OutBuf od = out_of(c, 2), ov = out_of(c, 0);
         int t1 = (c->ng + kTile - 1) / kTile;
         const long long tiles = tiles_per_block(t1, true);
         const int step = blocks_per_launch(tiles);
@@ -1660,37 +1804,38 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd)
             KTimer kt(c, fuse_vd ? "k_assemble_dnear<true>" : "k_assemble_dnear<false>", (double)n * c->ng * c->ng, s);
             if (fuse_vd)
                 hipLaunchKernelGGL(k_assemble_dnear<true>, dim3((unsigned)(n * tiles)), dim3(kWG), 0, s, geom(c), c->d_tab, c->ord,
-                                   (const int*)(c->d_blist[2] + off), t1, o, c->mat[0]);
+                                   (const int*)(c->d_blist[2] + off), t1, od, ov);
             else
                 hipLaunchKernelGGL(k_assemble_dnear<false>, dim3((unsigned)(n * tiles)), dim3(kWG), 0, s, geom(c), c->d_tab, c->ord,
-                                   (const int*)(c->d_blist[2] + off), t1, o, nullptr);
+                                   (const int*)(c->d_blist[2] + off), t1, od, OutBuf{nullptr, nullptr, nullptr});
         }
-        int rc = launch_assemble<OP_D>(c, o, s);
+        int rc = launch_assemble<OP_D>(c, od, s);
         if (rc) return rc;
         const int* bl = c->d_blist[2] + c->nlist_touch[2] + c->nlist_gen[2];
+        const OutBuf none{nullptr, nullptr, nullptr};
         for (int q = 3; q <= 8; ++q) {
             for (int off = 0; off < c->nlist_far[2][q]; off += step) {
                 const int n = std::min(step, c->nlist_far[2][q] - off);
                 dim3 gr((unsigned)(n * tiles)), blk(kWG);
                 const int* b2 = bl + off;
                 const std::string kn = std::string("k_assemble_dfar<") + std::to_string(q) + (fuse_vd ? ", true>" : ", false>");
-                KTimer kt(c, kn.c_str(), (double)n * c->ng * c->ng, s);
-                double* ov = c->mat[0];
+                KTimer kt(c, kn.c_str(), (double)n * c->ng * c->ng, s,
+                          c->timing ? flops_dfar(q, fuse_vd, n, sum_terms(c, 2, b2, n), tiles, (long long)c->ng * (c->ng + 1) / 2) : 0.0);
                 if (fuse_vd) switch (q) {
-                case 3: hipLaunchKernelGGL((k_assemble_dfar<3, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov, c->d_tbs); break;
-                case 4: hipLaunchKernelGGL((k_assemble_dfar<4, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov, c->d_tbs); break;
-                case 5: hipLaunchKernelGGL((k_assemble_dfar<5, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov, c->d_tbs); break;
-                case 6: hipLaunchKernelGGL((k_assemble_dfar<6, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov, c->d_tbs); break;
-                case 7: hipLaunchKernelGGL((k_assemble_dfar<7, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov, c->d_tbs); break;
-                default: hipLaunchKernelGGL((k_assemble_dfar<8, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, ov, c->d_tbs); break;
+                case 3: hipLaunchKernelGGL((k_assemble_dfar<3, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, ov, c->d_tbs); break;
+                case 4: hipLaunchKernelGGL((k_assemble_dfar<4, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, ov, c->d_tbs); break;
+                case 5: hipLaunchKernelGGL((k_assemble_dfar<5, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, ov, c->d_tbs); break;
+                case 6: hipLaunchKernelGGL((k_assemble_dfar<6, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, ov, c->d_tbs); break;
+                case 7: hipLaunchKernelGGL((k_assemble_dfar<7, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, ov, c->d_tbs); break;
+                default: hipLaunchKernelGGL((k_assemble_dfar<8, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, ov, c->d_tbs); break;
                 }
                 else switch (q) {
-                case 3: hipLaunchKernelGGL((k_assemble_dfar<3, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr, c->d_tbs); break;
-                case 4: hipLaunchKernelGGL((k_assemble_dfar<4, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr, c->d_tbs); break;
-                case 5: hipLaunchKernelGGL((k_assemble_dfar<5, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr, c->d_tbs); break;
-                case 6: hipLaunchKernelGGL((k_assemble_dfar<6, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr, c->d_tbs); break;
-                case 7: hipLaunchKernelGGL((k_assemble_dfar<7, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr, c->d_tbs); break;
-                default: hipLaunchKernelGGL((k_assemble_dfar<8, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, o, nullptr, c->d_tbs); break;
+                case 3: hipLaunchKernelGGL((k_assemble_dfar<3, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, none, c->d_tbs); break;
+                case 4: hipLaunchKernelGGL((k_assemble_dfar<4, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, none, c->d_tbs); break;
+                case 5: hipLaunchKernelGGL((k_assemble_dfar<5, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, none, c->d_tbs); break;
+                case 6: hipLaunchKernelGGL((k_assemble_dfar<6, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, none, c->d_tbs); break;
+                case 7: hipLaunchKernelGGL((k_assemble_dfar<7, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, none, c->d_tbs); break;
+                default: hipLaunchKernelGGL((k_assemble_dfar<8, false>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, none, c->d_tbs); break;
                 }
             }
             bl += c->nlist_far[2][q];
@@ -1698,8 +1843,8 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd)
         HIPCHK(c, hipGetLastError());
         return 0;
     }
-    case STBEM_DV: return launch_assemble<OP_DV>(c, o, s);
-    case STBEM_DK: launch_knear<OP_DK>(c, 5, o, s); return launch_assemble<OP_DK>(c, o, s);
+    case STBEM_DV: return launch_assemble<OP_DV>(c, out_of(c, 4), s);
+    case STBEM_DK: launch_knear<OP_DK>(c, 5, o, s); return launch_assemble<OP_DK>(c, out_of(c, 5), s);
     case STBEM_M0:
     case STBEM_DM0: {
         // whole time rows in chunks whose moment scratch stays below 1 GiB:
@@ -2093,9 +2238,10 @@ int stbem_destroy(stbem_ctx* c)
 {
     if (!c) return STBEM_OK;
     for (int s = 0; s < 7; ++s) dev_free(c, c->mat[s]);
-    dev_free(c, c->v_hi); dev_free(c, c->v_lo); dev_free(c, c->d_32);
+    free_f32(c, true, true);
     void* own[] = {c->d_t, c->d_vx, c->d_vy, c->d_ex, c->d_ey, c->d_len, c->d_ox, c->d_oy, c->d_mt, c->d_m0c, c->d_m0cd, c->d_m0n, c->d_m0amax, c->d_v2t_loc,
-                   c->d_tri, c->d_v2t_ptr, c->d_v2t, c->d_tab, c->d_m0tab, c->part, c->d_tbs};
+                   c->d_tri, c->d_v2t_ptr, c->d_v2t, c->d_tab, c->d_m0tab, c->part, c->d_tbs, c->wvec,
+                   c->gm_q, c->gm_part, c->gm_h, c->gm_v};
     for (void* p : own) if (p) (void)hipFree(p);
     for (int q = 0; q < 7; ++q) if (c->d_blist[q]) (void)hipFree(c->d_blist[q]);
     clear_timing(c);
@@ -2118,13 +2264,8 @@ int stbem_set_toeplitz(stbem_ctx* c, int on)
     // the storage format changes: drop the causal operators and FP32 copies
     (void)hipDeviceSynchronize();
     const int slots[5] = {0, 1, 2, 4, 5};
-    for (int e = 0; e < 5; ++e) {
-        dev_free(c, c->mat[slots[e]]);
-        c->mat[slots[e]] = nullptr;
-        c->mat_bytes[slots[e]] = 0;
-    }
-    dev_free(c, c->v_hi); dev_free(c, c->v_lo); dev_free(c, c->d_32);
-    c->v_hi = c->v_lo = nullptr; c->d_32 = nullptr;
+    for (int e = 0; e < 5; ++e) free_slot(c, slots[e]);
+    free_f32(c, true, true);
     c->toep = want;
     for (int q = 0; q < 7; ++q) if (c->d_blist[q]) { (void)hipFree(c->d_blist[q]); c->d_blist[q] = nullptr; }
     return build_block_lists(c);
@@ -2200,6 +2341,7 @@ int stbem_kernel_times(stbem_ctx* c, stbem_kernel_time* out, int cap)
         agg[e].launches += 1;
         agg[e].ms += ms;
         agg[e].units += r.units;
+        agg[e].flops += r.flops;
     }
     for (size_t e = 0; e < agg.size() && (int)e < cap; ++e) out[e] = agg[e];
     return (int)agg.size();
@@ -2225,17 +2367,22 @@ int stbem_sizes(const stbem_ctx* c, long long* n, int* ng, int* nt, int* nv, lon
     return STBEM_OK;
 }
 
-int stbem_assemble(stbem_ctx* c, unsigned mask, void* stream)
+int stbem_assemble(stbem_ctx* c, unsigned mask, int precision, void* stream)
 {
     if (!c) return STBEM_EINVAL;
     if (mask == 0 || (mask & ~127u)) return fail(c, STBEM_EINVAL, "bad operator mask %u", mask);
+    if (precision != STBEM_FP64 && precision != STBEM_FP32_IR) return fail(c, STBEM_EINVAL, "unknown precision %d", precision);
+    if (precision == STBEM_FP32_IR) {
+        if (mask & ~(STBEM_V | STBEM_D)) return fail(c, STBEM_EINVAL, "FP32 storage is for V_h and D_h only");
+        if (c->toep) return fail(c, STBEM_EINVAL, "FP32 storage needs packed storage (block-Toeplitz mode is FP64 only)");
+    }
     const unsigned ops[7] = {STBEM_V, STBEM_K, STBEM_D, STBEM_M0, STBEM_DV, STBEM_DK, STBEM_DM0};
     // V_h and D_h together: V_h's separated blocks are computed by D_h's far
     // tiles (same block lists); V is assembled first, so its storage exists
     const bool fuse = (mask & STBEM_V) && (mask & STBEM_D) && c->vd_fusable;
     for (unsigned op : ops)
         if (mask & op) {
-            int rc = assemble_one(c, op, S(stream), fuse);
+            int rc = assemble_one(c, op, S(stream), fuse, precision);
             if (rc) return rc;
         }
     return STBEM_OK;
@@ -2248,14 +2395,8 @@ int stbem_release(stbem_ctx* c, unsigned mask)
     const unsigned ops[7] = {STBEM_V, STBEM_K, STBEM_D, STBEM_M0, STBEM_DV, STBEM_DK, STBEM_DM0};
     for (unsigned op : ops)
         if (mask & op) {
-            int slot = op_slot(op);
-            dev_free(c, c->mat[slot]);
-            c->mat[slot] = nullptr;
-            c->mat_bytes[slot] = 0;
-            if (op == STBEM_V || op == STBEM_D) {       // FP32 copies derive from V and D
-                dev_free(c, c->v_hi); dev_free(c, c->v_lo); dev_free(c, c->d_32);
-                c->v_hi = c->v_lo = c->d_32 = nullptr;
-            }
+            free_slot(c, op_slot(op));
+            if (op == STBEM_V || op == STBEM_D) free_f32(c, op == STBEM_V, op == STBEM_D);
         }
     return STBEM_OK;
 }
@@ -2271,12 +2412,29 @@ int stbem_matrix(stbem_ctx* c, unsigned op, const double** ptr, size_t* bytes)
     return STBEM_OK;
 }
 
+int stbem_matrix_f32(stbem_ctx* c, unsigned op, const float** hi, const float** lo, size_t* bytes)
+{
+    if (!c || !hi) return STBEM_EINVAL;
+    if (op != STBEM_V && op != STBEM_D) return fail(c, STBEM_EINVAL, "FP32 storage exists for V_h and D_h only");
+    const float* h = op == STBEM_V ? c->v_hi : c->d_32;
+    if (!h) return fail(c, STBEM_ENOTASSEMBLED, "operator %u has no FP32 storage", op);
+    *hi = h;
+    if (lo) *lo = op == STBEM_V ? c->v_lo : nullptr;
+    if (bytes) *bytes = (size_t)causal_entries(c) * sizeof(float);
+    return STBEM_OK;
+}
+
 int stbem_apply(stbem_ctx* c, unsigned op, int trans, const double* x, double* y, void* stream)
 {
     if (!c || !x || !y) return STBEM_EINVAL;
     int slot = op_slot(op);
     if (slot < 0) return fail(c, STBEM_EINVAL, "unknown operator %u", op);
-    if (!c->mat[slot]) return fail(c, STBEM_ENOTASSEMBLED, "operator %u not assembled", op);
+    if (!c->mat[slot]) {
+        // V_h or D_h held in FP32 storage only
+        if (op == STBEM_V && c->v_hi && c->v_lo) return packed_apply(c, nullptr, c->v_hi, c->v_lo, nullptr, trans ? 1 : 0, x, y, S(stream));
+        if (op == STBEM_D && c->d_32) return packed_apply(c, nullptr, nullptr, nullptr, c->d_32, trans ? 1 : 0, x, y, S(stream));
+        return fail(c, STBEM_ENOTASSEMBLED, "operator %u not assembled", op);
+    }
     if (op == STBEM_M0 || op == STBEM_DM0) return dense_apply(c, c->mat[slot], trans ? 1 : 0, x, y, S(stream));
     return packed_apply(c, c->mat[slot], nullptr, nullptr, nullptr, trans ? 1 : 0, x, y, S(stream));
 }
@@ -2290,11 +2448,14 @@ int stbem_mass(stbem_ctx* c, int trans, const double* x, double* y, void* stream
     return STBEM_OK;
 }
 
+// z = Mt^-1 D_h Mt^-1 r (D_h^T for trans), D_h from d32 if given, else the
+// stored D_h (FP64, or FP32 when D_h was assembled in FP32_IR); tmp: N doubles
 static int precondition_impl(stbem_ctx* c, int trans, const double* r, double* z, double* tmp, const float* d32,
                              hipStream_t s)
 {
     hipLaunchKernelGGL(k_div, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, r, (const double*)c->d_mt, tmp);
     HIPCHK(c, hipGetLastError());
+    if (!d32 && !c->mat[2]) d32 = c->d_32;
     int rc = d32 ? packed_apply(c, nullptr, nullptr, nullptr, d32, trans, tmp, z, s)
                  : packed_apply(c, c->mat[2], nullptr, nullptr, nullptr, trans, tmp, z, s);
     if (rc) return rc;
@@ -2306,13 +2467,10 @@ static int precondition_impl(stbem_ctx* c, int trans, const double* r, double* z
 int stbem_precondition(stbem_ctx* c, int trans, const double* r, double* z, void* stream)
 {
     if (!c || !r || !z) return STBEM_EINVAL;
-    if (!c->mat[2]) return fail(c, STBEM_ENOTASSEMBLED, "D_h not assembled");
-    double* tmp = (double*)dev_alloc(c, (size_t)c->n * sizeof(double));
-    if (!tmp) return fail(c, STBEM_ENOMEM, "temporary vector");
-    int rc = precondition_impl(c, trans ? 1 : 0, r, z, tmp, nullptr, S(stream));
-    (void)hipStreamSynchronize(S(stream));
-    dev_free(c, tmp);
-    return rc;
+    if (!c->mat[2] && !c->d_32) return fail(c, STBEM_ENOTASSEMBLED, "D_h not assembled");
+    int rc = ensure_wvec(c, 2);
+    if (rc) return rc;
+    return precondition_impl(c, trans ? 1 : 0, r, z, c->wvec, nullptr, S(stream));
 }
 
 int stbem_rhs(stbem_ctx* c, const double* g, const double* u0, double* f, void* stream)
@@ -2321,26 +2479,37 @@ int stbem_rhs(stbem_ctx* c, const double* g, const double* u0, double* f, void* 
     if (!c->mat[1]) return fail(c, STBEM_ENOTASSEMBLED, "K_h not assembled");
     if (u0 && !c->mat[3] && c->nv == 0) return fail(c, STBEM_EINVAL, "u0 given but no Omega mesh");
     hipStream_t s = S(stream);
-    double* tmp = (double*)dev_alloc(c, (size_t)c->n * sizeof(double));
-    if (!tmp) return fail(c, STBEM_ENOMEM, "temporary vector");
-    int rc = 0;
-    // f = K g;  f = 1/2 M g + f;  f -= M0 u0
-    if ((rc = packed_apply(c, c->mat[1], nullptr, nullptr, nullptr, 0, g, f, s))) goto done;
-    hipLaunchKernelGGL(k_mass, dim3(grid1(c->n)), dim3(kWG), 0, s, c->d_t, c->d_len, g, tmp, c->ng, c->nt, 0, 0.5,
-                       (const double*)f);
-    if (hipGetLastError() != hipSuccess) { rc = fail(c, STBEM_EHIP, "mass kernel"); goto done; }
+    int rc = ensure_wvec(c, 2);
+    if (rc) return rc;
+    double* tmp = c->wvec;
+    // tmp = K g;  f = 1/2 M g + tmp;  f -= M0 u0
+    if ((rc = packed_apply(c, c->mat[1], nullptr, nullptr, nullptr, 0, g, tmp, s))) return rc;
+    hipLaunchKernelGGL(k_mass, dim3(grid1(c->n)), dim3(kWG), 0, s, c->d_t, c->d_len, g, f, c->ng, c->nt, 0, 0.5,
+                       (const double*)tmp);
+    HIPCHK(c, hipGetLastError());
     if (u0) {
         // M0 u0 from the stored matrix, or computed row chunk by row chunk
-        if ((rc = c->mat[3] ? dense_apply(c, c->mat[3], 0, u0, f, s) : m0_fused_apply(c, u0, f, s))) goto done;
-        hipLaunchKernelGGL(k_axpby, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, 1.0, (const double*)tmp, -1.0, f);
-    } else {
-        hipLaunchKernelGGL(k_axpby, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, 1.0, (const double*)tmp, 0.0, f);
+        if ((rc = c->mat[3] ? dense_apply(c, c->mat[3], 0, u0, tmp, s) : m0_fused_apply(c, u0, tmp, s))) return rc;
+        hipLaunchKernelGGL(k_axpby, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, -1.0, (const double*)tmp, 1.0, f);
+        HIPCHK(c, hipGetLastError());
     }
-    if (hipGetLastError() != hipSuccess) { rc = fail(c, STBEM_EHIP, "axpby kernel"); goto done; }
-done:
-    (void)hipStreamSynchronize(s);
-    dev_free(c, tmp);
-    return rc;
+    return STBEM_OK;
+}
+
+int stbem_rhs_adjoint(stbem_ctx* c, const double* lam, double* out, void* stream)
+{
+    if (!c || !lam || !out) return STBEM_EINVAL;
+    if (!c->mat[1]) return fail(c, STBEM_ENOTASSEMBLED, "K_h not assembled");
+    hipStream_t s = S(stream);
+    int rc = ensure_wvec(c, 2);
+    if (rc) return rc;
+    double* tmp = c->wvec;
+    // tmp = K^T lam;  out = 1/2 M^T lam + tmp
+    if ((rc = packed_apply(c, c->mat[1], nullptr, nullptr, nullptr, 1, lam, tmp, s))) return rc;
+    hipLaunchKernelGGL(k_mass, dim3(grid1(c->n)), dim3(kWG), 0, s, c->d_t, c->d_len, lam, out, c->ng, c->nt, 1, 0.5,
+                       (const double*)tmp);
+    HIPCHK(c, hipGetLastError());
+    return STBEM_OK;
 }
 
 // ----------------------------------------------------------------- GMRES
@@ -2374,22 +2543,42 @@ int op_precond(const SolveOp& o, const double* r, double* z, hipStream_t s)
     return precondition_impl(c, o.trans, r, z, o.tmp, o.d32, s);
 }
 
+// GMRES workspace for up to maxit iterations, kept by the context
+int ensure_gmres(stbem_ctx* c, int maxit)
+{
+    if (c->gm_q && c->gm_cap >= maxit) return 0;
+    double* own[4] = {c->gm_q, c->gm_part, c->gm_h, c->gm_v};
+    for (double* p : own) if (p) (void)hipFree(p);
+    c->gm_q = c->gm_part = c->gm_h = c->gm_v = nullptr;
+    c->gm_cap = 0;
+    const long long n = c->n, nchunk = (n + kDotChunk - 1) / kDotChunk;
+    if (hipMalloc((void**)&c->gm_q, (size_t)(maxit + 1) * n * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&c->gm_part, (size_t)(maxit + 1) * nchunk * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&c->gm_h, (size_t)(maxit + 2) * 2 * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&c->gm_v, (size_t)n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        double* got[4] = {c->gm_q, c->gm_part, c->gm_h, c->gm_v};
+        for (double* p : got) if (p) (void)hipFree(p);
+        c->gm_q = c->gm_part = c->gm_h = c->gm_v = nullptr;
+        return fail(c, STBEM_ENOMEM, "GMRES workspace (%d vectors of %lld)", maxit + 1, n);
+    }
+    c->gm_cap = maxit;
+    return 0;
+}
+
 // left-preconditioned GMRES, x0 = 0, CGS2 orthogonalisation in FP64
 int gmres(const SolveOp& o, const double* f, double* w, double tol, int maxit, int* iters, double* relres, hipStream_t s)
 {
     stbem_ctx* c = o.c;
     const long long n = c->n;
     const long long ldq = n;
-    double* Q = (double*)dev_alloc(c, (size_t)(maxit + 1) * n * sizeof(double));
+    if (int rcw = ensure_gmres(c, maxit)) return rcw;
+    double* Q = c->gm_q;
     DotWork dw;
     dw.nchunk = (int)((n + kDotChunk - 1) / kDotChunk);
-    dw.part = (double*)dev_alloc(c, (size_t)(maxit + 1) * dw.nchunk * sizeof(double));
-    double* hdev = (double*)dev_alloc(c, (size_t)(maxit + 2) * 2 * sizeof(double));
-    double* v = (double*)dev_alloc(c, (size_t)n * sizeof(double));
-    if (!Q || !dw.part || !hdev || !v) {
-        dev_free(c, Q); dev_free(c, dw.part); dev_free(c, hdev); dev_free(c, v);
-        return fail(c, STBEM_ENOMEM, "GMRES workspace (%d vectors of %lld)", maxit + 1, n);
-    }
+    dw.part = c->gm_part;
+    double* hdev = c->gm_h;
+    double* v = c->gm_v;
     std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), gv(maxit + 1, 0.0), hh(2 * (maxit + 2));
     int rc = 0, j = 0;
     double beta = 0.0;
@@ -2401,7 +2590,8 @@ int gmres(const SolveOp& o, const double* f, double* w, double tol, int maxit, i
     HIPCHK(c, hipStreamSynchronize(s));
     beta = std::sqrt(hh[0]);
     if (beta == 0.0) {
-        HIPCHK(c, hipMemsetAsync(w, 0, (size_t)n * sizeof(double), s));
+        hipLaunchKernelGGL(k_fill, dim3(grid1(n)), dim3(kWG), 0, s, n, 0.0, w);
+        HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipStreamSynchronize(s));
         goto out;
     }
@@ -2459,7 +2649,6 @@ int gmres(const SolveOp& o, const double* f, double* w, double tol, int maxit, i
     }
     *iters = j;
 out:
-    dev_free(c, Q); dev_free(c, dw.part); dev_free(c, hdev); dev_free(c, v);
     return rc;
 }
 
@@ -2469,18 +2658,15 @@ int true_relres(stbem_ctx* c, const SolveOp& o64, const double* f, const double*
     int rc = packed_apply(c, o64.A, o64.hi, o64.lo, nullptr, o64.trans, w, r, s);
     if (rc) return rc;
     hipLaunchKernelGGL(k_axpby, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, 1.0, f, -1.0, r);
+    if ((rc = ensure_gmres(c, 1))) return rc;
     DotWork dw;
     dw.nchunk = (int)((c->n + kDotChunk - 1) / kDotChunk);
-    dw.part = (double*)dev_alloc(c, (size_t)2 * dw.nchunk * sizeof(double));
-    double* hd = (double*)dev_alloc(c, 2 * sizeof(double));
-    if (!dw.part || !hd) { dev_free(c, dw.part); dev_free(c, hd); return fail(c, STBEM_ENOMEM, "norms"); }
+    dw.part = c->gm_part;
+    double* hd = c->gm_h;
     double hh[2];
-    if ((rc = dots(c, dw, r, c->n, 1, r, hd, s)) || (rc = dots(c, dw, f, c->n, 1, f, hd + 1, s))) {
-        dev_free(c, dw.part); dev_free(c, hd); return rc;
-    }
-    (void)hipMemcpyAsync(hh, hd, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
-    (void)hipStreamSynchronize(s);
-    dev_free(c, dw.part); dev_free(c, hd);
+    if ((rc = dots(c, dw, r, c->n, 1, r, hd, s)) || (rc = dots(c, dw, f, c->n, 1, f, hd + 1, s))) return rc;
+    HIPCHK(c, hipMemcpyAsync(hh, hd, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
     *res = hh[1] > 0 ? std::sqrt(hh[0] / hh[1]) : 0.0;
     return 0;
 }
@@ -2491,16 +2677,22 @@ int stbem_prepare_ir(stbem_ctx* c, void* stream)
 {
     if (!c) return STBEM_EINVAL;
     if (c->toep) return fail(c, STBEM_EINVAL, "FP32 refinement needs packed storage (block-Toeplitz mode is FP64 only)");
-    if (!c->mat[0] || !c->mat[2]) return fail(c, STBEM_ENOTASSEMBLED, "FP32 storage needs V_h and D_h");
+    if (!c->mat[0] && !c->v_hi) return fail(c, STBEM_ENOTASSEMBLED, "V_h not assembled");
     hipStream_t s = S(stream);
-    size_t fb = (size_t)c->packed * sizeof(float);
-    if (!c->v_hi) c->v_hi = (float*)dev_alloc(c, fb);
-    if (!c->v_lo) c->v_lo = (float*)dev_alloc(c, fb);
-    if (!c->d_32) c->d_32 = (float*)dev_alloc(c, fb);
-    if (!c->v_hi || !c->v_lo || !c->d_32) return fail(c, STBEM_ENOMEM, "FP32 storage (3 x %zu bytes)", fb);
+    const size_t fb = (size_t)c->packed * sizeof(float);
     const unsigned gs = (unsigned)std::min<long long>(grid1(c->packed), 1LL << 20);   // grid-stride
-    hipLaunchKernelGGL(k_split, dim3(gs), dim3(kWG), 0, s, c->packed, (const double*)c->mat[0], c->v_hi, c->v_lo);
-    hipLaunchKernelGGL(k_split, dim3(gs), dim3(kWG), 0, s, c->packed, (const double*)c->mat[2], c->d_32, (float*)nullptr);
+    // FP64 V_h resident: the inner solves read hi = fl32(V), the outer
+    // residual reads the FP64 V_h itself (no lo part is kept)
+    if (c->mat[0] && !c->v_hi) {
+        c->v_hi = (float*)dev_alloc(c, fb);
+        if (!c->v_hi) return fail(c, STBEM_ENOMEM, "FP32 copy of V_h (%zu bytes)", fb);
+        hipLaunchKernelGGL(k_split, dim3(gs), dim3(kWG), 0, s, c->packed, (const double*)c->mat[0], c->v_hi, (float*)nullptr);
+    }
+    if (c->mat[2] && !c->d_32) {
+        c->d_32 = (float*)dev_alloc(c, fb);
+        if (!c->d_32) return fail(c, STBEM_ENOMEM, "FP32 copy of D_h (%zu bytes)", fb);
+        hipLaunchKernelGGL(k_split, dim3(gs), dim3(kWG), 0, s, c->packed, (const double*)c->mat[2], c->d_32, (float*)nullptr);
+    }
     HIPCHK(c, hipGetLastError());
     return STBEM_OK;
 }
@@ -2508,38 +2700,44 @@ int stbem_prepare_ir(stbem_ctx* c, void* stream)
 int stbem_solve(stbem_ctx* c, const double* f, double* w, const stbem_solve_opts* opts, stbem_solve_info* info, void* stream)
 {
     if (!c || !f || !w || !opts) return STBEM_EINVAL;
-    if (!c->mat[0]) return fail(c, STBEM_ENOTASSEMBLED, "V_h not assembled");
-    if (opts->precondition && !c->mat[2]) return fail(c, STBEM_ENOTASSEMBLED, "D_h not assembled");
     if (opts->max_it < 1 || !(opts->tol > 0)) return fail(c, STBEM_EINVAL, "bad tolerance or iteration limit");
+    if (opts->mode != STBEM_FP64 && opts->mode != STBEM_FP32_IR) return fail(c, STBEM_EINVAL, "unknown solve mode %d", opts->mode);
+    const bool ir = opts->mode == STBEM_FP32_IR;
+    if (!c->mat[0] && !(ir && c->v_hi)) {
+        if (c->v_hi) return fail(c, STBEM_ENOTASSEMBLED, "V_h is held in FP32 storage only: use the FP32_IR mode");
+        return fail(c, STBEM_ENOTASSEMBLED, "V_h not assembled");
+    }
+    if (opts->precondition && !c->mat[2] && !(ir && c->d_32)) return fail(c, STBEM_ENOTASSEMBLED, "D_h not assembled");
     hipStream_t s = S(stream);
     stbem_solve_info inf = {0, 0, 0.0, 0.0};
-    double* tmp = (double*)dev_alloc(c, (size_t)3 * c->n * sizeof(double));
-    if (!tmp) return fail(c, STBEM_ENOMEM, "solver vectors");
-    int rc = 0;
+    int rc = ensure_wvec(c, 5);
+    if (rc) return rc;
+    double* tmp = c->wvec;                       // 3 vectors for the operators; r and the correction
     SolveOp o64 = {c, opts->trans ? 1 : 0, opts->precondition ? 1 : 0, c->mat[0], nullptr, nullptr, nullptr, nullptr, tmp};
-    if (opts->mode == STBEM_FP64) {
+    if (!ir) {
         int it = 0;
         double rr = 0.0;
         rc = gmres(o64, f, w, opts->tol, opts->max_it, &it, &rr, s);
         inf.iters = it; inf.relres = rr;
         if (!rc) rc = true_relres(c, o64, f, w, tmp + 2 * c->n, &inf.true_relres, s);
         if (!rc && rr > opts->tol) rc = STBEM_WARN_NOT_CONVERGED;
-    } else if (opts->mode == STBEM_FP32_IR) {
-        if (!c->v_hi || !c->d_32) {
-            if ((rc = stbem_prepare_ir(c, stream))) { dev_free(c, tmp); return rc; }
+    } else {
+        if (!c->v_hi || (opts->precondition && !c->d_32 && c->mat[2])) {
+            if ((rc = stbem_prepare_ir(c, stream))) return rc;
         }
-        // outer: r = f - V w with V = hi + lo (FP64 accumulation); inner:
-        // GMRES on FP32 V_hi and FP32 D; w += correction
-        SolveOp ohl = {c, o64.trans, 0, nullptr, c->v_hi, c->v_lo, nullptr, nullptr, tmp};
+        // outer: r = f - V w in FP64 (the FP64 V_h when resident, else the
+        // pair hi + lo, accurate to about 2^-48); inner: GMRES on FP32 V_hi
+        // with the FP32 D_h in the preconditioner; w += correction
+        SolveOp ores = c->mat[0] ? o64 : SolveOp{c, o64.trans, 0, nullptr, c->v_hi, c->v_lo, nullptr, nullptr, tmp};
         SolveOp o32 = {c, o64.trans, opts->precondition ? 1 : 0, nullptr, nullptr, nullptr, c->v_hi, c->d_32, tmp};
-        double* r = (double*)dev_alloc(c, (size_t)2 * c->n * sizeof(double));
-        if (!r) { dev_free(c, tmp); return fail(c, STBEM_ENOMEM, "IR vectors"); }
-        double* corr = r + c->n;
-        HIPCHK(c, hipMemsetAsync(w, 0, (size_t)c->n * sizeof(double), s));
+        double* r = tmp + 3 * c->n;
+        double* corr = tmp + 4 * c->n;
+        hipLaunchKernelGGL(k_fill, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, 0.0, w);
+        HIPCHK(c, hipGetLastError());
         double prev = 1e300, res = 0.0;
         int outer = 0;
         for (;;) {
-            if ((rc = true_relres(c, ohl, f, w, r, &res, s))) break;
+            if ((rc = true_relres(c, ores, f, w, r, &res, s))) break;
             if (res <= opts->ir_tol) break;
             if (outer >= opts->max_outer) { rc = STBEM_WARN_NOT_CONVERGED; break; }
             if (res > 0.5 * prev) { rc = STBEM_WARN_IR_STAGNATION; break; }
@@ -2553,15 +2751,13 @@ int stbem_solve(stbem_ctx* c, const double* f, double* w, const stbem_solve_opts
             ++outer;
         }
         inf.outer = outer;
-        int rc2 = true_relres(c, o64, f, w, r, &inf.true_relres, s);
-        if (!rc && rc2) rc = rc2;
-        dev_free(c, r);
-    } else {
-        dev_free(c, tmp);
-        return fail(c, STBEM_EINVAL, "unknown solve mode %d", opts->mode);
+        inf.true_relres = res;
+        if (rc == 0 || rc == STBEM_WARN_NOT_CONVERGED || rc == STBEM_WARN_IR_STAGNATION) {
+            int rc2 = true_relres(c, ores, f, w, r, &inf.true_relres, s);
+            if (rc2) rc = rc2;
+        }
     }
     (void)hipStreamSynchronize(s);
-    dev_free(c, tmp);
     if (info) *info = inf;
     return rc;
 }
@@ -2572,30 +2768,21 @@ int stbem_grad_alpha(stbem_ctx* c, const double* lam, const double* w, const dou
     if (!c || !lam || !w || !g || !out) return STBEM_EINVAL;
     if (!c->mat[4] || !c->mat[5] || (u0 && !c->mat[6])) return fail(c, STBEM_ENOTASSEMBLED, "alpha-derivative operators not assembled");
     hipStream_t s = S(stream);
-    double* t = (double*)dev_alloc(c, (size_t)2 * c->n * sizeof(double));
-    if (!t) return fail(c, STBEM_ENOMEM, "temporaries");
-    int rc = 0;
+    int rc = ensure_wvec(c, 2);
+    if (rc || (rc = ensure_gmres(c, 1))) return rc;
+    double* t = c->wvec;
     // t = dK g - dV w - dM0 u0
-    if ((rc = packed_apply(c, c->mat[5], nullptr, nullptr, nullptr, 0, g, t, s))) goto done;
-    if ((rc = packed_apply(c, c->mat[4], nullptr, nullptr, nullptr, 0, w, t + c->n, s))) goto done;
+    if ((rc = packed_apply(c, c->mat[5], nullptr, nullptr, nullptr, 0, g, t, s))) return rc;
+    if ((rc = packed_apply(c, c->mat[4], nullptr, nullptr, nullptr, 0, w, t + c->n, s))) return rc;
     hipLaunchKernelGGL(k_axpby, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, -1.0, (const double*)(t + c->n), 1.0, t);
     if (u0) {
-        if ((rc = dense_apply(c, c->mat[6], 0, u0, t + c->n, s))) goto done;
+        if ((rc = dense_apply(c, c->mat[6], 0, u0, t + c->n, s))) return rc;
         hipLaunchKernelGGL(k_axpby, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, -1.0, (const double*)(t + c->n), 1.0, t);
     }
-    {
-        DotWork dw;
-        dw.nchunk = (int)((c->n + kDotChunk - 1) / kDotChunk);
-        dw.part = (double*)dev_alloc(c, (size_t)dw.nchunk * sizeof(double));
-        if (!dw.part) { rc = fail(c, STBEM_ENOMEM, "dot"); goto done; }
-        rc = dots(c, dw, lam, c->n, 1, t, out, s);
-        (void)hipStreamSynchronize(s);
-        dev_free(c, dw.part);
-    }
-done:
-    (void)hipStreamSynchronize(s);
-    dev_free(c, t);
-    return rc;
+    DotWork dw;
+    dw.nchunk = (int)((c->n + kDotChunk - 1) / kDotChunk);
+    dw.part = c->gm_part;
+    return dots(c, dw, lam, c->n, 1, t, out, s);
 }
 
 int stbem_entries(stbem_ctx* c, unsigned op, long long n, const int* idx, double* out, void* stream)

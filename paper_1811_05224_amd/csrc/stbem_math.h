@@ -530,6 +530,20 @@ SDEV void pair_integral(const Tables& T, const Orders& O, const TimeBlock& tb, i
 }
 
 // ---------------------------------------------------------- kernel functors
+// Compensated sum: s + c carries the running sum to about twice the working
+// precision (error-free transformation of each addition, Knuth's TwoSum; no
+// products, so contraction into FMA cannot change it).
+struct CSum {
+    double s, c;
+    SDEV void add(double x)
+    {
+        const double t = s + x, bp = t - s;
+        c += (s - (t - bp)) + (x - bp);
+        s = t;
+    }
+    SDEV double value() const { return s + c; }
+};
+
 // V_h (and dV_h/dalpha): constant shapes, the kernel depends on r only.
 template <bool DERIV>
 struct KernV {
@@ -605,8 +619,8 @@ struct KernD {
     double cc;                 // psi'_P psi'_Q
     double cn;                 // alpha n_P . n_Q
     double p0, dp, q0, dq;     // psi_P(sP) = p0 + dp sP, psi_Q(sQ) = q0 + dq sQ
-    double acc;
-    SDEV KernD(const TimeBlock& t, double al) : tb(t), alpha(al), acc(0.0) {}
+    CSum acc;                  // compensated: see DMomBP
+    SDEV KernD(const TimeBlock& t, double al) : tb(t), alpha(al), acc{0.0, 0.0} {}
     int raw;                         // use the raw-kernel form (smooth kernel)
     double tt, txx, txy, tyx, tyy;   // t_P.t_Q and the tangents
     SDEV void val(double w, double sP, double sQ, double dx, double dy, double r2)
@@ -624,10 +638,11 @@ struct KernD {
             else { TouchH s = touch_h(tb, a); dd = s.dd; va = s.va; vaa = s.vaa; }
             double zt = (dx * txx + dy * txy) * (dx * tyx + dy * tyy);
             double h = 0.25 * alpha * alpha * vaa * zt + 0.5 * alpha * va * tt;
-            acc += w * sh * (cn * dd - h);
+            acc.add(w * sh * (cn * dd - h));
         } else {
             TouchVals s = touch<true, false, true, false, false>(tb, a, alpha);
-            acc += w * (cc * s.v + cn * sh * s.dd);
+            acc.add(w * cc * s.v);
+            acc.add(w * cn * sh * s.dd);
         }
     }
     SDEV void split(double wa, double wb, double sP, double sQ, double, double, double r2, double lnr)
@@ -635,9 +650,11 @@ struct KernD {
         double a = 0.25 * alpha * r2;
         SplitVals s = touch_split<true, false, true, false, false>(tb, a, lnr, alpha);
         double sh = cn * (p0 + dp * sP) * (q0 + dq * sQ);
-        acc += wa * (cc * s.v.a + sh * s.dd.a) + wb * (cc * s.v.b + sh * s.dd.b);
+        acc.add(wa * cc * s.v.a + wb * cc * s.v.b);
+        acc.add(wa * sh * s.dd.a + wb * sh * s.dd.b);
     }
 };
+
 
 // Moments of one pair of half-segment pieces on touching time elements, for
 // D_h entries assembled from shared piece-pair moments.  x^, y^ in [0, 1] are
@@ -645,16 +662,20 @@ struct KernD {
 // a0 (1 - x^) + a1 x^ on each piece of its support.
 // By-parts form: m[0] = int int Delta F_V; m[1..4] = alpha n_P.n_Q times the
 // moments of Delta F_D against (1-x^)(1-y^), (1-x^) y^, x^ (1-y^), x^ y^.
+// For neighbouring dual functions the curl and the normal part of an entry
+// nearly cancel (by up to ~5e3 on coarse meshes), so the quadrature sums are
+// compensated: plain sums leave their rounding, amplified by that factor, at
+// a few 1e-13 of the entry.
 struct DMomBP {
-    const TimeBlock& tb; double alpha, iLP, iLQ; double m[5];
+    const TimeBlock& tb; double alpha, iLP, iLQ; CSum m[5];
     SDEV DMomBP(const TimeBlock& t, double al, const Piece& P, const Piece& Q)
-        : tb(t), alpha(al), iLP(1.0 / P.len), iLQ(1.0 / Q.len), m{0.0, 0.0, 0.0, 0.0, 0.0} {}
+        : tb(t), alpha(al), iLP(1.0 / P.len), iLQ(1.0 / Q.len), m{{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}} {}
     SDEV void add(double v, double d, double sP, double sQ)
     {
         const double x = sP * iLP, y = sQ * iLQ;
-        m[0] += v;
-        m[1] += d * (1.0 - x) * (1.0 - y); m[2] += d * (1.0 - x) * y;
-        m[3] += d * x * (1.0 - y);         m[4] += d * x * y;
+        m[0].add(v);
+        m[1].add(d * (1.0 - x) * (1.0 - y)); m[2].add(d * (1.0 - x) * y);
+        m[3].add(d * x * (1.0 - y));         m[4].add(d * x * y);
     }
     SDEV void val(double w, double sP, double sQ, double, double, double r2)
     {
@@ -698,8 +719,8 @@ SDEV void d_pair_bp(const Tables& T, const Orders& O, const TimeBlock& tb, doubl
     DMomBP f(tb, alpha, P, Q);
     pair_integral(T, O, tb, 0, 0, P, Q, f);
     const double cn = alpha * (P.nx * Q.nx + P.ny * Q.ny);
-    m[0] = f.m[0];
-    for (int c = 1; c < 5; ++c) m[c] = cn * f.m[c];
+    m[0] = f.m[0].value();
+    for (int c = 1; c < 5; ++c) m[c] = cn * f.m[c].value();
 }
 
 template <bool WV = false>
@@ -813,7 +834,7 @@ SDEV double entry(const Tables& T, const Orders& O, const Geom& g, const TimeBlo
             }
             raw = eta > O.eta_raw;
         }
-        double acc = 0.0;
+        CSum acc = {0.0, 0.0};
         for (int u = 0; u < 4; ++u) {
             Piece P = half_piece(g, si.piece[u]);
             for (int v = 0; v < 4; ++v) {
@@ -827,10 +848,11 @@ SDEV double entry(const Tables& T, const Orders& O, const Geom& g, const TimeBlo
                 kf.tt = P.ex * Q.ex + P.ey * Q.ey;
                 kf.raw = raw;
                 pair_integral(T, O, tb, q_far, q_inc(OP), P, Q, kf);
-                acc += kf.acc;
+                acc.add(kf.acc.s);
+                acc.add(kf.acc.c);
             }
         }
-        return acc;
+        return acc.value();
     }
 }
 

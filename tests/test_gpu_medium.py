@@ -41,7 +41,7 @@ def _sample(ng, nt, rng, nblocks=24):
     return np.array(idx, dtype=np.int32)
 
 
-@pytest.mark.parametrize("op,tol", [("V", 1e-12), ("K", 1e-12), ("D", 2e-12)])
+@pytest.mark.parametrize("op,tol", [("V", 1e-12), ("K", 1e-12), ("D", 1e-12)])
 def test_medium_sampled_entries(medium, op, tol):
     wl, o, c, L = medium
     rng = np.random.default_rng({"V": 1, "K": 2, "D": 3}[op])
