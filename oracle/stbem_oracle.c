@@ -33,6 +33,19 @@
  * and 1/r behaviour turns into exponential decay.  No singular splitting,
  * no series, no fixed rule: plain definitions integrated to ~1e-16.
  *
+ * Pins (CPU tests; none compares the oracle with itself):
+ *   E1 and the time primitives: mpmath tables and quadrature of the raw
+ *     kernels (V, K, D, dV/dalpha and the E1 kernel of dK/dalpha; M_h^0's);
+ *   V_h, K_h, D_h entries: brute-force integration of the raw fundamental
+ *     solution on coincident, vertex-sharing and separated pairs of touching
+ *     and separated time elements (D_h in the by-parts form, and against
+ *     the raw hypersingular kernel where the supports are disjoint);
+ *   M_h^0 rows of the first steps: brute force near the boundary;
+ *   dV, dK, dM_0: central differences in alpha of V_h, K_h, M_h^0;
+ *   together: affine exactness of eq.(4), the constant identity, symmetry
+ *     and positivity of V_h and D_h, causality, Toeplitz invariance, the
+ *     scaling laws, the lumped mass by quadrature, convergence of the flux.
+ *
  * Conventions: segment i joins polygon vertex i to vertex i+1 (cyclic),
  * outward normal n = (e_y, -e_x) for a CCW polygon; time element m is
  * (t_m, t_{m+1}]; DOF l = m * N_Gamma + i.

@@ -48,6 +48,10 @@ def test_time_integrals_vs_quadrature(d, r):
         "K": lambda s: a * mp.exp(-a / s) / s ** 2,                   # F_K'' (times (x-y).n/(2 pi r^2))
         "D": lambda s: mp.exp(-a / s) * (a - s) / (4 * mp.pi * s ** 3),   # d/ds of the V kernel
         "dV": lambda s: -(mp.mpf(r) ** 2 / (4 * s)) * mp.exp(-a / s) / (4 * mp.pi * s),
+        # dK_h/dalpha: at fixed r the alpha-derivative of the K kernel
+        # alpha (x-y).n_y e^{-a/s}/(8 pi s^2) is -(x-y).n_y/(8 pi) times
+        # e^{-a/s}(a - s)/s^3 (the four-point difference of E1(a/delta))
+        "E1": lambda s: mp.exp(-a / s) * (a - s) / s ** 3,
     }
     tk0, tk1, tm0, tm1 = map(mp.mpf, (t[k], t[k + 1], t[m], t[m + 1]))
     for name, f in kern.items():
@@ -310,3 +314,117 @@ def test_representation_formula_reproduces_affine_solutions(name):
     # the constant u = 1: only the initial and the double-layer potential
     P1 = o.potential(pts, 0 * w, 0 * g + 1, 0 * u0 + 1)
     assert np.abs(P1[:, 0] - P1[:, 2] - 1).max() <= 1e-14
+
+
+# ------------------------------------------- alpha-derivatives by differences
+def test_alpha_derivatives_vs_central_differences():
+    """dV_h/dalpha, dK_h/dalpha (entries, touching and separated time
+    elements, singular pairs included) and dM_h^0/dalpha (rows of the first
+    steps) equal central differences in alpha of the oracle's own V_h, K_h,
+    M_h^0, Richardson-extrapolated from steps 1e-3 alpha and 5e-4 alpha
+    (truncation O(h^4) ~ 1e-12): the derivative formulas are pinned by the
+    definition of a derivative, not by themselves."""
+    alpha = 1.3
+    wl = W.make("custom", n_side=2, n_t=4, n_omega=2, alpha=alpha)
+    t, bnd, vx, tr = wl.t_nodes, wl.bnd_xy, wl.vtx_xy, wl.tri
+    mk = lambda al: Oracle(al, t, bnd, vx, tr)
+    o = mk(alpha)
+    idx = [(0, 0, 1, 1), (0, 0, 1, 2), (1, 0, 1, 2), (1, 0, 2, 5), (3, 1, 0, 6), (2, 0, 3, 3), (3, 0, 7, 1)]
+
+    def cdiff(fn, h):
+        return (fn(mk(alpha + h)) - fn(mk(alpha - h))) / (2 * h)
+
+    def richardson(fn):
+        h = 1e-3 * alpha
+        return (4 * cdiff(fn, h / 2) - cdiff(fn, h)) / 3
+
+    for op, dop in (("V", "dV"), ("K", "dK")):
+        fd = richardson(lambda oo: oo.entries(op, idx))
+        got = o.entries(dop, idx)
+        np.testing.assert_allclose(got, fd, rtol=1e-9, atol=1e-11 * np.abs(fd).max(), err_msg=dop)
+    rows = [(0, 0), (0, 3), (1, 5), (3, 2)]
+    fd = richardson(lambda oo: oo.m0_rows(rows))
+    got = o.m0_rows(rows, deriv=True)
+    np.testing.assert_allclose(got, fd, rtol=1e-9, atol=1e-11 * np.abs(fd).max(), err_msg="dM0")
+
+
+# ------------------------------------------------- D_h: symmetry, positivity
+def test_D_symmetric_blocks_and_positive_definite():
+    """The kernel of every time block of D_h is symmetric in x and y
+    (it depends on |x - y| and n_x.n_y only), so every block D_(k,m) is a
+    symmetric matrix; the causal matrix has a positive definite symmetric
+    part (the hypersingular operator is elliptic, Sec. 2, Theorem 1).  The
+    oracle computes (i, j) and (j, i) with the pieces in swapped roles."""
+    wl = W.make("custom", n_side=2, n_t=4, n_omega=2, alpha=0.7,
+                t_nodes=W.graded_times(4, 1.5))
+    o = Oracle.from_workload(wl)
+    D = o.packed("D")
+    for b in range(D.shape[0]):
+        B_ = D[b]
+        assert np.abs(B_ - B_.T).max() <= 1e-14 * np.abs(B_).max(), b
+    A = o.dense(D)
+    assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0
+
+
+# ------------------------------------------------ lumped dual mass matrix
+def test_lumped_dual_mass_vs_quadrature():
+    """The lumped mass of the preconditioner (Sec. 4): for each dual hat
+    psi_i, the sum over the primal indicators phi_k of <phi_k, psi_i> is the
+    integral of psi_i over Gamma times h_m.  Computed here by Gauss
+    quadrature of the dual hat from its definition (1 at the midpoint of
+    segment i, 0 at the midpoints of segments i -/+ 1, linear in arclength)
+    on a polygon with unequal segments; the row sums over the dual hats give
+    |gamma_k| (the dual hats are a partition of unity)."""
+    rng = np.random.default_rng(3)
+    ang = np.sort(rng.uniform(0, 2 * np.pi, 9))
+    rad = rng.uniform(0.7, 1.3, 9)
+    bnd = np.stack([rad * np.cos(ang), rad * np.sin(ang)], 1)
+    t = W.graded_times(3, 1.4)
+    o = Oracle(1.0, t, bnd)
+    ng = bnd.shape[0]
+    L, e, _ = _normals(bnd)
+    cum = np.concatenate([[0.0], np.cumsum(L)])          # arclength of vertex i
+    P = cum[-1]
+    mids = cum[:-1] + 0.5 * L
+
+    def psi(i, s):
+        """Dual hat i at arclength s (periodic)."""
+        c, lo, hi = mids[i], mids[i - 1] - (P if i == 0 else 0), mids[(i + 1) % ng] + (P if i == ng - 1 else 0)
+        s = np.where(s < lo, s + P, np.where(s > hi, s - P, s))
+        return np.clip(np.where(s <= c, (s - lo) / (c - lo), (hi - s) / (hi - c)), 0, 1)
+
+    x, w = np.polynomial.legendre.leggauss(8)
+    Mk = np.zeros((ng, ng))
+    for k in range(ng):
+        for half in (0, 1):                                  # psi is linear on each half segment
+            a = cum[k] + half * 0.5 * L[k]
+            s = a + 0.25 * L[k] * (x + 1)
+            for i in range(ng):
+                Mk[k, i] = Mk[k, i] + np.sum(0.25 * L[k] * w * psi(i, s))
+    np.testing.assert_allclose(Mk.sum(1), L, rtol=1e-14)
+    h = np.diff(t)
+    lump = (h[:, None] * Mk.sum(0)[None, :]).reshape(-1)
+    np.testing.assert_allclose(o.lumped_dual_mass(), lump, rtol=1e-14)
+
+
+# ----------------------------------------------- convergence of the flux
+def test_neumann_datum_converges_for_manufactured_solution():
+    """u = exp(k.x + |k|^2 t/alpha) solves alpha u_t = Laplace u; its Neumann
+    datum w = (k.n) u.  With h_x = h_t halved per level (square, Omega_h the
+    matching grid), the oracle's discrete flux (eq.(4) solved by block
+    forward substitution) approaches the exact flux: the L2(Sigma) error of
+    w_h against the element means of w falls at every level, with an
+    observed order above 1."""
+    errs = []
+    for L in (1, 2, 3):
+        n = 2 ** L
+        wl = W.make("custom", n_side=n, n_t=n, n_omega=n, alpha=1.0, k=(0.5, 0.5))
+        o = Oracle.from_workload(wl)
+        V, K, M0 = o.packed("V"), o.packed("K"), o.m0()
+        w = o.solve_direct(V, o.rhs(K, M0, wl.g, wl.u0))
+        wt = np.repeat(o.h, o.ng) * np.tile(o.L, o.nt)
+        errs.append(np.sqrt(np.sum(wt * (w - wl.w_ref) ** 2) / np.sum(wt * wl.w_ref ** 2)))
+    eoc = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    print("flux errors", errs, "observed orders", eoc)
+    assert errs[0] < 0.1
+    assert np.all(eoc > 1.0), (errs, eoc)
