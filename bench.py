@@ -41,7 +41,14 @@ FP32_PEAK_TFLOPS = 157.3
 # (KiB x 1024) per dispatch over the units of the dispatch; the factor 2 on
 # FETCH_SIZE comes from a 1 GiB device copy read by the same counters.  A
 # kernel changed after its counters were taken has no entry here.
-HBM_BYTES_PER_UNIT = {}
+HBM_BYTES_PER_UNIT = {
+    # precision workload, profiles/dfar_q3_precision_counters.md: FETCH_SIZE
+    # 175,779 KiB (x 2) and WRITE_SIZE 128,512,000 KiB per dispatch of
+    # 8.2248e9 D entries (the D and the V entry written, FP64); the FP32-store
+    # launches write 96,384,000 KiB (V as hi + lo, D as FP32)
+    "k_assemble_dfar<3, true>": 16.04,
+    "k_assemble_dfar<3, true> f32-store": 12.04,
+}
 # bytes streamed per stored entry by the matrix-vector kernels
 GEMV_BYTES = {"k_gemv_n_vec<double>": 8, "k_gemv_t_vec<double>": 8, "k_gemv_n_vec<float hi+lo>": 8,
               "k_gemv_t_vec<float hi+lo>": 8, "k_gemv_n_vec<float>": 4, "k_gemv_t_vec<float>": 4}
@@ -217,7 +224,7 @@ def roofline(ktimes):
         achieved = GEMV_BYTES[name] * per_launch_units / per_launch_s / 1e9
         return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, **base}
-    peak = FP32_PEAK_TFLOPS if "f32" in name else FP64_PEAK_TFLOPS
+    peak = FP64_PEAK_TFLOPS             # every assembly kernel computes in FP64 (f32-store only stores FP32)
     achieved = flops / launches / per_launch_s / 1e12 if flops > 0 else None
     return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak if achieved is not None else None,
@@ -261,10 +268,22 @@ def adjoint_gradient(dev):
         e[6].record(stream)
         torch.cuda.synchronize()
         res = {n: e[q].elapsed_time(e[q + 1]) for q, n in enumerate(names)}
+    # dJ/dalpha with the alpha-derivative matrices recomputed block-row range
+    # by range instead of stored (the path for meshes where they do not fit)
+    c.release(L.DV | L.DK | L.DM0)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    ga2 = c.grad_alpha(lam, w, g, u0)
+    b.record(stream)
+    torch.cuda.synchronize()
+    res["grad alpha, matrices recomputed (not stored)"] = a.elapsed_time(b)
+    d_alpha, d_alpha2 = float(ga.cpu()[0]), float(ga2.cpu()[0])
     c.close()
     return {"workload": "diff: N_Gamma=128, N_I=128, N=16384, M_Omega=1089, alpha=1.0", "ms": res,
             "gradient_ms": sum(res[n] for n in names[1:]), "iters": {"forward": i1.iters, "adjoint": i2.iters},
-            "dJ_dalpha": float(ga.cpu()[0]), "norm_dJ_dg": float(gg.norm())}
+            "dJ_dalpha": d_alpha, "dJ_dalpha_recomputed_rel_diff": abs(d_alpha2 - d_alpha) / abs(d_alpha),
+            "norm_dJ_dg": float(gg.norm())}
 
 
 def paper_table2(dev):

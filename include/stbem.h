@@ -213,8 +213,15 @@ int stbem_solve(stbem_ctx* ctx, const double* f_dev, double* w_dev, const stbem_
 /* d J / d alpha contribution lambda^T (dK_h g - dM_h^0 u0 - dV_h w) for an
  * adjoint state lambda (from a trans = 1 solve): the alpha-derivative of
  * eq.(4), V_h w = (1/2 M_h + K_h) g - M_h^0 u0, with M_h independent of
- * alpha.  Needs STBEM_DV, STBEM_DK and, if u0_dev is not NULL, STBEM_DM0.
- * The scalar is written to out_dev[0] (device).  */
+ * alpha.  Each of dV_h w, dK_h g and dM_h^0 u0 (u0_dev may be NULL: no
+ * initial term) uses the stored matrix when STBEM_DV / STBEM_DK / STBEM_DM0
+ * is assembled; otherwise it is recomputed without storing the matrix:
+ * ranges of block rows are assembled into a buffer of at most 1 GiB (at
+ * least one block row) by the same kernels and contracted at once, M_h^0's
+ * derivative in row chunks.  Results agree with the stored path to
+ * rounding.  Not available in block-Toeplitz mode without the stored
+ * matrices (STBEM_ENOTASSEMBLED).  Synchronises the stream on the recomputed
+ * path.  The scalar is written to out_dev[0] (device).  */
 int stbem_grad_alpha(stbem_ctx* ctx, const double* lambda_dev, const double* w_dev, const double* g_dev,
                      const double* u0_dev, double* out_dev, void* stream);
 

@@ -145,6 +145,22 @@ class Oracle:
         # np.tril_indices orders (k, m) row by row: index = k(k+1)/2 + m
         return self.entries(op, idx.reshape(-1, 4)).reshape(nb, ng, ng)
 
+    def toeplitz_blocks(self, op: str) -> np.ndarray:
+        """Uniform time steps only: block (k, m) of a causal operator depends
+        on k - m alone (the kernel is a function of t - tau), so the blocks
+        (d, 0), d = 0..nt-1, determine the whole matrix."""
+        h = np.diff(self.t)
+        if np.abs(h - h[0]).max() > 1e-12 * h[0]:
+            raise ValueError("Toeplitz blocks need uniform time steps")
+        ng, nt = self.ng, self.nt
+        ii, jj = np.meshgrid(np.arange(ng), np.arange(ng), indexing="ij")
+        idx = np.empty((nt, ng * ng, 4), dtype=np.int32)
+        idx[:, :, 0] = np.arange(nt)[:, None]
+        idx[:, :, 1] = 0
+        idx[:, :, 2] = ii.ravel()[None, :]
+        idx[:, :, 3] = jj.ravel()[None, :]
+        return self.entries(op, idx.reshape(-1, 4)).reshape(nt, ng, ng)
+
     def m0_rows(self, rows, deriv: bool = False) -> np.ndarray:
         rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int32).reshape(-1, 2))
         out = np.empty((rows.shape[0], self.nv), dtype=np.float64)
@@ -245,6 +261,35 @@ def packed_apply(P, x, nt, ng, trans=False):
             else:
                 Y[k] += B @ X[m]
     return Y.reshape(-1)
+
+
+def toeplitz_apply(T, x, nt, ng, trans=False):
+    """y = A x (or A^T x) for a causal block-Toeplitz A with blocks
+    T[d] = A_(k, k-d)."""
+    X = x.reshape(nt, ng)
+    Y = np.zeros((nt, ng))
+    for k in range(nt):
+        for m in range(k + 1):
+            if trans:
+                Y[m] += T[k - m].T @ X[k]
+            else:
+                Y[k] += T[k - m] @ X[m]
+    return Y.reshape(-1)
+
+
+def toeplitz_forward_solve(T, f, nt, ng):
+    """Block forward substitution for a causal block-Toeplitz A:
+    T[0] w_k = f_k - sum_{m<k} T[k-m] w_m (T[0] symmetric positive definite)."""
+    import scipy.linalg as sla
+    F = f.reshape(nt, ng)
+    W = np.zeros((nt, ng))
+    c = sla.cho_factor(0.5 * (T[0] + T[0].T))
+    for k in range(nt):
+        rhs = F[k].copy()
+        for m in range(k):
+            rhs -= T[k - m] @ W[m]
+        W[k] = sla.cho_solve(c, rhs)
+    return W.reshape(-1)
 
 
 def block_forward_solve(P, f, nt, ng, trans=False):

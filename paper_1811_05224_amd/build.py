@@ -9,7 +9,7 @@ HEADERS = ["stbem_math.h", "stbem_m0.h", "stbem_tables.h", "loggauss_table.h"]
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-result", "-L/opt/rocm/lib", "-lrocblas"]
+         "-Wno-unused-result"]
 
 
 def build(verbose: bool = False) -> str:

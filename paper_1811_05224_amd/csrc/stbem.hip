@@ -16,10 +16,10 @@
 // bitwise reproducible.  GMRES keeps the Krylov basis in HBM; the small
 // Hessenberg least-squares problem is solved on the host.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -187,16 +187,28 @@ __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restri
     store_tile(stage, SYM, v, live, block_slot(g, b, k, m) * g.ng * g.ng, g.ng, I0, J0, il, jl, out);
 }
 
-// V_h and K_h on separated time elements (series), Gauss order Q fixed at
-// compile time so the Q x Q node pairs of a segment pair unroll into Q
-// independent series recurrences per step (instruction-level parallelism).
-template <int Q, bool NEED_V>
+// V_h, K_h and their alpha-derivatives on separated time elements (series),
+// Gauss order Q fixed at compile time so the Q x Q node pairs of a segment
+// pair unroll into Q independent series recurrences per step
+// (instruction-level parallelism).  With z = alpha r^2 / (4 dc) and the sums
+// S0 = sum c_n L_2n(z), S1 = sum c_n L^(1)_2n(z), S2 = sum c_n L^(2)_2n(z):
+//   V  integrand  e^{-z} S0 / (4 pi dc)
+//   K  integrand  (x-y).n_y alpha / (8 pi dc^2) e^{-z} S1
+// and, as d/dalpha = (z / alpha) d/dz with d/dz (e^{-z} L^(b)_n) = -e^{-z} L^(b+1)_n,
+//   dV integrand  -(z / alpha) e^{-z} S1 / (4 pi dc)
+//   dK integrand  (x-y).n_y / (8 pi dc^2) e^{-z} (S1 - z S2)
+//               = (x-y).n_y / (8 pi dc^2) e^{-z} SD,  SD = sum (2n+1) c_n L_2n+1(z)
+// (z L^(2)_n = (n+2) L^(1)_n - (n+1) L^(1)_n+1 and L^(1)_n+1 - L^(1)_n = L_n+1):
+// the series of the time kernel E1 that D_h's normal part uses, without the
+// subtraction.
+template <int Q, int OP>
 __device__ __forceinline__ void far_pair(const Tables& T, const TimeBlock& tb, double al,
                                          const double* P, const double* Qs, double nqx, double nqy,
                                          double& m0, double& m1)
 {
-    // P, Qs: ax ay ex ey len; V: m0 = int int Delta F_V; K: shape moments of the
-    // double-layer kernel (x-y).n_Q/(2 pi r^2) Delta F_K (a/r^2 = alpha/4)
+    // P, Qs: ax ay ex ey len; V, dV: m0 = int int of the kernel; K, dK: the
+    // two shape moments of the double-layer kernel
+    constexpr bool VT = OP == OP_V || OP == OP_DV;
     m0 = 0.0; m1 = 0.0;
 #pragma unroll 1
     for (int a = 0; a < Q; ++a) {
@@ -210,7 +222,7 @@ __device__ __forceinline__ void far_pair(const Tables& T, const TimeBlock& tb, d
             z[c] = 0.25 * al * (dx * dx + dy * dy) * tb.inv_dc;
             dn[c] = dx * nqx + dy * nqy;
             l0[c] = 1.0; l1[c] = 1.0 - z[c];
-            acc[c] = NEED_V ? tb.st[0][11] : tb.st[0][6] + tb.st[0][7] * l1[c];
+            acc[c] = OP == OP_V ? tb.st[0][11] : OP == OP_DK ? tb.st[0][10] * l1[c] : tb.st[0][6] + tb.st[0][7] * l1[c];
         }
         for (int n = 1; n < tb.nterm; ++n) {
             const double* st = tb.st[n];
@@ -218,7 +230,8 @@ __device__ __forceinline__ void far_pair(const Tables& T, const TimeBlock& tb, d
             for (int c = 0; c < Q; ++c) {
                 const double x2 = fma(fma(-st[1], z[c], st[0]), l1[c], -st[2] * l0[c]);
                 const double x3 = fma(fma(-st[4], z[c], st[3]), x2, -st[5] * l1[c]);
-                if (NEED_V) acc[c] = fma(st[11], x2, acc[c]);
+                if (OP == OP_V) acc[c] = fma(st[11], x2, acc[c]);
+                else if (OP == OP_DK) acc[c] = fma(st[10], x3, acc[c]);
                 else acc[c] = fma(st[7], x3, fma(st[6], x2, acc[c]));
                 l0[c] = x2; l1[c] = x3;
             }
@@ -227,17 +240,24 @@ __device__ __forceinline__ void far_pair(const Tables& T, const TimeBlock& tb, d
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
             const double e = exp(-z[c]);
-            if (NEED_V) {
-                m0 += wP * Qs[4] * T.gl_w[Q][c] * e * acc[c];
+            const double wq = wP * Qs[4] * T.gl_w[Q][c];
+            if (OP == OP_V) {
+                m0 += wq * e * acc[c];
+            } else if (OP == OP_DV) {
+                m0 += wq * e * z[c] * acc[c];
             } else {
-                const double v = wP * Qs[4] * T.gl_w[Q][c] * dn[c] * e * acc[c];
+                const double v = wq * dn[c] * e * acc[c];
                 m0 += v * (1.0 - T.gl_x[Q][c]);
                 m1 += v * T.gl_x[Q][c];
             }
         }
     }
-    if (NEED_V) m0 *= tb.inv_dc * kInv4Pi;
-    else { const double f = al * 0.125 / kPi * tb.inv_dc * tb.inv_dc; m0 *= f; m1 *= f; }
+    if (OP == OP_V) m0 *= tb.inv_dc * kInv4Pi;
+    else if (OP == OP_DV) m0 *= -tb.inv_dc * kInv4Pi / al;
+    else {
+        const double f = (OP == OP_K ? al : 1.0) * 0.125 / kPi * tb.inv_dc * tb.inv_dc;
+        m0 *= f; m1 *= f;
+    }
 }
 
 template <int OP, int Q>
@@ -245,7 +265,8 @@ __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __
                                                         const int* __restrict__ blist, int tiles_i, int tiles_j,
                                                         OutBuf out, const TimeBlock* __restrict__ tbs)
 {
-    constexpr bool SYM = OP == OP_V;
+    constexpr bool SYM = OP == OP_V || OP == OP_DV;
+    constexpr bool KT = OP == OP_K || OP == OP_DK;     // hat columns (15 per tile)
     __shared__ double stage[kTile][kTile + 1];
     const int tid = threadIdx.x;
     const long long tiles = SYM ? (long long)tiles_i * (tiles_i + 1) / 2 : (long long)tiles_i * tiles_j;
@@ -261,18 +282,18 @@ __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __
     const int i = ti * kTile + ty;
     // V: column j = J0 + tx.  K: the tile covers segments J0-1 .. J0+14 and
     // writes the 15 hats J0 .. J0+14 (hat j = rising part on j-1 + falling on j)
-    const int J0 = tj * (OP == OP_K ? kTile - 1 : kTile);
-    int jseg = OP == OP_K ? J0 - 1 + tx : J0 + tx;
+    const int J0 = tj * (KT ? kTile - 1 : kTile);
+    int jseg = KT ? J0 - 1 + tx : J0 + tx;
     jseg = jseg < 0 ? jseg + g.ng : (jseg >= g.ng ? jseg - g.ng : jseg);
     double m0 = 0.0, m1 = 0.0;
-    const bool live = i < g.ng && (OP == OP_K || J0 + tx < g.ng);
+    const bool live = i < g.ng && (KT || J0 + tx < g.ng);
     if (live && !mirrored(SYM, ti * kTile, J0, ty, tx)) {
         const double P[5] = {g.vx[i], g.vy[i], g.ex[i], g.ey[i], g.len[i]};
         const double Qs[5] = {g.vx[jseg], g.vy[jseg], g.ex[jseg], g.ey[jseg], g.len[jseg]};
-        far_pair<Q, OP == OP_V>(T, tb, g.alpha, P, Qs, g.ey[jseg], -g.ex[jseg], m0, m1);
+        far_pair<Q, OP>(T, tb, g.alpha, P, Qs, g.ey[jseg], -g.ex[jseg], m0, m1);
     }
     const long long boff = block_slot(g, b, k, m) * g.ng * g.ng, rowoff = boff + (long long)i * g.ng;
-    if (OP == OP_V) {
+    if (SYM) {
         store_tile(stage, true, m0, live, boff, g.ng, ti * kTile, J0, ty, tx, out);
     } else {
         // lanes of one tile row are consecutive: the rising moment of segment
@@ -1038,10 +1059,10 @@ constexpr int kRowsPerWave = 8;
 template <class T, int VW, class ACC, bool HILO>
 __global__ __launch_bounds__(kWG) void k_gemv_n_vec(const T* __restrict__ A, const T* __restrict__ A2,
                                                     const double* __restrict__ x, double* __restrict__ part,
-                                                    int ng, int rowchunks)
+                                                    int ng, int rowchunks, long long b0)
 {
     typedef typename VecLd<T, VW>::type VT;
-    const long long b = blockIdx.x / rowchunks;
+    const long long b = b0 + blockIdx.x / rowchunks;
     const int rc = (int)(blockIdx.x % rowchunks);
     int k, m;
     block_of(b, k, m);
@@ -1079,18 +1100,18 @@ __global__ __launch_bounds__(kWG) void k_gemv_n_vec(const T* __restrict__ A, con
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
         const int i = (rc * 4 + wave) * kRowsPerWave + rr;
-        if (lane == 0 && i < ng) part[b * ng + i] = (double)v;
+        if (lane == 0 && i < ng) part[(b - b0) * ng + i] = (double)v;
     }
 }
 
 template <class T, int VW, class ACC, bool HILO>
 __global__ __launch_bounds__(kWG) void k_gemv_t_vec(const T* __restrict__ A, const T* __restrict__ A2,
                                                     const double* __restrict__ x, double* __restrict__ part,
-                                                    int ng, int colchunks)
+                                                    int ng, int colchunks, long long b0)
 {
     typedef typename VecLd<T, VW>::type VT;
     __shared__ ACC red[4][64 * VW];
-    const long long b = blockIdx.x / colchunks;
+    const long long b = b0 + blockIdx.x / colchunks;
     const int cc = (int)(blockIdx.x % colchunks);
     int k, m;
     block_of(b, k, m);
@@ -1124,7 +1145,7 @@ __global__ __launch_bounds__(kWG) void k_gemv_t_vec(const T* __restrict__ A, con
 #pragma unroll
         for (int q = 0; q < VW; ++q) {
             const int c = lane * VW + q;
-            part[b * ng + j0 + q] = (double)(((red[0][c] + red[1][c]) + red[2][c]) + red[3][c]);
+            part[(b - b0) * ng + j0 + q] = (double)(((red[0][c] + red[1][c]) + red[2][c]) + red[3][c]);
         }
     }
 }
@@ -1134,32 +1155,152 @@ __global__ __launch_bounds__(kWG) void k_gemv_t_vec(const T* __restrict__ A, con
 // the transpose).  A workgroup takes 32 outputs; 8 lanes per output sum
 // fixed contiguous chunks of the partials, and the 8 chunk sums are added in
 // chunk order, so the result does not depend on the launch.
+// The partials present are those of the block rows [k0, k1), part[0] being
+// packed block pb0 = k0 (k0 + 1) / 2.  trans = 0: outputs of block rows
+// [k0, k1).  trans = 1: outputs of block columns [0, k1), summed over the
+// rows k in [max(blk, k0), k1); a column's first rows (blk >= k0) write y,
+// columns met in earlier row ranges (blk < k0) add to it.
 constexpr int kRedSplit = 8, kRedOut = kWG / kRedSplit;
 __global__ __launch_bounds__(kWG) void k_gemv_reduce(const double* __restrict__ part, double* __restrict__ y,
-                                                     int ng, int nt, int trans)
+                                                     int ng, int k0, int k1, long long pb0, int trans)
 {
     __shared__ double red[kRedSplit][kRedOut];
     const int seg = threadIdx.x / kRedOut, il = threadIdx.x % kRedOut;
-    const long long e = (long long)blockIdx.x * kRedOut + il;
+    const long long e = (trans ? 0 : (long long)k0 * ng) + (long long)blockIdx.x * kRedOut + il;
+    const long long eend = (long long)k1 * ng;
     double s = 0.0;
-    if (e < (long long)ng * nt) {
-        const int blk = (int)(e / ng), i = (int)(e % ng);
-        const int lo = trans ? blk : 0, len = trans ? nt - blk : blk + 1;
+    int blk = 0;
+    if (e < eend) {
+        blk = (int)(e / ng);
+        const int i = (int)(e % ng);
+        const int lo = trans ? (blk > k0 ? blk : k0) : 0, len = trans ? k1 - lo : blk + 1;
         const int a = lo + (int)((long long)len * seg / kRedSplit), b = lo + (int)((long long)len * (seg + 1) / kRedSplit);
         if (!trans) {
-            const long long b0 = (long long)blk * (blk + 1) / 2;
+            const long long b0 = (long long)blk * (blk + 1) / 2 - pb0;
             for (int m = a; m < b; ++m) s += part[(b0 + m) * ng + i];
         } else {
-            for (int k = a; k < b; ++k) s += part[((long long)k * (k + 1) / 2 + blk) * ng + i];
+            for (int k = a; k < b; ++k) s += part[((long long)k * (k + 1) / 2 + blk - pb0) * ng + i];
         }
     }
     red[seg][il] = s;
     __syncthreads();
-    if (seg == 0 && e < (long long)ng * nt) {
+    if (seg == 0 && e < eend) {
         double t = red[0][il];
         for (int c = 1; c < kRedSplit; ++c) t += red[c][il];
-        y[e] = t;
+        if (trans && blk < k0) y[e] += t;
+        else y[e] = t;
     }
+}
+
+// Block-Toeplitz product (uniform time steps: block (k, m) = A_{k-m}, stored
+// row-major at lag d = k - m).  With X, Y the N_Gamma x N_I views of x, y
+// (column k = time element k):
+//   TRANS = 0:  Y[i, k] = sum_{d <= k}        sum_j A_d[i, j] X[j, k - d]
+//   TRANS = 1:  Y[j, m] = sum_{d < N_I - m}   sum_i A_d[i, j] X[i, m + d]
+// a contraction over (d, j) (or (d, i)): it runs on the FP64 matrix cores.
+// A workgroup owns a 64 x 64 tile of Y (rows x time columns), each of its
+// four waves a 32 x 32 quarter as 2 x 2 MFMA tiles of 16 x 16
+// (v_mfma_f64_16x16x4f64 on gfx950, layout measured: A operand lane =
+// row + 16 kk, B operand lane = col + 16 kk, result register r of lane l =
+// row l / 16 + 4 r, column l % 16).  The
+// contraction index advances 16 at a time; lane kk of a 16-wide step takes
+// the indices 4 kk .. 4 kk + 3, one per MFMA, so A's rows (TRANS = 0) and X's
+// columns are read as 32-byte vectors when N_Gamma is a multiple of 16.
+// The sum over (d, index) runs in one fixed order per output: results are
+// bitwise reproducible.  Tiles are dealt to the 8 XCDs in runs that share
+// a row strip of the A_d (L2 reuse), the longest lag ranges first.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kTT = 64;            // tile edge
+template <int TRANS, bool VEC>
+__global__ __launch_bounds__(kWG) void k_toeplitz_mfma(const double* __restrict__ A, const double* __restrict__ x,
+                                                       double* __restrict__ y, int ng, int nt, int tiles_r, int tiles_c)
+{
+    const int ntile = tiles_r * tiles_c;
+    const int per = (ntile + 7) / 8;
+    const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (t >= ntile) return;
+    const int rt = t / tiles_c, cslot = t % tiles_c;
+    // TRANS = 0: column tiles with more lags (larger k) first; TRANS = 1: smaller m first
+    const int ct = TRANS ? cslot : tiles_c - 1 - cslot;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int r0 = rt * kTT + (wave >> 1) * 32, c0 = ct * kTT + (wave & 1) * 32;
+    const int lr = l & 15, kk = l >> 4;
+    const long long ngl = ng, bsz = ngl * ngl;
+    v4d acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    // lags that reach this wave's columns
+    const int cmax = min(c0 + 31, nt - 1);
+    if (c0 < nt && r0 < ng) {
+        const int dend = TRANS ? nt - c0 : cmax + 1;
+        for (int d = 0; d < dend; ++d) {
+            const double* Ad = A + (long long)d * bsz;
+            // time column of X feeding output column c: c - d (TRANS = 0) or c + d
+            int xc[2];
+            bool xok[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int c = c0 + b * 16 + lr;
+                xc[b] = TRANS ? c + d : c - d;
+                xok[b] = c < nt && xc[b] >= 0 && xc[b] < nt;
+            }
+            for (int j0 = 0; j0 < ng; j0 += 16) {
+                const int jb = j0 + 4 * kk;          // this lane's 4 contraction indices
+                double av[2][4], bv[2][4];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const int row = r0 + a * 16 + lr;
+                    if (!TRANS) {
+                        // A_d[row][jb .. jb+3]
+                        if (VEC && row < ng) {
+                            const v4d q = *reinterpret_cast<const v4d*>(Ad + (long long)row * ng + jb);
+                            av[a][0] = q[0]; av[a][1] = q[1]; av[a][2] = q[2]; av[a][3] = q[3];
+                        } else {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                av[a][q] = (row < ng && jb + q < ng) ? Ad[(long long)row * ng + jb + q] : 0.0;
+                        }
+                    } else {
+                        // A_d[jb + q][row]: rows of A_d, 16 lanes read 16 consecutive columns
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            av[a][q] = (row < ng && jb + q < ng) ? Ad[(long long)(jb + q) * ng + row] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const double* xcol = x + (long long)xc[b] * ng;
+                    if (VEC && xok[b]) {
+                        const v4d q = *reinterpret_cast<const v4d*>(xcol + jb);
+                        bv[b][0] = q[0]; bv[b][1] = q[1]; bv[b][2] = q[2]; bv[b][3] = q[3];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) bv[b][q] = (xok[b] && jb + q < ng) ? xcol[jb + q] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b)
+                            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a][q], bv[b][q], acc[a][b], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int c = c0 + b * 16 + lr;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + a * 16 + kk + 4 * r;
+                if (row < ng && c < nt) y[(long long)c * ng + row] = acc[a][b][r];
+            }
+        }
 }
 
 // dense row-major M (rows x cols): y = M x (a wavefront per row)
@@ -1340,6 +1481,7 @@ struct stbem_ctx {
     int nlist_gen[7] = {0, 0, 0, 0, 0, 0, 0};
     int nlist_far[7][9] = {};
     std::vector<int> list_nterm[7];       // series terms of each listed block (host copy, for the work model)
+    std::vector<int> h_blist[7];          // host copy of the block lists (each group in increasing k)
     bool vd_fusable = false;              // V_h and D_h have the same far-tile block lists
     // work
     double* part = nullptr;     // nblk * ng
@@ -1356,7 +1498,6 @@ struct stbem_ctx {
     std::string err;
     // block-Toeplitz storage (stbem_set_toeplitz): block (k, m) at lag k - m
     bool toep = false;
-    rocblas_handle blas = nullptr;
     // launch timing (stbem_set_timing): one event pair per launch
     struct TRec { std::string name; double units, flops; hipEvent_t a, b; };
     bool timing = false;
@@ -1515,6 +1656,14 @@ std::string kname(const char* base, int a, int b)
     return std::string(base) + "<" + std::to_string(a) + ", " + std::to_string(b) + ">";
 }
 
+// timer name of an assembly launch: the kernel's name, marked when the
+// launch stores into FP32 storage (same kernel, 12 instead of 16 bytes per
+// entry pair written)
+std::string store_name(const char* base, const OutBuf& o)
+{
+    return o.f64 ? std::string(base) : std::string(base) + " f32-store";
+}
+
 // stored entries of a causal operator: packed lower block triangle, or one
 // block per lag in block-Toeplitz mode
 long long causal_entries(const stbem_ctx* c)
@@ -1571,9 +1720,10 @@ void launch_knear(stbem_ctx* c, int slot, double* o, hipStream_t s)
 // Algorithmic operation counts of the far-field (series) kernels, FMA = 2,
 // an FP64 exponential = 29 (range reduction, degree-11 polynomial, scaling),
 // counted from the kernels' arithmetic for the lanes that do work:
-//   far_pair (V_h, K_h; one segment pair per lane): per row of Q nodes 5;
-//     per node pair V 13 + 35 after the series, K 18 + 39; per series term
-//     and node pair V 12, K 14 (two recurrence steps of 5, sums 2 or 4)
+//   far_pair (V_h, K_h, dV_h, dK_h; one segment pair per lane): per row of
+//     Q nodes 5; per node pair V 13 + 35 after the series, dV 14 + 38,
+//     K 18 + 39, dK 17 + 39; per series term and node pair V and dK 12, K and
+//     dV 14 (two recurrence steps of 5, sums 2 or 4)
 //   far_dpair (D_h; one half-piece pair): 21 per pair; per row 19 (WV) or
 //     17; per node pair 25 + 45 (WV) or 42 after the series; per term 22 (WV)
 //     or 20; per stored D_h entry of a tile 196 to combine 16 pairs (+3 V_h)
@@ -1581,7 +1731,8 @@ void launch_knear(stbem_ctx* c, int slot, double* o, hipStream_t s)
 double flops_vkfar(int op, int Q, long long nblk, long long sum_nterm, long long lanes_per_block)
 {
     const double q2 = (double)Q * Q;
-    const double node = op == OP_V ? 48.0 : 57.0, term = op == OP_V ? 12.0 : 14.0;
+    const double node = op == OP_V ? 48.0 : op == OP_DV ? 52.0 : op == OP_K ? 57.0 : 56.0;
+    const double term = op == OP_V || op == OP_DK ? 12.0 : 14.0;
     return (double)lanes_per_block * ((double)nblk * (5.0 * Q + q2 * (node - term) + 5.0) + term * q2 * (double)sum_nterm);
 }
 
@@ -1607,13 +1758,14 @@ long long sum_terms(const stbem_ctx* c, int slot, const int* bl, int cnt)
 template <int OP, int Q>
 void launch_vkfar(stbem_ctx* c, int slot, const int* bl, int cnt, OutBuf o, hipStream_t s)
 {
+    constexpr bool SYM = OP == OP_V || OP == OP_DV;
     int ti = (c->ng + kTile - 1) / kTile;
-    int tj = OP == OP_V ? ti : (c->ng + kTile - 2) / (kTile - 1);
-    const long long tiles = OP == OP_V ? tiles_per_block(ti, true) : (long long)ti * tj;
+    int tj = SYM ? ti : (c->ng + kTile - 2) / (kTile - 1);
+    const long long tiles = SYM ? tiles_per_block(ti, true) : (long long)ti * tj;
     const int step = blocks_per_launch(tiles);
     for (int off = 0; off < cnt; off += step) {
         const int n = std::min(step, cnt - off);
-        const long long lanes = OP == OP_V ? (long long)c->ng * (c->ng + 1) / 2 : (long long)c->ng * tj * kTile;
+        const long long lanes = SYM ? (long long)c->ng * (c->ng + 1) / 2 : (long long)c->ng * tj * kTile;
         KTimer kt(c, kname("k_assemble_vkfar", OP, Q).c_str(), (double)n * c->ng * c->ng, s,
                   c->timing ? flops_vkfar(OP, Q, n, sum_terms(c, slot, bl + off, n), lanes) : 0.0);
         hipLaunchKernelGGL((k_assemble_vkfar<OP, Q>), dim3((unsigned)(n * tiles)), dim3(kWG), 0, s, geom(c), c->d_tab,
@@ -1655,7 +1807,7 @@ int build_block_lists(stbem_ctx* c)
                 time_block(g, k, m, tb);
                 int q = q_block(op, c->lmax, block_min_lag(g.t, k, m), g.alpha);
                 if ((op == OP_V || op == OP_D || op == OP_K || op == OP_DK) && tb.d <= 1) touch.push_back(b);
-                else if (!tb.ser || op == OP_DV || op == OP_DK) gen.push_back(b);
+                else if (!tb.ser) gen.push_back(b);
                 else if (q >= 3 && q <= 8) { far[q].push_back(b); nterm_far[q].push_back(tb.nterm); }
                 else gen.push_back(b);
             }
@@ -1669,6 +1821,7 @@ int build_block_lists(stbem_ctx* c)
         }
         c->nlist_touch[slot] = (int)touch.size();
         c->nlist_gen[slot] = (int)gen.size();
+        c->h_blist[slot] = all;
         int rc = upload(c, &c->d_blist[slot], all);
         if (rc) return rc;
         if (slot == 0 || slot == 2) far_lists[slot / 2].assign(all.end() - (all.size() - touch.size() - gen.size()), all.end());
@@ -1801,7 +1954,8 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd, int pre
         const int step = blocks_per_launch(tiles);
         for (int off = 0; off < c->nlist_touch[2]; off += step) {
             const int n = std::min(step, c->nlist_touch[2] - off);
-            KTimer kt(c, fuse_vd ? "k_assemble_dnear<true>" : "k_assemble_dnear<false>", (double)n * c->ng * c->ng, s);
+            KTimer kt(c, store_name(fuse_vd ? "k_assemble_dnear<true>" : "k_assemble_dnear<false>", od).c_str(),
+                      (double)n * c->ng * c->ng, s);
             if (fuse_vd)
                 hipLaunchKernelGGL(k_assemble_dnear<true>, dim3((unsigned)(n * tiles)), dim3(kWG), 0, s, geom(c), c->d_tab, c->ord,
                                    (const int*)(c->d_blist[2] + off), t1, od, ov);
@@ -1819,7 +1973,7 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd, int pre
                 dim3 gr((unsigned)(n * tiles)), blk(kWG);
                 const int* b2 = bl + off;
                 const std::string kn = std::string("k_assemble_dfar<") + std::to_string(q) + (fuse_vd ? ", true>" : ", false>");
-                KTimer kt(c, kn.c_str(), (double)n * c->ng * c->ng, s,
+                KTimer kt(c, store_name(kn.c_str(), od).c_str(), (double)n * c->ng * c->ng, s,
                           c->timing ? flops_dfar(q, fuse_vd, n, sum_terms(c, 2, b2, n), tiles, (long long)c->ng * (c->ng + 1) / 2) : 0.0);
                 if (fuse_vd) switch (q) {
                 case 3: hipLaunchKernelGGL((k_assemble_dfar<3, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, ov, c->d_tbs); break;
@@ -1843,8 +1997,15 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd, int pre
         HIPCHK(c, hipGetLastError());
         return 0;
     }
-    case STBEM_DV: return launch_assemble<OP_DV>(c, out_of(c, 4), s);
-    case STBEM_DK: launch_knear<OP_DK>(c, 5, o, s); return launch_assemble<OP_DK>(c, out_of(c, 5), s);
+    case STBEM_DV: {
+        int rc = launch_assemble<OP_DV>(c, out_of(c, 4), s);
+        return rc ? rc : launch_far<OP_DV>(c, 4, out_of(c, 4), s);
+    }
+    case STBEM_DK: {
+        launch_knear<OP_DK>(c, 5, o, s);
+        int rc = launch_assemble<OP_DK>(c, out_of(c, 5), s);
+        return rc ? rc : launch_far<OP_DK>(c, 5, out_of(c, 5), s);
+    }
     case STBEM_M0:
     case STBEM_DM0: {
         // whole time rows in chunks whose moment scratch stays below 1 GiB:
@@ -1898,34 +2059,91 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd, int pre
     return fail(c, STBEM_EINVAL, "unknown operator %u", op);
 }
 
-// y = A x for block-Toeplitz storage A_d = block (m + d, m): with X, Y the
-// N_Gamma x N_I column-major views of x, y (column m = time element m),
-//   Y[:, d:] += A_d X[:, :N_I-d]      (A^T: Y[:, :N_I-d] += A_d^T X[:, d:])
-// for d = 0, 1, ... in this order, one GEMM per lag; A_d is stored
-// row-major, i.e. as A_d^T in column-major terms.
+// y = A x (A^T x) for block-Toeplitz storage A_d = block (m + d, m): one
+// launch of k_toeplitz_mfma over the 64 x 64 tiles of Y.
 int toeplitz_apply(stbem_ctx* c, const double* A, int trans, const double* x, double* y, hipStream_t s)
 {
-    if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success) {
-        c->blas = nullptr;
-        return fail(c, STBEM_EHIP, "rocBLAS handle");
-    }
-    if (rocblas_set_stream(c->blas, s) != rocblas_status_success) return fail(c, STBEM_EHIP, "rocBLAS stream");
     const int ng = c->ng, nt = c->nt;
-    const double one = 1.0, zero = 0.0;
-    KTimer kt(c, trans ? "toeplitz_gemm_t<double>" : "toeplitz_gemm_n<double>", (double)causal_entries(c), s);
-    for (int d = 0; d < nt; ++d) {
-        const double* Ad = A + (long long)d * ng * ng;
-        const int cols = nt - d;
-        rocblas_status st;
-        if (!trans)
-            st = rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, ng, cols, ng, &one, Ad, ng,
-                               x, ng, d == 0 ? &zero : &one, y + (long long)d * ng, ng);
-        else
-            st = rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, ng, cols, ng, &one, Ad, ng,
-                               x + (long long)d * ng, ng, d == 0 ? &zero : &one, y, ng);
-        if (st != rocblas_status_success) return fail(c, STBEM_EHIP, "rocBLAS dgemm (lag %d): status %d", d, (int)st);
+    const int tr = (ng + kTT - 1) / kTT, tc = (nt + kTT - 1) / kTT;
+    const int ntile = tr * tc, grid = 8 * ((ntile + 7) / 8);
+    const bool vec = ng % 16 == 0 && ((uintptr_t)A % 32) == 0 && ((uintptr_t)x % 32) == 0;
+    KTimer kt(c, trans ? "k_toeplitz_mfma<1>" : "k_toeplitz_mfma<0>", (double)causal_entries(c), s);
+    if (!trans) {
+        if (vec) hipLaunchKernelGGL((k_toeplitz_mfma<0, true>), dim3(grid), dim3(kWG), 0, s, A, x, y, ng, nt, tr, tc);
+        else hipLaunchKernelGGL((k_toeplitz_mfma<0, false>), dim3(grid), dim3(kWG), 0, s, A, x, y, ng, nt, tr, tc);
+    } else {
+        if (vec) hipLaunchKernelGGL((k_toeplitz_mfma<1, true>), dim3(grid), dim3(kWG), 0, s, A, x, y, ng, nt, tr, tc);
+        else hipLaunchKernelGGL((k_toeplitz_mfma<1, false>), dim3(grid), dim3(kWG), 0, s, A, x, y, ng, nt, tr, tc);
     }
+    HIPCHK(c, hipGetLastError());
     return 0;
+}
+
+// Pass 1 of y = A x (A^T x) for packed causal storage (FP64, or hi+lo FP32
+// pair, or FP32): the partial vectors of the packed blocks [b0, b0 + nb)
+// into part[(b - b0) * ng + i].
+int gemv_partials(stbem_ctx* c, const double* A, const float* hi, const float* lo, const float* a32, int trans,
+                  const double* x, double* part, long long b0, long long nb, hipStream_t s)
+{
+    const int ng = c->ng;
+    // vector width: the row length must be a multiple of 64 * VW
+    const int vw64 = (ng % 128 == 0) ? 2 : 1;
+    const int vw32 = (ng % 256 == 0) ? 4 : (ng % 128 == 0 ? 2 : 1);
+    if (!trans) {
+        int rowchunks = (ng + 4 * kRowsPerWave - 1) / (4 * kRowsPerWave);
+        dim3 gr((unsigned)(nb * rowchunks)), bl(kWG);
+        if (A) {
+            if (vw64 == 2) hipLaunchKernelGGL((k_gemv_n_vec<double, 2, double, false>), gr, bl, 0, s, A, (const double*)nullptr, x, part, ng, rowchunks, b0);
+            else hipLaunchKernelGGL((k_gemv_n_vec<double, 1, double, false>), gr, bl, 0, s, A, (const double*)nullptr, x, part, ng, rowchunks, b0);
+        } else if (hi) {
+            if (vw32 == 4) hipLaunchKernelGGL((k_gemv_n_vec<float, 4, double, true>), gr, bl, 0, s, hi, lo, x, part, ng, rowchunks, b0);
+            else if (vw32 == 2) hipLaunchKernelGGL((k_gemv_n_vec<float, 2, double, true>), gr, bl, 0, s, hi, lo, x, part, ng, rowchunks, b0);
+            else hipLaunchKernelGGL((k_gemv_n_vec<float, 1, double, true>), gr, bl, 0, s, hi, lo, x, part, ng, rowchunks, b0);
+        } else {
+            if (vw32 == 4) hipLaunchKernelGGL((k_gemv_n_vec<float, 4, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, part, ng, rowchunks, b0);
+            else if (vw32 == 2) hipLaunchKernelGGL((k_gemv_n_vec<float, 2, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, part, ng, rowchunks, b0);
+            else hipLaunchKernelGGL((k_gemv_n_vec<float, 1, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, part, ng, rowchunks, b0);
+        }
+    } else {
+        if (A) {
+            int cc = (ng + 64 * vw64 - 1) / (64 * vw64);
+            dim3 gr((unsigned)(nb * cc)), bl(kWG);
+            if (vw64 == 2) hipLaunchKernelGGL((k_gemv_t_vec<double, 2, double, false>), gr, bl, 0, s, A, (const double*)nullptr, x, part, ng, cc, b0);
+            else hipLaunchKernelGGL((k_gemv_t_vec<double, 1, double, false>), gr, bl, 0, s, A, (const double*)nullptr, x, part, ng, cc, b0);
+        } else {
+            int cc = (ng + 64 * vw32 - 1) / (64 * vw32);
+            dim3 gr((unsigned)(nb * cc)), bl(kWG);
+            if (hi) {
+                if (vw32 == 4) hipLaunchKernelGGL((k_gemv_t_vec<float, 4, double, true>), gr, bl, 0, s, hi, lo, x, part, ng, cc, b0);
+                else if (vw32 == 2) hipLaunchKernelGGL((k_gemv_t_vec<float, 2, double, true>), gr, bl, 0, s, hi, lo, x, part, ng, cc, b0);
+                else hipLaunchKernelGGL((k_gemv_t_vec<float, 1, double, true>), gr, bl, 0, s, hi, lo, x, part, ng, cc, b0);
+            } else {
+                if (vw32 == 4) hipLaunchKernelGGL((k_gemv_t_vec<float, 4, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, part, ng, cc, b0);
+                else if (vw32 == 2) hipLaunchKernelGGL((k_gemv_t_vec<float, 2, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, part, ng, cc, b0);
+                else hipLaunchKernelGGL((k_gemv_t_vec<float, 1, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, part, ng, cc, b0);
+            }
+        }
+    }
+    HIPCHK(c, hipGetLastError());
+    return 0;
+}
+
+// Pass 2: the outputs of the block rows [k0, k1) (trans: the block columns
+// [0, k1), accumulated over row ranges) from their partials.
+int gemv_reduce(stbem_ctx* c, const double* part, double* y, int trans, int k0, int k1, hipStream_t s)
+{
+    const long long outs = (long long)(trans ? k1 : k1 - k0) * c->ng;
+    const long long pb0 = (long long)k0 * (k0 + 1) / 2;
+    hipLaunchKernelGGL(k_gemv_reduce, dim3((unsigned)((outs + kRedOut - 1) / kRedOut)), dim3(kWG), 0, s, part, y, c->ng,
+                       k0, k1, pb0, trans);
+    HIPCHK(c, hipGetLastError());
+    return 0;
+}
+
+const char* gemv_name(const double* A, const float* hi, int trans)
+{
+    return !trans ? (A ? "k_gemv_n_vec<double>" : hi ? "k_gemv_n_vec<float hi+lo>" : "k_gemv_n_vec<float>")
+                  : (A ? "k_gemv_t_vec<double>" : hi ? "k_gemv_t_vec<float hi+lo>" : "k_gemv_t_vec<float>");
 }
 
 // y = A x for packed causal storage (FP64, or hi+lo FP32 pair, or FP32)
@@ -1938,53 +2156,11 @@ int packed_apply(stbem_ctx* c, const double* A, const float* hi, const float* lo
     }
     int rc = ensure_part(c);
     if (rc) return rc;
-    const int ng = c->ng;
-    // vector width: the row length must be a multiple of 64 * VW
-    const int vw64 = (ng % 128 == 0) ? 2 : 1;
-    const int vw32 = (ng % 256 == 0) ? 4 : (ng % 128 == 0 ? 2 : 1);
-    const char* gname = !trans ? (A ? "k_gemv_n_vec<double>" : hi ? "k_gemv_n_vec<float hi+lo>" : "k_gemv_n_vec<float>")
-                               : (A ? "k_gemv_t_vec<double>" : hi ? "k_gemv_t_vec<float hi+lo>" : "k_gemv_t_vec<float>");
-    KTimer kt(c, gname, (double)c->nblk * ng * ng, s);
-    if (!trans) {
-        int rowchunks = (ng + 4 * kRowsPerWave - 1) / (4 * kRowsPerWave);
-        dim3 gr((unsigned)(c->nblk * rowchunks)), bl(kWG);
-        if (A) {
-            if (vw64 == 2) hipLaunchKernelGGL((k_gemv_n_vec<double, 2, double, false>), gr, bl, 0, s, A, (const double*)nullptr, x, c->part, ng, rowchunks);
-            else hipLaunchKernelGGL((k_gemv_n_vec<double, 1, double, false>), gr, bl, 0, s, A, (const double*)nullptr, x, c->part, ng, rowchunks);
-        } else if (hi) {
-            if (vw32 == 4) hipLaunchKernelGGL((k_gemv_n_vec<float, 4, double, true>), gr, bl, 0, s, hi, lo, x, c->part, ng, rowchunks);
-            else if (vw32 == 2) hipLaunchKernelGGL((k_gemv_n_vec<float, 2, double, true>), gr, bl, 0, s, hi, lo, x, c->part, ng, rowchunks);
-            else hipLaunchKernelGGL((k_gemv_n_vec<float, 1, double, true>), gr, bl, 0, s, hi, lo, x, c->part, ng, rowchunks);
-        } else {
-            if (vw32 == 4) hipLaunchKernelGGL((k_gemv_n_vec<float, 4, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, c->part, ng, rowchunks);
-            else if (vw32 == 2) hipLaunchKernelGGL((k_gemv_n_vec<float, 2, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, c->part, ng, rowchunks);
-            else hipLaunchKernelGGL((k_gemv_n_vec<float, 1, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, c->part, ng, rowchunks);
-        }
-    } else {
-        if (A) {
-            int cc = (ng + 64 * vw64 - 1) / (64 * vw64);
-            dim3 gr((unsigned)(c->nblk * cc)), bl(kWG);
-            if (vw64 == 2) hipLaunchKernelGGL((k_gemv_t_vec<double, 2, double, false>), gr, bl, 0, s, A, (const double*)nullptr, x, c->part, ng, cc);
-            else hipLaunchKernelGGL((k_gemv_t_vec<double, 1, double, false>), gr, bl, 0, s, A, (const double*)nullptr, x, c->part, ng, cc);
-        } else {
-            int cc = (ng + 64 * vw32 - 1) / (64 * vw32);
-            dim3 gr((unsigned)(c->nblk * cc)), bl(kWG);
-            if (hi) {
-                if (vw32 == 4) hipLaunchKernelGGL((k_gemv_t_vec<float, 4, double, true>), gr, bl, 0, s, hi, lo, x, c->part, ng, cc);
-                else if (vw32 == 2) hipLaunchKernelGGL((k_gemv_t_vec<float, 2, double, true>), gr, bl, 0, s, hi, lo, x, c->part, ng, cc);
-                else hipLaunchKernelGGL((k_gemv_t_vec<float, 1, double, true>), gr, bl, 0, s, hi, lo, x, c->part, ng, cc);
-            } else {
-                if (vw32 == 4) hipLaunchKernelGGL((k_gemv_t_vec<float, 4, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, c->part, ng, cc);
-                else if (vw32 == 2) hipLaunchKernelGGL((k_gemv_t_vec<float, 2, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, c->part, ng, cc);
-                else hipLaunchKernelGGL((k_gemv_t_vec<float, 1, float, false>), gr, bl, 0, s, a32, (const float*)nullptr, x, c->part, ng, cc);
-            }
-        }
+    {
+        KTimer kt(c, gemv_name(A, hi, trans), (double)c->nblk * c->ng * c->ng, s);
+        if ((rc = gemv_partials(c, A, hi, lo, a32, trans, x, c->part, 0, c->nblk, s))) return rc;
     }
-    HIPCHK(c, hipGetLastError());
-    kt.stop();
-    hipLaunchKernelGGL(k_gemv_reduce, dim3((unsigned)((c->n + kRedOut - 1) / kRedOut)), dim3(kWG), 0, s, c->part, y, c->ng, c->nt, trans);
-    HIPCHK(c, hipGetLastError());
-    return 0;
+    return gemv_reduce(c, c->part, y, trans, 0, c->nt, s);
 }
 
 int dense_apply(stbem_ctx* c, const double* M, int trans, const double* x, double* y, hipStream_t s)
@@ -2005,7 +2181,7 @@ int dense_apply(stbem_ctx* c, const double* M, int trans, const double* x, doubl
 // y = M_h^0 u0 without storing M_h^0 (for meshes where the N x M_Omega
 // matrix does not fit): chunks of rows are computed by the per-row moment
 // kernels, gathered into a chunk buffer and applied, in row order.
-int m0_fused_apply(stbem_ctx* c, const double* u0, double* y, hipStream_t s)
+int m0_fused_apply(stbem_ctx* c, const double* u0, double* y, hipStream_t s, bool deriv = false)
 {
     if (c->nv == 0) return fail(c, STBEM_EINVAL, "no Omega mesh for M0");
     const long long per_row = (long long)c->ntri * 3 * (long long)sizeof(double) + (long long)c->nv * sizeof(double);
@@ -2023,14 +2199,22 @@ int m0_fused_apply(stbem_ctx* c, const double* u0, double* y, hipStream_t s)
         const long long nr = std::min(rows, c->n - r0);
         const long long nf = r0 < c->ng ? std::min<long long>(nr, c->ng - r0) : 0, nl = nr - nf;
         if (nf > 0) {
-            KTimer kt(c, "k_m0_tri<false, true>", (double)nf * c->ntri, s);
-            hipLaunchKernelGGL((k_m0_tri<false, true>), dim3((unsigned)(nf * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab,
-                               c->d_m0tab, c->m0ord, m0poly(c), r0, 0LL, tchunk, scratch);
+            KTimer kt(c, deriv ? "k_m0_tri<true, true>" : "k_m0_tri<false, true>", (double)nf * c->ntri, s);
+            if (deriv)
+                hipLaunchKernelGGL((k_m0_tri<true, true>), dim3((unsigned)(nf * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab,
+                                   c->d_m0tab, c->m0ord, m0poly(c), r0, 0LL, tchunk, scratch);
+            else
+                hipLaunchKernelGGL((k_m0_tri<false, true>), dim3((unsigned)(nf * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab,
+                                   c->d_m0tab, c->m0ord, m0poly(c), r0, 0LL, tchunk, scratch);
         }
         if (nl > 0) {
-            KTimer kt(c, "k_m0_tri<false, false>", (double)nl * c->ntri, s);
-            hipLaunchKernelGGL((k_m0_tri<false, false>), dim3((unsigned)(nl * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab,
-                               c->d_m0tab, c->m0ord, m0poly(c), r0, nf, tchunk, scratch);
+            KTimer kt(c, deriv ? "k_m0_tri<true, false>" : "k_m0_tri<false, false>", (double)nl * c->ntri, s);
+            if (deriv)
+                hipLaunchKernelGGL((k_m0_tri<true, false>), dim3((unsigned)(nl * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab,
+                                   c->d_m0tab, c->m0ord, m0poly(c), r0, nf, tchunk, scratch);
+            else
+                hipLaunchKernelGGL((k_m0_tri<false, false>), dim3((unsigned)(nl * tchunk)), dim3(kWG), 0, s, geom(c), mesh(c), c->d_tab,
+                                   c->d_m0tab, c->m0ord, m0poly(c), r0, nf, tchunk, scratch);
         }
         hipLaunchKernelGGL(k_m0_gather, dim3((unsigned)(nr * vchunk)), dim3(kWG), 0, s, mesh(c), (const int*)c->d_v2t_loc, 0LL,
                            vchunk, (const double*)scratch, buf);
@@ -2040,6 +2224,94 @@ int m0_fused_apply(stbem_ctx* c, const double* u0, double* y, hipStream_t s)
     (void)hipStreamSynchronize(s);
     dev_free(c, scratch);
     dev_free(c, buf);
+    return rc;
+}
+
+// y = A x for A = dV_h/dalpha (slot 4) or dK_h/dalpha (slot 5) without
+// storing A: the block rows are assembled in ranges into a bounded buffer
+// (<= 1 GiB, at least one block row) by the same kernels as the stored
+// operator, and each range is contracted with x right away (the same two
+// GEMV passes); y's block rows [k0, k1) are final after their range.  The
+// block lists of the slot are swapped for the range's sub-lists (each list
+// group is in increasing k, so a range keeps the group structure).
+int deriv_apply_blockwise(stbem_ctx* c, int slot, const double* x, double* y, hipStream_t s)
+{
+    if (c->toep) return fail(c, STBEM_ENOTASSEMBLED, "alpha-derivative operators not assembled (block-Toeplitz mode)");
+    const long long ng2 = (long long)c->ng * c->ng;
+    long long cap = (1LL << 30) / (ng2 * (long long)sizeof(double));
+    if (cap < c->nt) cap = c->nt;
+    if (cap > c->nblk) cap = c->nblk;
+    int rc = ensure_part(c);
+    if (rc) return rc;
+    const std::vector<int>& all = c->h_blist[slot];
+    double* T = (double*)dev_alloc(c, (size_t)(cap * ng2 * (long long)sizeof(double)));
+    int* dl = (int*)dev_alloc(c, (all.empty() ? 1 : all.size()) * sizeof(int));
+    if (!T || !dl) {
+        dev_free(c, T); dev_free(c, dl);
+        return fail(c, STBEM_ENOMEM, "blockwise alpha-derivative buffers (%lld blocks)", cap);
+    }
+    // list groups: touch | gen | far Q = 3..8
+    int gsz[8] = {c->nlist_touch[slot], c->nlist_gen[slot]};
+    for (int q = 3; q <= 8; ++q) gsz[q - 1] = c->nlist_far[slot][q];
+    int* const save_list = c->d_blist[slot];
+    const int save_touch = c->nlist_touch[slot], save_gen = c->nlist_gen[slot];
+    int save_far[9];
+    for (int q = 0; q < 9; ++q) save_far[q] = c->nlist_far[slot][q];
+    std::vector<int> save_nterm = c->list_nterm[slot];
+    auto row_of = [](long long b) { long long k = (long long)((std::sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+                                    while (k * (k + 1) / 2 > b) --k;
+                                    while ((k + 1) * (k + 2) / 2 <= b) ++k;
+                                    return (int)k; };
+    for (int k0 = 0; k0 < c->nt && !rc; ) {
+        const long long pb0 = (long long)k0 * (k0 + 1) / 2;
+        int k1 = k0 + 1;
+        while (k1 < c->nt && (long long)(k1 + 1) * (k1 + 2) / 2 - pb0 <= cap) ++k1;
+        std::vector<int> sub, subn;
+        int cnt[8];
+        int at = 0;
+        for (int gi = 0; gi < 8; ++gi) {
+            cnt[gi] = 0;
+            for (int e = at; e < at + gsz[gi]; ++e) {
+                const int kb = row_of(all[e]);
+                if (kb >= k0 && kb < k1) { sub.push_back(all[e]); subn.push_back(save_nterm[e]); ++cnt[gi]; }
+            }
+            at += gsz[gi];
+        }
+        // the previous range's kernels must be done with dl and T
+        if (hipStreamSynchronize(s) != hipSuccess ||
+            (!sub.empty() && hipMemcpy(dl, sub.data(), sub.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)) {
+            rc = fail(c, STBEM_EHIP, "blockwise alpha-derivative list upload");
+            break;
+        }
+        c->d_blist[slot] = dl;
+        c->nlist_touch[slot] = cnt[0];
+        c->nlist_gen[slot] = cnt[1];
+        for (int q = 3; q <= 8; ++q) c->nlist_far[slot][q] = cnt[q - 1];
+        c->list_nterm[slot] = subn;
+        // block b of the range is written at T + (b - pb0) ng^2
+        double* Tb = (double*)((uintptr_t)T - (uintptr_t)(pb0 * ng2 * (long long)sizeof(double)));
+        const OutBuf o{Tb, nullptr, nullptr};
+        if (slot == 4) {
+            rc = launch_assemble<OP_DV>(c, o, s);
+            if (!rc) rc = launch_far<OP_DV>(c, 4, o, s);
+        } else {
+            launch_knear<OP_DK>(c, 5, Tb, s);
+            rc = launch_assemble<OP_DK>(c, o, s);
+            if (!rc) rc = launch_far<OP_DK>(c, 5, o, s);
+        }
+        const long long nb = (long long)k1 * (k1 + 1) / 2 - pb0;
+        if (!rc) rc = gemv_partials(c, Tb, nullptr, nullptr, nullptr, 0, x, c->part, pb0, nb, s);
+        if (!rc) rc = gemv_reduce(c, c->part, y, 0, k0, k1, s);
+        k0 = k1;
+    }
+    (void)hipStreamSynchronize(s);
+    c->d_blist[slot] = save_list;
+    c->nlist_touch[slot] = save_touch;
+    c->nlist_gen[slot] = save_gen;
+    for (int q = 0; q < 9; ++q) c->nlist_far[slot][q] = save_far[q];
+    c->list_nterm[slot] = save_nterm;
+    dev_free(c, T);
+    dev_free(c, dl);
     return rc;
 }
 
@@ -2245,7 +2517,6 @@ int stbem_destroy(stbem_ctx* c)
     for (void* p : own) if (p) (void)hipFree(p);
     for (int q = 0; q < 7; ++q) if (c->d_blist[q]) (void)hipFree(c->d_blist[q]);
     clear_timing(c);
-    if (c->blas) (void)rocblas_destroy_handle(c->blas);
     delete c;
     return STBEM_OK;
 }
@@ -2766,17 +3037,22 @@ int stbem_grad_alpha(stbem_ctx* c, const double* lam, const double* w, const dou
                      double* out, void* stream)
 {
     if (!c || !lam || !w || !g || !out) return STBEM_EINVAL;
-    if (!c->mat[4] || !c->mat[5] || (u0 && !c->mat[6])) return fail(c, STBEM_ENOTASSEMBLED, "alpha-derivative operators not assembled");
+    if (u0 && c->nv == 0) return fail(c, STBEM_EINVAL, "u0 given but no Omega mesh");
     hipStream_t s = S(stream);
     int rc = ensure_wvec(c, 2);
     if (rc || (rc = ensure_gmres(c, 1))) return rc;
     double* t = c->wvec;
-    // t = dK g - dV w - dM0 u0
-    if ((rc = packed_apply(c, c->mat[5], nullptr, nullptr, nullptr, 0, g, t, s))) return rc;
-    if ((rc = packed_apply(c, c->mat[4], nullptr, nullptr, nullptr, 0, w, t + c->n, s))) return rc;
+    // t = dK g - dV w - dM0 u0, each product from the stored matrix or, when
+    // it is not assembled, recomputed block row range by range
+    rc = c->mat[5] ? packed_apply(c, c->mat[5], nullptr, nullptr, nullptr, 0, g, t, s) : deriv_apply_blockwise(c, 5, g, t, s);
+    if (rc) return rc;
+    rc = c->mat[4] ? packed_apply(c, c->mat[4], nullptr, nullptr, nullptr, 0, w, t + c->n, s)
+                   : deriv_apply_blockwise(c, 4, w, t + c->n, s);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_axpby, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, -1.0, (const double*)(t + c->n), 1.0, t);
     if (u0) {
-        if ((rc = dense_apply(c, c->mat[6], 0, u0, t + c->n, s))) return rc;
+        rc = c->mat[6] ? dense_apply(c, c->mat[6], 0, u0, t + c->n, s) : m0_fused_apply(c, u0, t + c->n, s, true);
+        if (rc) return rc;
         hipLaunchKernelGGL(k_axpby, dim3(grid1(c->n)), dim3(kWG), 0, s, c->n, -1.0, (const double*)(t + c->n), 1.0, t);
     }
     DotWork dw;

@@ -90,3 +90,29 @@ def test_gradient_vs_central_differences_diff_workload():
         ga64 = ga if mode == L.FP64 else ga64
     print("FP32-refined vs FP64 dJ/dalpha rel diff", abs(ga - ga64) / abs(ga64))
     assert abs(ga - ga64) <= 1e-8 * abs(ga64)
+
+
+def test_grad_alpha_recomputed_blockwise_equals_stored():
+    """stbem_grad_alpha without the stored alpha-derivative matrices: dV_h w
+    and dK_h g recomputed in ranges of block rows (two ranges on the
+    differentiation workload's mesh, whose 8256 blocks of 128 x 128 exceed
+    the 1 GiB range buffer) and dM_h^0 u0 in row chunks; equal to the
+    contraction with the stored matrices to rounding."""
+    import torch
+    import paper_1811_05224_amd as P
+    from paper_1811_05224_amd import _lib as L
+    wl = W.make("diff")
+    c = P.Context.from_workload(wl)
+    rng = np.random.default_rng(5)
+    lam, w = (torch.as_tensor(rng.standard_normal(c.n), device=c.device) for _ in range(2))
+    g, u0 = torch.as_tensor(wl.g, device=c.device), torch.as_tensor(wl.u0, device=c.device)
+    c.assemble(L.DV | L.DK | L.DM0)
+    stored = float(c.grad_alpha(lam, w, g, u0).cpu()[0])
+    parts = [float(lam @ c.apply(L.DK, g)), float(lam @ c.apply(L.DV, w)), float(lam @ c.apply(L.DM0, u0))]
+    c.release(L.DV | L.DK | L.DM0)
+    torch.cuda.synchronize()
+    fused = float(c.grad_alpha(lam, w, g, u0).cpu()[0])
+    scale = sum(abs(p) for p in parts)
+    print("grad alpha stored", stored, "recomputed", fused, "difference / scale", abs(stored - fused) / scale)
+    assert abs(stored - fused) <= 1e-13 * scale
+    c.close()

@@ -1,7 +1,10 @@
 """The far-field tile kernels (separated time elements) against the
 per-entry kernel of the same library on meshes of 384 and 512 segments
 (both code paths run the same integrals; summation orders differ), all
-entries of every separated block."""
+entries of every separated block, for V_h, K_h, D_h and the
+alpha-derivatives dV_h, dK_h (whose tiles evaluate the derivative series
+dV ~ -(z/alpha) e^{-z} S1, dK ~ e^{-z} SD, while the per-entry kernel takes
+them from the same series through another route)."""
 import numpy as np
 import pytest
 
@@ -16,9 +19,9 @@ def test_far_tiles_match_per_entry_kernel(nside):
     from paper_1811_05224_amd import _lib as L
     wl = W.make("custom", n_side=nside, n_t=5, n_omega=2, alpha=1.0)
     c = P.Context.from_workload(wl)
-    c.assemble(L.V | L.K | L.D)
+    c.assemble(L.V | L.K | L.D | L.DV | L.DK)
     ng = c.ng
-    for code, name in ((L.V, "V"), (L.K, "K"), (L.D, "D")):
+    for code, name in ((L.V, "V"), (L.K, "K"), (L.D, "D"), (L.DV, "dV"), (L.DK, "dK")):
         Pm = c.packed(code).cpu().numpy()
         for (k, m) in [(2, 0), (4, 1), (4, 0)]:
             ii, jj = np.meshgrid(np.arange(ng), np.arange(ng), indexing="ij")

@@ -1,6 +1,11 @@
 """Block-Toeplitz storage for uniform time steps (stbem_set_toeplitz) and the
 right-hand side with M_h^0 computed in row chunks, on the GPU path.
 
+The products run in one hand-written kernel on the FP64 matrix cores
+(k_toeplitz_mfma); they are checked against the oracle's own block-Toeplitz
+blocks and products (test_products_vs_oracle), and the solve against the
+oracle's stored solution of the 128 x 128 mesh (tests/test_gpu_reference_solutions.py).
+
 With equal steps the block (k, m) depends on k - m only, so the N_I stored
 blocks (d, 0) must equal the packed blocks (d, 0) bit for bit (same kernels)
 and every other packed block (k, k - d) to rounding (the steps of a linspace
@@ -61,6 +66,34 @@ def test_products_rhs_and_solve(uniform):
     wt, info = c.solve(ft, tol=1e-13, max_it=300)
     assert info.status == 0
     assert float((wt - w).norm() / w.norm()) <= 1e-11
+
+
+@pytest.mark.parametrize("n_side,n_t", [(3, 70), (4, 40)])
+def test_products_vs_oracle(n_side, n_t):
+    """A x and A^T x of block-Toeplitz V_h and K_h against the oracle's
+    blocks (d, 0) and its Toeplitz product: 12 segments (scalar loads) over
+    70 steps (two column tiles, ragged), 16 segments (vector loads) over 40
+    steps.  Bar: 1e-12 of the product of the absolute values."""
+    import torch
+    import paper_1811_05224_amd as P
+    from paper_1811_05224_amd import _lib as L
+    from oracle.oracle import Oracle, toeplitz_apply
+    wl = W.make("custom", n_side=n_side, n_t=n_t, n_omega=2, alpha=0.9)
+    o = Oracle.from_workload(wl)
+    c = P.Context.from_workload(wl)
+    c.set_toeplitz(True)
+    c.assemble(L.V | L.K)
+    x = np.random.default_rng(4).standard_normal(c.n)
+    xt = torch.as_tensor(x, device=c.device)
+    for name, op in (("V", L.V), ("K", L.K)):
+        T = o.toeplitz_blocks(name)
+        for tr in (False, True):
+            print("Toeplitz product vs oracle", name, "trans", tr, "N", c.n, flush=True)
+            y = c.apply(op, xt, trans=tr).cpu().numpy()
+            ref = toeplitz_apply(T, x, o.nt, o.ng, trans=tr)
+            scale = toeplitz_apply(np.abs(T), np.abs(x), o.nt, o.ng, trans=tr)
+            assert np.all(np.abs(y - ref) <= 1e-12 * scale + 1e-300), (name, tr, np.max(np.abs(y - ref) / scale))
+    c.close()
 
 
 def test_refinement_refused_and_nonuniform_rejected(uniform):

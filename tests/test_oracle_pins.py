@@ -428,3 +428,23 @@ def test_neumann_datum_converges_for_manufactured_solution():
     print("flux errors", errs, "observed orders", eoc)
     assert errs[0] < 0.1
     assert np.all(eoc > 1.0), (errs, eoc)
+
+
+def test_toeplitz_mode_equals_packed():
+    """Uniform steps: the oracle's block-Toeplitz blocks (d, 0) reproduce the
+    packed lower block triangle, and its Toeplitz product and forward
+    substitution equal the packed ones (the reference solutions of larger
+    meshes are computed this way)."""
+    from oracle.oracle import toeplitz_apply, toeplitz_forward_solve, block_forward_solve
+    wl = W.make("custom", n_side=2, n_t=5, n_omega=2, alpha=0.8)
+    o = Oracle.from_workload(wl)
+    V = o.packed("V")
+    T = o.toeplitz_blocks("V")
+    for k in range(o.nt):
+        for m in range(k + 1):
+            B_ = V[packed_index(k, m)]
+            assert np.abs(B_ - T[k - m]).max() <= 1e-14 * np.abs(B_).max()
+    x = np.random.default_rng(1).standard_normal(o.n)
+    np.testing.assert_allclose(toeplitz_apply(T, x, o.nt, o.ng), packed_apply(V, x, o.nt, o.ng), rtol=1e-13, atol=1e-16)
+    np.testing.assert_allclose(toeplitz_forward_solve(T, x, o.nt, o.ng), block_forward_solve(V, x, o.nt, o.ng),
+                               rtol=1e-11)
