@@ -144,6 +144,27 @@ int stbem_matrix_f32(stbem_ctx* ctx, unsigned op, const float** hi_dev, const fl
  * entry once and adds partial sums in a fixed order (bitwise reproducible). */
 int stbem_apply(stbem_ctx* ctx, unsigned op, int trans, const double* x_dev, double* y_dev, void* stream);
 
+/* For callers that cannot allocate device memory (work under HIP stream or
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * y = A x (trans = 0) or A^T x (trans = 1) like stbem_apply, for the causal
+ * operators STBEM_V, STBEM_K, STBEM_D, STBEM_DV, STBEM_DK in packed storage
+ * (FP64, or the FP32 storage of V_h / D_h), with no device allocation or
+ * free and no host synchronisation.  The partial sums go to a fixed device
+ * buffer of STBEM_NOALLOC_SCRATCH_BYTES owned by the library: one per GPU,
+ * held from the first stbem_create on that GPU until the process ends.
+ * The block rows are processed in ranges whose partials fit that buffer;
+ * one block row must fit, so n_t * n_bnd <= STBEM_NOALLOC_SCRATCH_BYTES / 8
+ * (4194304), else STBEM_EINVAL.  trans = 0 gives bitwise the y of
+ * stbem_apply; trans = 1 too when all partials fit one range
+ * (n_t (n_t + 1) / 2 * n_bnd <= 4194304), otherwise the same sums added in
+ * another order.  STBEM_EINVAL for STBEM_M0 / STBEM_DM0 and in block-Toeplitz
+ * mode.  Every call on a GPU uses that GPU's one buffer, which keeps the last
+ * call's contents: calls that overlap in time on one GPU (other streams,
+ * other host threads, other contexts) race and give wrong results; calls
+ * ordered on one stream are safe.  x and y must not overlap. */
+#define STBEM_NOALLOC_SCRATCH_BYTES (32LL << 20)
+int stbem_apply_noalloc(stbem_ctx* ctx, unsigned op, int trans, const double* x_dev, double* y_dev, void* stream);
+
 /* M_h g for g in X_h^{1,0} (trans = 0) or M_h^T x (trans = 1). */
 int stbem_mass(stbem_ctx* ctx, int trans, const double* x_dev, double* y_dev, void* stream);
 

@@ -61,6 +61,7 @@ def load():
         "stbem_matrix": (ctypes.c_int, [vp, ctypes.c_uint, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]),
         "stbem_matrix_f32": (ctypes.c_int, [vp, ctypes.c_uint, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]),
         "stbem_apply": (ctypes.c_int, [vp, ctypes.c_uint, ctypes.c_int, vp, vp, vp]),
+        "stbem_apply_noalloc": (ctypes.c_int, [vp, ctypes.c_uint, ctypes.c_int, vp, vp, vp]),
         "stbem_mass": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
         "stbem_precondition": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
         "stbem_rhs": (ctypes.c_int, [vp, vp, vp, vp, vp]),
@@ -82,7 +83,7 @@ def load():
 
 
 EXPORTED = ["stbem_create", "stbem_destroy", "stbem_last_error", "stbem_set_allocator", "stbem_sizes",
-            "stbem_assemble", "stbem_release", "stbem_matrix", "stbem_matrix_f32", "stbem_apply", "stbem_mass",
+            "stbem_assemble", "stbem_release", "stbem_matrix", "stbem_matrix_f32", "stbem_apply", "stbem_apply_noalloc", "stbem_mass",
             "stbem_precondition", "stbem_rhs", "stbem_rhs_adjoint",
             "stbem_prepare_ir", "stbem_solve", "stbem_grad_alpha", "stbem_entries", "stbem_set_timing",
             "stbem_kernel_times", "stbem_set_toeplitz", "stbem_potential"]

@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1450,6 +1451,13 @@ __global__ __launch_bounds__(kWG) void k_split(long long n, const double* __rest
 }  // namespace
 
 // ============================================================ host side
+// Device buffer of stbem_apply_noalloc: the partial vectors of a range of
+// block rows.  One copy per GPU, held until the process ends; host code uses
+// its address from hipGetSymbolAddress (per device), never the symbol itself.
+constexpr long long kNoAllocDoubles = 1LL << 22;        // 32 MiB
+static __device__ __align__(256) double noalloc_scratch[kNoAllocDoubles];
+static_assert(kNoAllocDoubles * sizeof(double) == STBEM_NOALLOC_SCRATCH_BYTES, "scratch size and header disagree");
+
 struct stbem_ctx {
     int ng = 0, nt = 0, nv = 0, ntri = 0;
     long long n = 0, nblk = 0, packed = 0;
@@ -1486,6 +1494,7 @@ struct stbem_ctx {
     // work
     double* part = nullptr;     // nblk * ng
     size_t part_bytes = 0;
+    double* noalloc = nullptr;  // this device's noalloc_scratch (device address)
     double* wvec = nullptr;     // work vectors of N entries (right-hand side, preconditioner, solver)
     int wvec_count = 0;
     // GMRES workspace, kept between solves: Krylov basis (gm_cap + 1 vectors),
@@ -2326,6 +2335,29 @@ int dots(stbem_ctx* c, DotWork& w, const double* Q, long long ldq, int nq, const
     return 0;
 }
 
+// Device address of noalloc_scratch on the current device, looked up once
+// per device.
+constexpr int kMaxDevices = 64;
+std::mutex noalloc_mu;
+double* noalloc_ptr[kMaxDevices] = {};
+
+int noalloc_setup(stbem_ctx* c)
+{
+    int dev = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(c, STBEM_EHIP, "device %d beyond the table of %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        if (e != hipSuccess || !p)
+            return fail(c, STBEM_EHIP, "hipGetSymbolAddress(noalloc_scratch): %s", hipGetErrorString(e));
+        noalloc_ptr[dev] = (double*)p;
+    }
+    c->noalloc = noalloc_ptr[dev];
+    return 0;
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -2403,7 +2435,7 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
         (rc = upload(c, &c->d_ex, c->ex)) || (rc = upload(c, &c->d_ey, c->ey)) || (rc = upload(c, &c->d_len, c->len)) ||
         (rc = upload(c, &c->d_mt, mt)) || (rc = upload(c, &c->d_ox, c->ox)) || (rc = upload(c, &c->d_oy, c->oy)) ||
         (rc = upload(c, &c->d_tri, c->tri)) || (rc = upload(c, &c->d_v2t_ptr, c->v2t_ptr)) || (rc = upload(c, &c->d_v2t, c->v2t)) ||
-        (rc = upload(c, &c->d_v2t_loc, c->v2t_loc))) {
+        (rc = upload(c, &c->d_v2t_loc, c->v2t_loc)) || (rc = noalloc_setup(c))) {
         stbem_destroy(c);
         return rc;
     }
@@ -2708,6 +2740,41 @@ int stbem_apply(stbem_ctx* c, unsigned op, int trans, const double* x, double* y
     }
     if (op == STBEM_M0 || op == STBEM_DM0) return dense_apply(c, c->mat[slot], trans ? 1 : 0, x, y, S(stream));
     return packed_apply(c, c->mat[slot], nullptr, nullptr, nullptr, trans ? 1 : 0, x, y, S(stream));
+}
+
+int stbem_apply_noalloc(stbem_ctx* c, unsigned op, int trans, const double* x, double* y, void* stream)
+{
+    if (!c || !x || !y) return STBEM_EINVAL;
+    if (op == STBEM_M0 || op == STBEM_DM0) return fail(c, STBEM_EINVAL, "stbem_apply_noalloc: causal operators only");
+    int slot = op_slot(op);
+    if (slot < 0) return fail(c, STBEM_EINVAL, "unknown operator %u", op);
+    if (c->toep) return fail(c, STBEM_EINVAL, "stbem_apply_noalloc: packed storage only (not block-Toeplitz mode)");
+    if (!c->noalloc) return fail(c, STBEM_EHIP, "stbem_apply_noalloc: no scratch address for this context");
+    const double* A = c->mat[slot];
+    const float *hi = nullptr, *lo = nullptr, *a32 = nullptr;
+    if (!A) {
+        if (op == STBEM_V && c->v_hi && c->v_lo) { hi = c->v_hi; lo = c->v_lo; }
+        else if (op == STBEM_D && c->d_32) a32 = c->d_32;
+        else return fail(c, STBEM_ENOTASSEMBLED, "operator %u not assembled", op);
+    }
+    const long long ng = c->ng;
+    if ((long long)c->nt * ng > kNoAllocDoubles)
+        return fail(c, STBEM_EINVAL, "stbem_apply_noalloc: one block row needs %lld partials, the scratch holds %lld",
+                    (long long)c->nt * ng, kNoAllocDoubles);
+    hipStream_t s = S(stream);
+    int k0 = 0;
+    while (k0 < c->nt) {
+        // the most block rows whose partials fit the scratch
+        int k1 = k0 + 1;
+        const long long pb0 = (long long)k0 * (k0 + 1) / 2;
+        while (k1 < c->nt && ((long long)(k1 + 1) * (k1 + 2) / 2 - pb0) * ng <= kNoAllocDoubles) ++k1;
+        const long long nb = (long long)k1 * (k1 + 1) / 2 - pb0;
+        int rc = gemv_partials(c, A, hi, lo, a32, trans ? 1 : 0, x, c->noalloc, pb0, nb, s);
+        if (!rc) rc = gemv_reduce(c, c->noalloc, y, trans ? 1 : 0, k0, k1, s);
+        if (rc) return rc;
+        k0 = k1;
+    }
+    return STBEM_OK;
 }
 
 int stbem_mass(stbem_ctx* c, int trans, const double* x, double* y, void* stream)
