@@ -122,6 +122,64 @@ __global__ __launch_bounds__(kWG) void k_time_blocks(Geom g, long long nb, TimeB
     time_block(g, k, m, out[b]);
 }
 
+// The series data of separated time blocks for FP32 arithmetic (D_h's
+// far field in the FP32-storage mode): the same coefficients as the FP64
+// table (see TimeBlock), computed in FP64, truncated where p^(2n+2) < 1e-9
+// (ample for FP32 sums; the FP64 table runs to 1e-19) and stored as float.
+// nterm = 0 for blocks that are not series blocks.
+constexpr double kSeriesTol32 = 1e-9;
+struct TimeBlock32 {
+    int nterm;
+    float inv_dc;
+    float pad[2];
+    float st[kMaxTerms][12];
+};
+
+__global__ __launch_bounds__(kWG) void k_time_blocks32(Geom g, long long nb, TimeBlock32* __restrict__ out)
+{
+    const long long b = (long long)blockIdx.x * kWG + threadIdx.x;
+    if (b >= nb) return;
+    int k, m;
+    block_of(b, k, m);
+    TimeBlock32& tb = out[b];
+    tb.nterm = 0;
+    if (k - m < 2) return;
+    const double hk = g.t[k + 1] - g.t[k], hm = g.t[m + 1] - g.t[m];
+    const double A = 0.5 * hk, B = 0.5 * hm;
+    const double dc = 0.5 * (g.t[k] + g.t[k + 1]) - 0.5 * (g.t[m] + g.t[m + 1]);
+    const double p = (A + B) / dc, q = (A - B) / dc;
+    if (p > 0.62) return;
+    tb.inv_dc = (float)(1.0 / dc);
+    const double p2 = p * p, q2 = q * q;
+    int n = 0;
+    for (double pp = p2; n < kMaxTerms; ++n) {
+        if (n > 0 && pp < kSeriesTol32) { ++n; break; }
+        pp *= p2;
+    }
+    tb.nterm = n;
+    // tail sums kc, hc over the kept terms, as in time_block
+    double kc = 0.0, hc = 0.0;
+    for (int e = n - 1; e >= 0; --e) {
+        const double cn = 2.0 * dc * dc * (pow(p2, e + 1) - pow(q2, e + 1)) / ((2.0 * e + 1.0) * (2.0 * e + 2.0));
+        const double kc1 = e + 1 < n ? kc : 0.0;
+        hc += kc1;
+        const double hc1 = e + 1 < n ? hc : 0.0;
+        kc += cn;
+        hc += kc;
+        float* st = tb.st[e];
+        st[6] = (float)kc; st[7] = (float)kc1; st[8] = (float)hc; st[9] = (float)hc1;
+        st[10] = (float)((2.0 * e + 1.0) * cn);
+        st[11] = (float)cn;
+        for (int h = 0; h < 2; ++h) {
+            const int j = 2 * e - 1 + h;
+            const double bb = j >= 0 ? 1.0 / (j + 1.0) : 0.0;
+            st[3 * h] = (float)((2.0 * j + 1.0) * bb);
+            st[3 * h + 1] = (float)bb;
+            st[3 * h + 2] = (float)(j * bb);
+        }
+    }
+}
+
 template <int OP>
 __global__ __launch_bounds__(kWG) void k_assemble(Geom g, const Tables* __restrict__ Tg, Orders O,
                                                   double lmax, const int* __restrict__ blist, int tiles_1d,
@@ -495,6 +553,132 @@ __global__ __launch_bounds__(kWG, (Q == 3 || (Q == 4 && !WV)) ? 3 : 1) void k_as
         __syncthreads();          // the stage is reused
         store_tile(stage, true, own ? vsum : 0.0, live, boff, g.ng, I0, J0, il, jl, outv);
     }
+}
+
+// D_h's far field in FP32 arithmetic (FP32-storage mode): the raw
+// hypersingular kernel of far_dpair with the float series (TimeBlock32),
+// node offsets formed from the pieces' start points in FP64 and rounded
+// once, float moments and sums.  D_h only shapes the preconditioner.
+constexpr float kInv4PiF = 0.0795774715459476679f;
+template <int Q>
+__device__ __forceinline__ void far_dpair32(const Tables& T, const TimeBlock32& tb, double al,
+                                            const double* P, const double* Qs, float* mom)
+{
+    const float alf = (float)al;
+    const float cn = (float)(al * (P[5] * Qs[5] + P[6] * Qs[6]));
+    const float pex = (float)P[2], pey = (float)P[3], qex = (float)Qs[2], qey = (float)Qs[3];
+    const float LP = (float)P[4], LQ = (float)Qs[4];
+    const float tt = pex * qex + pey * qey;
+    const float i1 = tb.inv_dc, i2 = i1 * i1, zf = 0.25f * alf * i1;
+    const float fd = -cn * i2 * kInv4PiF, fk = 0.5f * alf * tt * i2 * kInv4PiF, fh = -0.25f * alf * alf * i2 * i1 * kInv4PiF;
+    const float dx0 = (float)(P[0] - Qs[0]), dy0 = (float)(P[1] - Qs[1]);
+    float m00 = 0.f, m01 = 0.f, m10 = 0.f, m11 = 0.f;
+#pragma unroll 1
+    for (int a = 0; a < Q; ++a) {
+        const float xa = (float)T.gl_x[Q][a];
+        const float sP = LP * xa, wP = LP * (float)T.gl_w[Q][a];
+        const float bx = fmaf(sP, pex, dx0), by = fmaf(sP, pey, dy0);
+        float z[Q], l0[Q], l1[Q], sd[Q], sk[Q], s2[Q], zt[Q];
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            const float sQ = LQ * (float)T.gl_x[Q][c];
+            const float dx = fmaf(-sQ, qex, bx), dy = fmaf(-sQ, qey, by);
+            z[c] = zf * fmaf(dx, dx, dy * dy);
+            zt[c] = fh * (fmaf(dx, pex, dy * pey) * fmaf(dx, qex, dy * qey));
+            l0[c] = 1.f; l1[c] = 1.f - z[c];
+            const float* s0 = tb.st[0];
+            sd[c] = s0[10] * l1[c]; sk[c] = fmaf(s0[7], l1[c], s0[6]); s2[c] = fmaf(s0[9], l1[c], s0[8]);
+        }
+        for (int n = 1; n < tb.nterm; ++n) {
+            const float* st = tb.st[n];
+#pragma unroll
+            for (int c = 0; c < Q; ++c) {
+                const float x2 = fmaf(fmaf(-st[1], z[c], st[0]), l1[c], -st[2] * l0[c]);
+                const float x3 = fmaf(fmaf(-st[4], z[c], st[3]), x2, -st[5] * l1[c]);
+                sk[c] = fmaf(st[7], x3, fmaf(st[6], x2, sk[c]));
+                s2[c] = fmaf(st[9], x3, fmaf(st[8], x2, s2[c]));
+                sd[c] = fmaf(st[10], x3, sd[c]);
+                l0[c] = x2; l1[c] = x3;
+            }
+        }
+        float r0 = 0.f, r1s = 0.f;
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            const float e = expf(-z[c]);
+            const float kap = e * fmaf(zt[c], s2[c], fmaf(fk, sk[c], fd * sd[c]));
+            const float xc = (float)T.gl_x[Q][c], w = LQ * (float)T.gl_w[Q][c] * kap;
+            r0 = fmaf(w, 1.f - xc, r0);
+            r1s = fmaf(w, xc, r1s);
+        }
+        m00 = fmaf(wP * (1.f - xa), r0, m00); m01 = fmaf(wP * (1.f - xa), r1s, m01);
+        m10 = fmaf(wP * xa, r0, m10);         m11 = fmaf(wP * xa, r1s, m11);
+    }
+    mom[0] = m00; mom[1] = m01; mom[2] = m10; mom[3] = m11;
+}
+
+template <int Q>
+__global__ __launch_bounds__(kWG) void k_assemble_dfar32(Geom g, const Tables* __restrict__ Tg,
+                                                         const int* __restrict__ blist, int tiles_1d,
+                                                         OutBuf out, const TimeBlock32* __restrict__ tbs)
+{
+    __shared__ float mom[kDP][kDP][4];
+    __shared__ double pc[2][kDP][7];       // ax ay ex ey len nx ny
+    __shared__ double stage[kTile][kTile + 1];
+    const Tables& T = *Tg;
+    const int tid = threadIdx.x;
+    const long long tiles = (long long)tiles_1d * (tiles_1d + 1) / 2;
+    const long long b = blist[blockIdx.x / tiles];
+    int ti, tj;
+    tile_of((int)(blockIdx.x % tiles), tiles_1d, true, ti, tj);
+    int k, m;
+    block_of(b, k, m);
+    const TimeBlock32& tb = tbs[b];
+    const int I0 = ti * kTile, J0 = tj * kTile;
+    const int np = 2 * g.ng;
+    if (tid < 2 * kDP) {
+        int side = tid / kDP, u = tid % kDP;
+        int base = side ? J0 : I0;
+        int h = ((2 * base - 1 + u) % np + np) % np;
+        Piece P = half_piece(g, h);
+        double* q = pc[side][u];
+        q[0] = P.ax; q[1] = P.ay; q[2] = P.ex; q[3] = P.ey; q[4] = P.len; q[5] = P.nx; q[6] = P.ny;
+    }
+    __syncthreads();
+    // the same pair assignment as k_assemble_dfar: lane (il, jl) takes the
+    // 2 x 2 pairs of pieces 2il+1, 2il+2 and 2jl+1, 2jl+2, then lanes
+    // 0..131 one pair each on the border of the piece range
+    const int il = tid / kTile, jl = tid % kTile, i = I0 + il, j = J0 + jl;
+#pragma unroll 1
+    for (int e = 0; e < 4; ++e) {
+        const int u = 2 * il + 1 + (e >> 1), v = 2 * jl + 1 + (e & 1);
+        far_dpair32<Q>(T, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v]);
+    }
+    if (tid < 4 * kDP - 4) {
+        int u, v;
+        if (tid < kDP) { u = 0; v = tid; }
+        else if (tid < 2 * kDP) { u = kDP - 1; v = tid - kDP; }
+        else if (tid < 3 * kDP - 2) { u = tid - 2 * kDP + 1; v = 0; }
+        else { u = tid - (3 * kDP - 2) + 1; v = kDP - 1; }
+        far_dpair32<Q>(T, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v]);
+    }
+    __syncthreads();
+    const bool live = i < g.ng && j < g.ng, own = live && !mirrored(true, I0, J0, il, jl);
+    float acc = 0.f;
+    if (own) {
+        DualSupport si = dual_support(g, i), sj = dual_support(g, j);
+        const int ui = 2 * il, vj = 2 * jl;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float a0 = (float)si.v0[u], a1 = (float)(si.v0[u] + si.slope[u] * pc[0][ui + u][4]);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float b0 = (float)sj.v0[v], b1 = (float)(sj.v0[v] + sj.slope[v] * pc[1][vj + v][4]);
+                const float* M = mom[ui + u][vj + v];
+                acc += a0 * fmaf(b0, M[0], b1 * M[1]) + a1 * fmaf(b0, M[2], b1 * M[3]);
+            }
+        }
+    }
+    store_tile(stage, true, (double)acc, live, block_slot(g, b, k, m) * g.ng * g.ng, g.ng, I0, J0, il, jl, out);
 }
 
 // D_h on touching time elements (d <= 1, closed form in time): one workgroup
@@ -1473,6 +1657,7 @@ struct stbem_ctx {
     int *d_tri = nullptr, *d_v2t_ptr = nullptr, *d_v2t = nullptr;
     Tables* d_tab = nullptr;
     TimeBlock* d_tbs = nullptr;         // the time data of every causal block, by packed index
+    TimeBlock32* d_tbs32 = nullptr;     // float series data (FP32-storage mode), built on first use
     M0Tables* d_m0tab = nullptr;
     Orders ord;
     M0Orders m0ord;
@@ -1939,6 +2124,44 @@ int prepare_storage(stbem_ctx* c, unsigned op, int prec)
     return 0;
 }
 
+// D_h's separated blocks in FP32 arithmetic into FP32 storage (the float
+// series table is built on first use)
+int launch_dfar32(stbem_ctx* c, const int* bl, OutBuf od, hipStream_t s)
+{
+    if (!c->d_tbs32) {
+        if (hipMalloc((void**)&c->d_tbs32, (size_t)c->nblk * sizeof(TimeBlock32)) != hipSuccess) {
+            (void)hipGetLastError();
+            c->d_tbs32 = nullptr;
+            return fail(c, STBEM_ENOMEM, "float series table (%zu bytes)", (size_t)c->nblk * sizeof(TimeBlock32));
+        }
+        hipLaunchKernelGGL(k_time_blocks32, dim3((unsigned)((c->nblk + kWG - 1) / kWG)), dim3(kWG), 0, s, geom(c), c->nblk,
+                           c->d_tbs32);
+        HIPCHK(c, hipGetLastError());
+    }
+    const int t1 = (c->ng + kTile - 1) / kTile;
+    const long long tiles = tiles_per_block(t1, true);
+    const int step = blocks_per_launch(tiles);
+    for (int q = 3; q <= 8; ++q) {
+        for (int off = 0; off < c->nlist_far[2][q]; off += step) {
+            const int n = std::min(step, c->nlist_far[2][q] - off);
+            dim3 gr((unsigned)(n * tiles)), blk(kWG);
+            const int* b2 = bl + off;
+            KTimer kt(c, (std::string("k_assemble_dfar32<") + std::to_string(q) + ">").c_str(), (double)n * c->ng * c->ng, s);
+            switch (q) {
+            case 3: hipLaunchKernelGGL((k_assemble_dfar32<3>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
+            case 4: hipLaunchKernelGGL((k_assemble_dfar32<4>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
+            case 5: hipLaunchKernelGGL((k_assemble_dfar32<5>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
+            case 6: hipLaunchKernelGGL((k_assemble_dfar32<6>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
+            case 7: hipLaunchKernelGGL((k_assemble_dfar32<7>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
+            default: hipLaunchKernelGGL((k_assemble_dfar32<8>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
+            }
+        }
+        bl += c->nlist_far[2][q];
+    }
+    HIPCHK(c, hipGetLastError());
+    return 0;
+}
+
 int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd, int prec)
 {
     int slot = op_slot(op);
@@ -1953,7 +2176,10 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd, int pre
         // V_h with D_h: its touching and separated blocks come with D_h's tiles
         int rc = op == STBEM_V ? launch_assemble<OP_V>(c, ob, s, !fuse_vd) : launch_assemble<OP_K>(c, ob, s);
         if (rc) return rc;
-        if (op == STBEM_V && fuse_vd) return 0;
+        // fused with D_h in FP64; in the FP32-storage mode D_h's far field is
+        // computed in FP32 by its own tiles, V_h's (which the refinement
+        // residual needs to FP64 accuracy) by the FP64 far tiles
+        if (op == STBEM_V && fuse_vd && prec != STBEM_FP32_IR) return 0;
         return op == STBEM_V ? launch_far<OP_V>(c, 0, ob, s) : launch_far<OP_K>(c, 1, ob, s);
     }
     case STBEM_D: {
@@ -1976,6 +2202,7 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd, int pre
         if (rc) return rc;
         const int* bl = c->d_blist[2] + c->nlist_touch[2] + c->nlist_gen[2];
         const OutBuf none{nullptr, nullptr, nullptr};
+        if (prec == STBEM_FP32_IR) return launch_dfar32(c, bl, od, s);
         for (int q = 3; q <= 8; ++q) {
             for (int off = 0; off < c->nlist_far[2][q]; off += step) {
                 const int n = std::min(step, c->nlist_far[2][q] - off);
@@ -2544,7 +2771,7 @@ int stbem_destroy(stbem_ctx* c)
     for (int s = 0; s < 7; ++s) dev_free(c, c->mat[s]);
     free_f32(c, true, true);
     void* own[] = {c->d_t, c->d_vx, c->d_vy, c->d_ex, c->d_ey, c->d_len, c->d_ox, c->d_oy, c->d_mt, c->d_m0c, c->d_m0cd, c->d_m0n, c->d_m0amax, c->d_v2t_loc,
-                   c->d_tri, c->d_v2t_ptr, c->d_v2t, c->d_tab, c->d_m0tab, c->part, c->d_tbs, c->wvec,
+                   c->d_tri, c->d_v2t_ptr, c->d_v2t, c->d_tab, c->d_m0tab, c->part, c->d_tbs, c->d_tbs32, c->wvec,
                    c->gm_q, c->gm_part, c->gm_h, c->gm_v};
     for (void* p : own) if (p) (void)hipFree(p);
     for (int q = 0; q < 7; ++q) if (c->d_blist[q]) (void)hipFree(c->d_blist[q]);

@@ -2,8 +2,11 @@
 
 Assembled with precision STBEM_FP32_IR, V_h is stored as the float pair
 hi = fl32(V), lo = fl32(V - hi) and D_h as float; no FP64 copy of either is
-kept.  The pair must reproduce the oracle's V_h to the FP64 bar (it carries
-about 48 bits), D_h to FP32 rounding, and the refinement solve with only this
+kept.  V_h is computed in FP64 everywhere; D_h in FP64 on touching time
+blocks and in FP32 arithmetic (float Laguerre series) on separated ones.  The
+pair must reproduce the oracle's V_h to the FP64 bar (it carries about 48
+bits), D_h's touching blocks to FP32 rounding and its separated blocks to
+1e-5 of the block maximum, and the refinement solve with only this
 storage must reach the oracle's solution within 1e-10.  Assembling V_h or D_h
 again in FP64 drops FP32 copies made from the old FP64 storage.
 """
@@ -43,11 +46,20 @@ def test_fp32_storage_entries(small_ir):
     e_hi = block_err(hi.double().cpu().numpy(), V).max()
     d32, dlo = c.packed_f32(L.D)
     assert dlo is None
-    e_d = block_err(d32.double().cpu().numpy(), D).max()
-    print("V hi+lo", e_pair, "V hi", e_hi, "D fp32", e_d)
+    d32 = d32.double().cpu().numpy()
+    # touching time blocks (k - m <= 1) are computed in FP64 and rounded once;
+    # separated blocks in FP32 arithmetic (float series), checked against the
+    # block's largest entry: the preconditioner needs normwise accuracy only
+    near = np.array([k - m <= 1 for k in range(c.nt) for m in range(k + 1)])
+    e_d_near = block_err(d32[near], D[near]).max()
+    dmax = np.abs(D[~near]).reshape((~near).sum(), -1).max(axis=1)[:, None, None]
+    e_d_far = (np.abs(d32[~near] - D[~near]) / dmax).max()
+    print("V hi+lo", e_pair, "V hi", e_hi, "D touching (FP64, stored FP32)", e_d_near,
+          "D separated (FP32 arithmetic), relative to the block maximum", e_d_far)
     assert e_pair <= 1e-12
     assert e_hi <= 1e-7
-    assert e_d <= 2e-6
+    assert e_d_near <= 2e-6
+    assert e_d_far <= 1e-5
     # stored blocks stay exactly symmetric
     h = hi.cpu().numpy()
     assert np.array_equal(h, np.transpose(h, (0, 2, 1)))
