@@ -1,14 +1,14 @@
 """Benchmark of the space-time BEM hot path on one MI355X.
 
 One step = the forward path of the method on one synthetic workload, in
-three phases that keep the resident matrices within the GPU's memory:
-  1. assemble K_h and M_h^0 (FP64), form the right-hand side of eq.(4),
-     release them;
-  2. assemble V_h and D_h in FP64, solve with D_h-preconditioned GMRES,
-     release them;
-  3. assemble V_h and D_h into FP32 storage (V_h as an FP32 hi + lo pair,
-     D_h as FP32; no FP64 copy), solve by FP64 iterative refinement around
-     FP32 inner GMRES.
+two phases that keep the resident matrices within the GPU's memory:
+  1. assemble V_h, K_h, D_h and M_h^0 in FP64 in one call (V_h's and K_h's
+     separated blocks come from D_h's far tiles), form the right-hand side of
+     eq.(4), release K_h and M_h^0, solve with D_h-preconditioned GMRES,
+     release V_h and D_h;
+  2. assemble V_h and D_h into FP32 storage (V_h as an FP32 hi + lo pair
+     computed in FP64, D_h in FP32 arithmetic on separated time blocks; no
+     FP64 copy), solve by FP64 iterative refinement around FP32 inner GMRES.
 Inputs are resident in HBM before the timed region.  Prints one JSON line.
 
 Default workload (the precision configuration, the largest that fits one
@@ -43,11 +43,9 @@ FP32_PEAK_TFLOPS = 157.3
 # kernel changed after its counters were taken has no entry here.
 HBM_BYTES_PER_UNIT = {
     # precision workload, profiles/dfar_q3_precision_counters.md: FETCH_SIZE
-    # 175,779 KiB (x 2) and WRITE_SIZE 128,512,000 KiB per dispatch of
-    # 8.2248e9 D entries (the D and the V entry written, FP64); the FP32-store
-    # launches write 96,384,000 KiB (V as hi + lo, D as FP32)
-    "k_assemble_dfar<3, true>": 16.04,
-    "k_assemble_dfar<3, true> f32-store": 12.04,
+    # 178,280 KiB (x 2) and WRITE_SIZE 199,177,840 KiB per dispatch of
+    # 8.2248e9 D entries (the D, V and K entries written, FP64)
+    "k_assemble_dfar<3, true, true>": 24.84,
 }
 # bytes streamed per stored entry by the matrix-vector kernels
 GEMV_BYTES = {"k_gemv_n_vec<double>": 8, "k_gemv_t_vec<double>": 8, "k_gemv_n_vec<float hi+lo>": 8,
@@ -101,27 +99,25 @@ def main():
     u0 = torch.as_tensor(wl.u0, device=dev)
     stream = torch.cuda.current_stream()
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    phases = ("K+M0", "rhs", "V+D fp64", "solve fp64", "V+D fp32", "solve fp32-refined")
+    phases = ("V+K+D+M0 fp64", "rhs", "solve fp64", "V+D fp32", "solve fp32-refined")
 
     def step(record):
         e = [ev() for _ in range(len(phases) + 1)]
         e[0].record(stream)
-        ctx.assemble(L.K | L.M0)
+        # V_h's and K_h's separated blocks come from D_h's far tiles (one call)
+        ctx.assemble(L.V | L.K | L.D | L.M0)
         e[1].record(stream)
         f = ctx.rhs(g, u0)
         e[2].record(stream)
         ctx.release(L.K | L.M0)
-        # V_h's separated and touching blocks come from D_h's tiles (one call)
-        ctx.assemble(L.V | L.D)
-        e[3].record(stream)
         w64, i64 = ctx.solve(f, tol=args.tol, max_it=400)
-        e[4].record(stream)
+        e[3].record(stream)
         ctx.release(L.V | L.D)
         ctx.assemble(L.V | L.D, precision=L.FP32_IR)
-        e[5].record(stream)
+        e[4].record(stream)
         w32, i32 = ctx.solve(f, tol=args.ir_tol, max_it=400, mode=L.FP32_IR, inner_tol=args.inner_tol, max_outer=12,
                              ir_tol=args.ir_tol)
-        e[6].record(stream)
+        e[5].record(stream)
         torch.cuda.synchronize()
         ctx.release(L.V | L.D)
         if record is not None:
@@ -156,18 +152,17 @@ def main():
         "config": {"workload": f"{args.workload}: N_Gamma={ctx.ng}, N_I={ctx.nt}, N={ctx.n}, M_Omega={ctx.nv}, "
                                f"alpha={wl.alpha}, entries per causal matrix={entries}"},
         "phase_ms": avg,
-        "assembly_entries_per_s": {"V+D fp64": 2 * entries / (avg["V+D fp64"] * 1e-3),
-                                   "V+D fp32 storage": 2 * entries / (avg["V+D fp32"] * 1e-3),
-                                   "K+M0": entries / (avg["K+M0"] * 1e-3)},
+        "assembly_entries_per_s": {"V+K+D fp64 (M0 in the same call)": 3 * entries / (avg["V+K+D+M0 fp64"] * 1e-3),
+                                   "V+D fp32 storage": 2 * entries / (avg["V+D fp32"] * 1e-3)},
         "solve_s_fp64": avg["solve fp64"] * 1e-3, "solve_s_fp32_refined": avg["solve fp32-refined"] * 1e-3,
-        "path_s_fp64": (avg["V+D fp64"] + avg["solve fp64"]) * 1e-3,
-        "path_s_fp32_refined": (avg["V+D fp32"] + avg["solve fp32-refined"]) * 1e-3,
+        "solve_speedup_fp32_refined": avg["solve fp64"] / avg["solve fp32-refined"],
         "gmres_iters_fp64": last64.iters, "gmres_iters_fp32_inner_total": last32.iters,
         "ir_outer_steps": last32.outer,
         "true_relres_fp64": last64.true_relres, "true_relres_fp32_refined": last32.true_relres,
         "solve_tol": {"fp64_precond_relres": args.tol, "fp32_refined_fp64_relres": args.ir_tol,
                       "fp32_inner": args.inner_tol},
-        "storage_GB": {"V+D fp64": 2 * entries * 8 / 1e9, "V+D fp32 (V hi+lo, D fp32)": entries * 12 / 1e9},
+        "storage_GB": {"V+K+D fp64": 3 * entries * 8 / 1e9, "M0 fp64": ctx.n * ctx.nv * 8 / 1e9,
+                       "V+D fp32 (V hi+lo, D fp32)": entries * 12 / 1e9},
     }
     out["gemv"] = gemv_rates(ktimes)
     out["roofline"] = roofline(ktimes)

@@ -417,9 +417,16 @@ constexpr int kDP = 2 * kTile + 2;     // pieces per tile side
 
 // four shape moments of the raw hypersingular kernel for one piece pair,
 // Q x Q Gauss nodes, the Q series of a row of nodes advanced together
-template <int Q, bool WV>
+// WK: also the moments of K_h's kernel (x-y).n alpha e^{-z} S1 / (8 pi dc^2)
+// (S1 = sum c_n L^(1)_2n, the sum the Hessian term already needs) in both
+// orientations of the pair: kmom[0..1] = int int (x - y).n_Q G (1 - fy, fy)
+// with fy the position of y along its whole segment (the piece is half hq of
+// it), kmom[2..3] = int int (y - x).n_P G (1 - fx, fx) (half hp).  Unscaled:
+// the caller multiplies by alpha / (8 pi dc^2).
+template <int Q, bool WV, bool WK = false>
 __device__ __forceinline__ void far_dpair(const Tables& T, const TimeBlock& tb, double al,
-                                          const double* P, const double* Qs, double* mom, double* vmom)
+                                          const double* P, const double* Qs, double* mom, double* vmom,
+                                          double* kmom = nullptr, int hp = 0, int hq = 0)
 {
     const double cn = al * (P[5] * Qs[5] + P[6] * Qs[6]);
     const double tt = P[2] * Qs[2] + P[3] * Qs[3];
@@ -427,18 +434,20 @@ __device__ __forceinline__ void far_dpair(const Tables& T, const TimeBlock& tb, 
     const double i1 = tb.inv_dc, i2 = i1 * i1, zf = 0.25 * al * i1;
     const double fd = -cn * i2 * kInv4Pi, fk = 0.5 * al * tt * i2 * kInv4Pi, fh = -0.25 * al * al * i2 * i1 * kInv4Pi;
     double m00 = 0, m01 = 0, m10 = 0, m11 = 0, mv = 0;
+    double ka0 = 0, ka1 = 0, kb0 = 0, kb1 = 0;
 #pragma unroll 1
     for (int a = 0; a < Q; ++a) {
         const double xa = T.gl_x[Q][a];
         const double sP = P[4] * xa, wP = P[4] * T.gl_w[Q][a];
         const double xx = P[0] + sP * P[2], xy = P[1] + sP * P[3];
-        double z[Q], l0[Q], l1[Q], sd[Q], sk[Q], s2[Q], zt[Q], sv[Q];
+        double z[Q], l0[Q], l1[Q], sd[Q], sk[Q], s2[Q], zt[Q], sv[Q], dna[Q], dnb[Q];
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
             const double sQ = Qs[4] * T.gl_x[Q][c];
             const double dx = xx - (Qs[0] + sQ * Qs[2]), dy = xy - (Qs[1] + sQ * Qs[3]);
             z[c] = zf * (dx * dx + dy * dy);
             zt[c] = fh * ((dx * P[2] + dy * P[3]) * (dx * Qs[2] + dy * Qs[3]));
+            if (WK) { dna[c] = dx * Qs[5] + dy * Qs[6]; dnb[c] = -(dx * P[5] + dy * P[6]); }
             l0[c] = 1.0; l1[c] = 1.0 - z[c];
             const double* s0 = tb.st[0];
             sd[c] = s0[10] * l1[c]; sk[c] = s0[6] + s0[7] * l1[c]; s2[c] = s0[8] + s0[9] * l1[c];
@@ -457,7 +466,7 @@ __device__ __forceinline__ void far_dpair(const Tables& T, const TimeBlock& tb, 
                 l0[c] = x2; l1[c] = x3;
             }
         }
-        double r0 = 0, r1s = 0, rv = 0;
+        double r0 = 0, r1s = 0, rv = 0, ra0 = 0, ra1 = 0, rb = 0;
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
             const double e = exp(-z[c]);
@@ -467,13 +476,71 @@ __device__ __forceinline__ void far_dpair(const Tables& T, const TimeBlock& tb, 
             r0 = fma(w, 1.0 - xc, r0);
             r1s = fma(w, xc, r1s);
             if (WV) rv = fma(wq * e, sv[c], rv);
+            if (WK) {
+                const double gk = wq * e * sk[c], fy = 0.5 * (hq + xc);
+                ra0 = fma(gk * dna[c], 1.0 - fy, ra0);
+                ra1 = fma(gk * dna[c], fy, ra1);
+                rb = fma(gk, dnb[c], rb);
+            }
         }
         m00 += wP * (1.0 - xa) * r0; m01 += wP * (1.0 - xa) * r1s;
         m10 += wP * xa * r0;         m11 += wP * xa * r1s;
         if (WV) mv = fma(wP, rv, mv);
+        if (WK) {
+            const double fx = 0.5 * (hp + xa);
+            ka0 = fma(wP, ra0, ka0); ka1 = fma(wP, ra1, ka1);
+            kb0 = fma(wP * (1.0 - fx), rb, kb0); kb1 = fma(wP * fx, rb, kb1);
+        }
     }
     mom[0] = m00; mom[1] = m01; mom[2] = m10; mom[3] = m11;
     if (WV) *vmom = mv * i1 * kInv4Pi;       // int int Delta F_V over the piece pair
+    if (WK) { kmom[0] = ka0; kmom[1] = ka1; kmom[2] = kb0; kmom[3] = kb1; }
+}
+
+// K_h's kernel alone on one half-piece pair (the border pairs of the fused
+// tile that only K_h needs): as far_dpair's kmom with the S1 series only;
+// ORI = 0: int int (x - y).n_Q G fy, ORI = 1: int int (y - x).n_P G fx.
+template <int Q, int ORI>
+__device__ __forceinline__ double far_kpair(const Tables& T, const TimeBlock& tb, double al,
+                                            const double* P, const double* Qs, int hp, int hq)
+{
+    const double zf = 0.25 * al * tb.inv_dc;
+    double acc = 0.0;
+#pragma unroll 1
+    for (int a = 0; a < Q; ++a) {
+        const double xa = T.gl_x[Q][a];
+        const double sP = P[4] * xa, wP = P[4] * T.gl_w[Q][a];
+        const double xx = P[0] + sP * P[2], xy = P[1] + sP * P[3];
+        double z[Q], l0[Q], l1[Q], sk[Q], dn[Q];
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            const double sQ = Qs[4] * T.gl_x[Q][c];
+            const double dx = xx - (Qs[0] + sQ * Qs[2]), dy = xy - (Qs[1] + sQ * Qs[3]);
+            z[c] = zf * (dx * dx + dy * dy);
+            dn[c] = ORI == 0 ? dx * Qs[5] + dy * Qs[6] : -(dx * P[5] + dy * P[6]);
+            l0[c] = 1.0; l1[c] = 1.0 - z[c];
+            sk[c] = tb.st[0][6] + tb.st[0][7] * l1[c];
+        }
+        for (int n = 1; n < tb.nterm; ++n) {
+            const double* st = tb.st[n];
+#pragma unroll
+            for (int c = 0; c < Q; ++c) {
+                const double x2 = fma(fma(-st[1], z[c], st[0]), l1[c], -st[2] * l0[c]);
+                const double x3 = fma(fma(-st[4], z[c], st[3]), x2, -st[5] * l1[c]);
+                sk[c] = fma(st[7], x3, fma(st[6], x2, sk[c]));
+                l0[c] = x2; l1[c] = x3;
+            }
+        }
+        double r = 0.0;
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            const double xc = T.gl_x[Q][c], wq = Qs[4] * T.gl_w[Q][c];
+            const double g = wq * exp(-z[c]) * sk[c] * dn[c];
+            r = fma(g, ORI == 0 ? 0.5 * (hq + xc) : 1.0, r);
+        }
+        acc = fma(ORI == 0 ? wP : wP * 0.5 * (hp + xa), r, acc);
+    }
+    return acc;
 }
 
 
@@ -481,14 +548,29 @@ __device__ __forceinline__ void far_dpair(const Tables& T, const TimeBlock& tb, 
 // is one more series sum at the nodes D_h already evaluates): the 2 x 2 half
 // pieces of segments I0 + s and J0 + r are pieces 2s+1, 2s+2 and 2r+1, 2r+2 of
 // the tile, and V_h's tiles are the same symmetric 16 x 16 tiles.
-template <int Q, bool WV>
+// WK (with WV): K_h's separated blocks from the same node pairs too.  Its
+// kernel needs only S1, which the Hessian term already sums, and the normal
+// components of x - y.  A lane's segment pair (I0+il, J0+jl) gives, in both
+// orientations, the falling and the rising moment of the trial hats on the
+// trial segment; the hat of vertex n takes its rising part from segment n-1:
+//   orientation A (K_h rows I0+il, hats J0+jl): from the lane on the left
+//   (__shfl_up), for jl = 0 from the pairs of the pieces -1, 0 (the halves of
+//   segment J0-1) computed by lanes 128..191;
+//   orientation B (rows J0+jl, hats I0+il; off-diagonal tiles only, the
+//   diagonal tile's A covers it): from the lane above through LDS, for il = 0
+//   from the pieces -1, 0 of the row side (lanes 192..255).
+// The piece arrays therefore start at piece -1.
+template <int Q, bool WV, bool WK = false>
 __global__ __launch_bounds__(kWG, (Q == 3 || (Q == 4 && !WV)) ? 3 : 1) void k_assemble_dfar(Geom g, const Tables* __restrict__ Tg,
                                                        const int* __restrict__ blist, int tiles_1d,
-                                                       OutBuf out, OutBuf outv, const TimeBlock* __restrict__ tbs)
+                                                       OutBuf out, OutBuf outv, const TimeBlock* __restrict__ tbs,
+                                                       double* __restrict__ outk = nullptr)
 {
     __shared__ double mom[kDP][kDP][4];
-    __shared__ double pc[2][kDP][7];       // ax ay ex ey len nx ny
+    __shared__ double pc[2][kDP + 1][7];   // pieces -1 .. kDP-1: ax ay ex ey len nx ny
     __shared__ double stage[kTile][kTile + 1];
+    __shared__ double kb[WK ? 2 : 1][kTile][4];        // border K moments (A, B)
+    __shared__ double kr[WK ? kTile : 1][kTile];        // orientation B rising moments
     const Tables& T = *Tg;                 // only the Q-point rule is read (uniform loads)
     const int tid = threadIdx.x;
     const long long tiles = (long long)tiles_1d * (tiles_1d + 1) / 2;
@@ -500,12 +582,12 @@ __global__ __launch_bounds__(kWG, (Q == 3 || (Q == 4 && !WV)) ? 3 : 1) void k_as
     const TimeBlock& tb = tbs[b];
     const int I0 = ti * kTile, J0 = tj * kTile;
     const int np = 2 * g.ng;
-    if (tid < 2 * kDP) {
-        int side = tid / kDP, u = tid % kDP;
+    if (tid < 2 * (kDP + 1)) {
+        int side = tid / (kDP + 1), u = tid % (kDP + 1) - 1;
         int base = side ? J0 : I0;
         int h = ((2 * base - 1 + u) % np + np) % np;
         Piece P = half_piece(g, h);
-        double* q = pc[side][u];
+        double* q = pc[side][u + 1];
         q[0] = P.ax; q[1] = P.ay; q[2] = P.ex; q[3] = P.ey; q[4] = P.len; q[5] = P.nx; q[6] = P.ny;
     }
     __syncthreads();
@@ -514,12 +596,14 @@ __global__ __launch_bounds__(kWG, (Q == 3 || (Q == 4 && !WV)) ? 3 : 1) void k_as
     // then lanes 0..131 one pair each on the border of the piece range
     const int il = tid / kTile, jl = tid % kTile, i = I0 + il, j = J0 + jl;
     double vsum = 0.0;
+    double ka[2] = {0.0, 0.0}, kbo[2] = {0.0, 0.0};     // K moments of the lane's segment pair
 #pragma unroll 1
     for (int e = 0; e < 4; ++e) {
         const int u = 2 * il + 1 + (e >> 1), v = 2 * jl + 1 + (e & 1);
-        double vm = 0.0;
-        far_dpair<Q, WV>(T, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v], &vm);
+        double vm = 0.0, km[4];
+        far_dpair<Q, WV, WK>(T, tb, g.alpha, pc[0][u + 1], pc[1][v + 1], mom[u][v], &vm, km, e >> 1, e & 1);
         vsum += vm;
+        if (WK) { ka[0] += km[0]; ka[1] += km[1]; kbo[0] += km[2]; kbo[1] += km[3]; }
     }
     if (tid < 4 * kDP - 4) {
         int u, v;
@@ -528,8 +612,21 @@ __global__ __launch_bounds__(kWG, (Q == 3 || (Q == 4 && !WV)) ? 3 : 1) void k_as
         else if (tid < 3 * kDP - 2) { u = tid - 2 * kDP + 1; v = 0; }
         else { u = tid - (3 * kDP - 2) + 1; v = kDP - 1; }
         double unused;
-        far_dpair<Q, false>(T, tb, g.alpha, pc[0][u], pc[1][v], mom[u][v], &unused);
+        far_dpair<Q, false>(T, tb, g.alpha, pc[0][u + 1], pc[1][v + 1], mom[u][v], &unused);
     }
+    if (WK && tid >= 128) {
+        // border pairs of K_h: (pieces of row segment il) x (pieces -1, 0 of
+        // column segment J0-1), or (pieces -1, 0 of row segment I0-1) x
+        // (pieces of column segment jl)
+        const int q = tid - 128, side = q >> 6, r = (q >> 2) & 15, sub = q & 3;
+        if (side == 0)
+            kb[0][r][sub] = far_kpair<Q, 0>(T, tb, g.alpha, pc[0][2 * r + 1 + (sub >> 1) + 1], pc[1][(sub & 1) - 1 + 1],
+                                            sub >> 1, sub & 1);
+        else if (I0 != J0)
+            kb[1][r][sub] = far_kpair<Q, 1>(T, tb, g.alpha, pc[0][(sub >> 1) - 1 + 1], pc[1][2 * r + 1 + (sub & 1) + 1],
+                                            sub >> 1, sub & 1);
+    }
+    if (WK) kr[il][jl] = kbo[1];
     __syncthreads();
     const bool live = i < g.ng && j < g.ng, own = live && !mirrored(true, I0, J0, il, jl);
     double acc = 0.0;
@@ -538,10 +635,10 @@ __global__ __launch_bounds__(kWG, (Q == 3 || (Q == 4 && !WV)) ? 3 : 1) void k_as
         const int ui = 2 * il, vj = 2 * jl;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const double a0 = si.v0[u], a1 = si.v0[u] + si.slope[u] * pc[0][ui + u][4];
+            const double a0 = si.v0[u], a1 = si.v0[u] + si.slope[u] * pc[0][ui + u + 1][4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const double b0 = sj.v0[v], b1 = sj.v0[v] + sj.slope[v] * pc[1][vj + v][4];
+                const double b0 = sj.v0[v], b1 = sj.v0[v] + sj.slope[v] * pc[1][vj + v + 1][4];
                 const double* M = mom[ui + u][vj + v];
                 acc += a0 * (b0 * M[0] + b1 * M[1]) + a1 * (b0 * M[2] + b1 * M[3]);
             }
@@ -552,6 +649,23 @@ __global__ __launch_bounds__(kWG, (Q == 3 || (Q == 4 && !WV)) ? 3 : 1) void k_as
     if (WV) {
         __syncthreads();          // the stage is reused
         store_tile(stage, true, own ? vsum : 0.0, live, boff, g.ng, I0, J0, il, jl, outv);
+    }
+    if (WK) {
+        const double f = g.alpha * 0.125 / kPi * tb.inv_dc * tb.inv_dc;
+        // orientation A: row i, hat j = falling part on segment j + rising
+        // part on segment j - 1
+        const double left = __shfl_up(ka[1], 1, kTile);
+        const double riseA = jl ? left : ((kb[0][il][0] + kb[0][il][1]) + kb[0][il][2]) + kb[0][il][3];
+        if (live) outk[boff + (long long)i * g.ng + j] = f * (riseA + ka[0]);
+        if (I0 != J0) {
+            // orientation B: row j, hat i, through the stage (transposed store)
+            const double riseB = il ? kr[il - 1][jl] : ((kb[1][jl][0] + kb[1][jl][1]) + kb[1][jl][2]) + kb[1][jl][3];
+            __syncthreads();      // the stage is reused
+            stage[jl][il] = f * (riseB + kbo[0]);
+            __syncthreads();
+            const int r = J0 + il, col = I0 + jl;
+            if (r < g.ng && col < g.ng) outk[boff + (long long)r * g.ng + col] = stage[il][jl];
+        }
     }
 }
 
@@ -1676,6 +1790,10 @@ struct stbem_ctx {
     std::vector<int> list_nterm[7];       // series terms of each listed block (host copy, for the work model)
     std::vector<int> h_blist[7];          // host copy of the block lists (each group in increasing k)
     bool vd_fusable = false;              // V_h and D_h have the same far-tile block lists
+    // K_h's blocks that are neither touching nor in D_h's far-tile lists: the
+    // generic kernel takes them when K_h comes from D_h's far tiles
+    int* d_klist_fused = nullptr;
+    int nklist_fused = 0;
     // work
     double* part = nullptr;     // nblk * ng
     size_t part_bytes = 0;
@@ -1897,6 +2015,24 @@ int launch_assemble(stbem_ctx* c, OutBuf o64, hipStream_t s, bool with_touch = f
     return 0;
 }
 
+// generic kernel over an explicit device list of blocks
+template <int OP>
+int launch_assemble_list(stbem_ctx* c, OutBuf o64, hipStream_t s, const int* list, int count)
+{
+    int t1 = (c->ng + kTile - 1) / kTile;
+    const long long tiles = tiles_per_block(t1, sym_op(OP));
+    Geom g = geom(c);
+    const int step = blocks_per_launch(tiles);
+    for (int off = 0; off < count; off += step) {
+        const int cnt = std::min(step, count - off);
+        dim3 gr((unsigned)(cnt * tiles)), blk(kWG);
+        KTimer kt(c, kname("k_assemble", OP).c_str(), (double)cnt * g.ng * g.ng, s);
+        hipLaunchKernelGGL((k_assemble<OP>), gr, blk, 0, s, g, c->d_tab, c->ord, c->lmax, list + off, t1, o64, (const TimeBlock*)c->d_tbs);
+    }
+    HIPCHK(c, hipGetLastError());
+    return 0;
+}
+
 template <int OP>
 void launch_knear(stbem_ctx* c, int slot, double* o, hipStream_t s)
 {
@@ -1930,15 +2066,25 @@ double flops_vkfar(int op, int Q, long long nblk, long long sum_nterm, long long
     return (double)lanes_per_block * ((double)nblk * (5.0 * Q + q2 * (node - term) + 5.0) + term * q2 * (double)sum_nterm);
 }
 
-double flops_dfar(int Q, bool wv, long long nblk, long long sum_nterm, long long tiles_per_blk, long long owned_per_blk)
+double flops_dfar(int Q, bool wv, long long nblk, long long sum_nterm, long long tiles_per_blk, long long owned_per_blk,
+                  bool wk = false)
 {
     const double q2 = (double)Q * Q;
     const double pw = wv ? 1024.0 : 0.0, pp = wv ? 132.0 : 1156.0;       // pairs per tile with / without V_h
-    const double per_pair_wv = 21.0 + 19.0 * Q + q2 * (70.0 - 22.0), per_pair = 21.0 + 17.0 * Q + q2 * (67.0 - 20.0);
+    double per_pair_wv = 21.0 + 19.0 * Q + q2 * (70.0 - 22.0), per_pair = 21.0 + 17.0 * Q + q2 * (67.0 - 20.0);
     const double tiles = (double)tiles_per_blk;
+    double kborder = 0.0;
+    if (wk) {
+        // K_h moments: per node pair 20 (normal components 6, weight 2,
+        // shape 2, four moments 10), per row 12; border pairs (64 per tile,
+        // 128 off the diagonal): per node pair 20 + 14 per series term, per row 4
+        per_pair_wv += 12.0 * Q + 20.0 * q2;
+        const double border = 64.0 + 128.0 * (tiles - 1.0) / tiles;
+        kborder = tiles * border * ((double)nblk * (4.0 * Q + 20.0 * q2) + 14.0 * q2 * (double)sum_nterm);
+    }
     return tiles * (pw * ((double)nblk * per_pair_wv + 22.0 * q2 * (double)sum_nterm) +
-                    pp * ((double)nblk * per_pair + 20.0 * q2 * (double)sum_nterm)) +
-           (double)nblk * (double)owned_per_blk * (wv ? 199.0 : 196.0);
+                    pp * ((double)nblk * per_pair + 20.0 * q2 * (double)sum_nterm)) + kborder +
+           (double)nblk * (double)owned_per_blk * (wv ? (wk ? 215.0 : 199.0) : 196.0);
 }
 
 long long sum_terms(const stbem_ctx* c, int slot, const int* bl, int cnt)
@@ -2022,6 +2168,18 @@ int build_block_lists(stbem_ctx* c)
     }
     c->vd_fusable = far_lists[0] == far_lists[1] && c->nlist_touch[0] == c->nlist_touch[2];
     for (int q = 0; q < 9; ++q) c->vd_fusable = c->vd_fusable && c->nlist_far[0][q] == c->nlist_far[2][q];
+    {
+        std::vector<char> in_dfar((size_t)c->nblk + 1, 0);      // by packed index
+        std::vector<int> rest;
+        for (int b : far_lists[1]) in_dfar[(size_t)b] = 1;
+        const std::vector<int>& kl = c->h_blist[1];
+        for (size_t e = (size_t)c->nlist_touch[1]; e < kl.size(); ++e)
+            if (!in_dfar[(size_t)kl[e]]) rest.push_back(kl[e]);
+        c->nklist_fused = (int)rest.size();
+        if (rest.empty()) rest.push_back(0);
+        int rc = upload(c, &c->d_klist_fused, rest);
+        if (rc) return rc;
+    }
     return 0;
 }
 
@@ -2162,7 +2320,7 @@ int launch_dfar32(stbem_ctx* c, const int* bl, OutBuf od, hipStream_t s)
     return 0;
 }
 
-int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd, int prec)
+int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd, int prec, bool fuse_k = false)
 {
     int slot = op_slot(op);
     int rc0 = prepare_storage(c, op, prec);
@@ -2173,6 +2331,9 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd, int pre
     case STBEM_K: {
         if (op == STBEM_K) launch_knear<OP_K>(c, 1, o, s);
         const OutBuf ob = out_of(c, slot);
+        // K_h with V_h and D_h: its separated blocks in D_h's far lists come
+        // from D_h's far tiles, the generic kernel takes the rest
+        if (op == STBEM_K && fuse_k) return launch_assemble_list<OP_K>(c, ob, s, c->d_klist_fused, c->nklist_fused);
         // V_h with D_h: its touching and separated blocks come with D_h's tiles
         int rc = op == STBEM_V ? launch_assemble<OP_V>(c, ob, s, !fuse_vd) : launch_assemble<OP_K>(c, ob, s);
         if (rc) return rc;
@@ -2208,10 +2369,21 @@ int assemble_one(stbem_ctx* c, unsigned op, hipStream_t s, bool fuse_vd, int pre
                 const int n = std::min(step, c->nlist_far[2][q] - off);
                 dim3 gr((unsigned)(n * tiles)), blk(kWG);
                 const int* b2 = bl + off;
-                const std::string kn = std::string("k_assemble_dfar<") + std::to_string(q) + (fuse_vd ? ", true>" : ", false>");
+                const std::string kn = std::string("k_assemble_dfar<") + std::to_string(q) +
+                                       (fuse_vd ? (fuse_k ? ", true, true>" : ", true>") : ", false>");
                 KTimer kt(c, store_name(kn.c_str(), od).c_str(), (double)n * c->ng * c->ng, s,
-                          c->timing ? flops_dfar(q, fuse_vd, n, sum_terms(c, 2, b2, n), tiles, (long long)c->ng * (c->ng + 1) / 2) : 0.0);
-                if (fuse_vd) switch (q) {
+                          c->timing ? flops_dfar(q, fuse_vd, n, sum_terms(c, 2, b2, n), tiles, (long long)c->ng * (c->ng + 1) / 2,
+                                                 fuse_k) : 0.0);
+                double* ok = c->mat[1];
+                if (fuse_vd && fuse_k) switch (q) {
+                case 3: hipLaunchKernelGGL((k_assemble_dfar<3, true, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, ov, c->d_tbs, ok); break;
+                case 4: hipLaunchKernelGGL((k_assemble_dfar<4, true, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, ov, c->d_tbs, ok); break;
+                case 5: hipLaunchKernelGGL((k_assemble_dfar<5, true, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, ov, c->d_tbs, ok); break;
+                case 6: hipLaunchKernelGGL((k_assemble_dfar<6, true, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, ov, c->d_tbs, ok); break;
+                case 7: hipLaunchKernelGGL((k_assemble_dfar<7, true, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, ov, c->d_tbs, ok); break;
+                default: hipLaunchKernelGGL((k_assemble_dfar<8, true, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, ov, c->d_tbs, ok); break;
+                }
+                else if (fuse_vd) switch (q) {
                 case 3: hipLaunchKernelGGL((k_assemble_dfar<3, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, ov, c->d_tbs); break;
                 case 4: hipLaunchKernelGGL((k_assemble_dfar<4, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, ov, c->d_tbs); break;
                 case 5: hipLaunchKernelGGL((k_assemble_dfar<5, true>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, ov, c->d_tbs); break;
@@ -2775,6 +2947,7 @@ int stbem_destroy(stbem_ctx* c)
                    c->gm_q, c->gm_part, c->gm_h, c->gm_v};
     for (void* p : own) if (p) (void)hipFree(p);
     for (int q = 0; q < 7; ++q) if (c->d_blist[q]) (void)hipFree(c->d_blist[q]);
+    if (c->d_klist_fused) (void)hipFree(c->d_klist_fused);
     clear_timing(c);
     delete c;
     return STBEM_OK;
@@ -2798,6 +2971,7 @@ int stbem_set_toeplitz(stbem_ctx* c, int on)
     free_f32(c, true, true);
     c->toep = want;
     for (int q = 0; q < 7; ++q) if (c->d_blist[q]) { (void)hipFree(c->d_blist[q]); c->d_blist[q] = nullptr; }
+    if (c->d_klist_fused) { (void)hipFree(c->d_klist_fused); c->d_klist_fused = nullptr; }
     return build_block_lists(c);
 }
 
@@ -2910,9 +3084,12 @@ int stbem_assemble(stbem_ctx* c, unsigned mask, int precision, void* stream)
     // V_h and D_h together: V_h's separated blocks are computed by D_h's far
     // tiles (same block lists); V is assembled first, so its storage exists
     const bool fuse = (mask & STBEM_V) && (mask & STBEM_D) && c->vd_fusable;
+    // K_h too (FP64): its separated blocks from the same tiles; K is
+    // assembled before D, so its storage exists when D's far tiles run
+    const bool fuse_k = fuse && (mask & STBEM_K) && precision == STBEM_FP64;
     for (unsigned op : ops)
         if (mask & op) {
-            int rc = assemble_one(c, op, S(stream), fuse, precision);
+            int rc = assemble_one(c, op, S(stream), fuse, precision, fuse_k);
             if (rc) return rc;
         }
     return STBEM_OK;

@@ -71,9 +71,11 @@ def test_launch_timing_records(small):
     V_h + D_h + K_h assembly with its work units (matrix entries of the
     blocks it processed) and a positive event time; switching it off drops
     the records.  Assembled together, V_h's blocks come from D_h's tile
-    launches (named "k_assemble_dfar<q, true>" and "k_assemble_dnear<true>"),
-    which count their D_h entries; the V_h entries they write are the same
-    number."""
+    launches (named "k_assemble_dfar<q, true, true>" and
+    "k_assemble_dnear<true>"), which count their D_h entries; the V_h entries
+    they write are the same number, and so are the K_h entries of the far
+    tiles (K_h's touching blocks and the blocks outside D_h's far lists go
+    through K_h's own kernels)."""
     wl, o, c, L = small
     c.set_timing(True)
     c.assemble(L.V | L.K | L.D)
@@ -86,9 +88,13 @@ def test_launch_timing_records(small):
     fused = sum(u for name, (n, ms, u, fl) in rec.items()
                 if name.startswith(("k_assemble_dfar<", "k_assemble_dnear<")) and name.endswith("true>"))
     assert fused > 0
+    fused_k = sum(u for name, (n, ms, u, fl) in rec.items()
+                  if name.startswith("k_assemble_dfar<") and name.endswith("true, true>"))
+    assert fused_k > 0
+    extra = {"V": fused, "K": fused_k, "D": 0}
     for op, prefixes in by_op.items():
         units = sum(u for name, (n, ms, u, fl) in rec.items() if name.startswith(prefixes))
-        assert units + (fused if op == "V" else 0) == entries, (op, units, entries)
+        assert units + extra[op] == entries, (op, units, entries)
     for name, (n, ms, u, fl) in rec.items():
         assert n >= 1 and ms > 0.0 and u > 0, name
 
@@ -192,19 +198,20 @@ def test_tiny_solution(tiny):
 
 
 def test_assembled_alone_or_together(small):
-    """V_h and D_h assembled in one call share D_h's tiles (V_h's blocks come
-    from the same piece pairs); assembled alone each uses its own kernels.
-    Both ways must meet the oracle bar, and agree with each other to the
-    quadrature level; D_h's own arithmetic is the same either way."""
+    """V_h, K_h and D_h assembled in one call share D_h's tiles (V_h's and
+    K_h's separated blocks come from the same piece pairs, V_h's touching
+    blocks too); assembled alone each uses its own kernels.  Both ways must
+    meet the oracle bar, and agree with each other to the quadrature level;
+    D_h's own arithmetic is the same either way."""
     wl, o, c, L = small
     import paper_1811_05224_amd as P
     alone = {}
-    for code in (L.V, L.D):
+    for code in (L.V, L.K, L.D):
         ca = P.Context.from_workload(wl)
         ca.assemble(code)
         alone[code] = ca.packed(code).cpu().numpy()
         ca.close()
-    for code, op in ((L.V, "V"), (L.D, "D")):
+    for code, op in ((L.V, "V"), (L.K, "K"), (L.D, "D")):
         fused = c.packed(code).cpu().numpy()
         ref = o.packed(op)
         ea, ef = block_err(alone[code], ref).max(), block_err(fused, ref).max()
