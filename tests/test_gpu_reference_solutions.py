@@ -6,8 +6,9 @@ N = 16384) and for an L-shape with 48 segments x 32 graded steps
 (alpha = 0.1, N = 1536), the right-hand side f = (1/2 M_h + K_h) g of eq.(4)
 for manufactured Dirichlet data g, u0 = 0, and the solution w of V_h w = f
 by block forward substitution.  Here the GPU forms f from g and solves
-V_h w = f (the oracle's f) with D_h-preconditioned GMRES in FP64 and with the
-FP32-stored iterative refinement; w must match element by element.
+V_h w = f (the oracle's f) with D_h-preconditioned GMRES in FP64, with the
+FP32-stored iterative refinement and, for uniform steps, in block-Toeplitz
+storage; w must match element by element.
 """
 import os
 
@@ -54,5 +55,13 @@ def test_solution_matches_oracle(name):
     c.assemble(L.V | L.D, precision=L.FP32_IR)
     w32, i32 = c.solve(f_ref, tol=1e-13, max_it=400, mode=L.FP32_IR, inner_tol=1e-6, max_outer=12, ir_tol=1e-13)
     check(w32, f"FP32-stored refinement ({i32.outer} outer / {i32.iters} inner)")
+    c.release(L.V | L.D)
+    h = np.diff(z["t_nodes"])
+    if np.abs(h - h[0]).max() <= 1e-12 * h[0]:
+        # uniform steps: the block-Toeplitz storage and its matrix-core product
+        c.set_toeplitz(True)
+        c.assemble(L.V | L.D)
+        wt, it = c.solve(f_ref, tol=1e-13, max_it=400)
+        check(wt, f"block-Toeplitz FP64 GMRES ({it.iters} it)")
     c.close()
     torch.cuda.empty_cache()
