@@ -1765,7 +1765,7 @@ struct stbem_ctx {
     // device copies
     double *d_t = nullptr, *d_vx = nullptr, *d_vy = nullptr, *d_ex = nullptr, *d_ey = nullptr, *d_len = nullptr;
     double *d_ox = nullptr, *d_oy = nullptr, *d_mt = nullptr;
-    double *d_m0c = nullptr, *d_m0cd = nullptr, *d_m0amax = nullptr;
+    double *d_m0c = nullptr, *d_m0cd = nullptr, *d_m0amax = nullptr, *d_m0it = nullptr;
     int m0_ksplit = 0, m0_npow = 0;   // M0 rows k >= m0_ksplit by moments of powers (none if == nt)
     int *d_m0n = nullptr, *d_v2t_loc = nullptr;
     int *d_tri = nullptr, *d_v2t_ptr = nullptr, *d_v2t = nullptr;
@@ -1888,7 +1888,7 @@ Geom geom(const stbem_ctx* c)
 M0Poly m0poly(const stbem_ctx* c)
 {
     M0Poly p;
-    p.c = c->d_m0c; p.cd = c->d_m0cd; p.n = c->d_m0n; p.amax = c->d_m0amax;
+    p.c = c->d_m0c; p.cd = c->d_m0cd; p.n = c->d_m0n; p.amax = c->d_m0amax; p.it = c->d_m0it;
     return p;
 }
 
@@ -2896,7 +2896,8 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
         double amax = 0.25 * c->alpha * R2;
         std::vector<double> cf((size_t)c->nt * kPolyMax, 0.0), cfd((size_t)c->nt * kPolyMax, 0.0);
         std::vector<int> nn(c->nt, 0);
-        std::vector<double> am(c->nt, 0.0);
+        std::vector<double> am(c->nt, 0.0), it(c->nt + 1, 0.0);
+        for (int k = 1; k <= c->nt; ++k) it[k] = 1.0 / c->t[k];
         for (int k = 1; k < c->nt; ++k) {
             long double t0 = c->t[k], t1 = c->t[k + 1], h = (long double)c->t[k + 1] - (long double)c->t[k];
             double amk = std::fmin(4.0 * c->t[k], amax);   // the series is used for a <= amk
@@ -2928,7 +2929,7 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
         for (int k = c->m0_ksplit; k < c->nt; ++k) c->m0_npow = std::max(c->m0_npow, nn[k]);
         int rc2 = 0;
         if ((rc2 = upload(c, &c->d_m0c, cf)) || (rc2 = upload(c, &c->d_m0cd, cfd)) || (rc2 = upload(c, &c->d_m0n, nn)) ||
-            (rc2 = upload(c, &c->d_m0amax, am))) {
+            (rc2 = upload(c, &c->d_m0amax, am)) || (rc2 = upload(c, &c->d_m0it, it))) {
             stbem_destroy(c);
             return rc2;
         }
@@ -2942,7 +2943,7 @@ int stbem_destroy(stbem_ctx* c)
     if (!c) return STBEM_OK;
     for (int s = 0; s < 7; ++s) dev_free(c, c->mat[s]);
     free_f32(c, true, true);
-    void* own[] = {c->d_t, c->d_vx, c->d_vy, c->d_ex, c->d_ey, c->d_len, c->d_ox, c->d_oy, c->d_mt, c->d_m0c, c->d_m0cd, c->d_m0n, c->d_m0amax, c->d_v2t_loc,
+    void* own[] = {c->d_t, c->d_vx, c->d_vy, c->d_ex, c->d_ey, c->d_len, c->d_ox, c->d_oy, c->d_mt, c->d_m0c, c->d_m0cd, c->d_m0n, c->d_m0amax, c->d_m0it, c->d_v2t_loc,
                    c->d_tri, c->d_v2t_ptr, c->d_v2t, c->d_tab, c->d_m0tab, c->part, c->d_tbs, c->d_tbs32, c->wvec,
                    c->gm_q, c->gm_part, c->gm_h, c->gm_v};
     for (void* p : own) if (p) (void)hipFree(p);

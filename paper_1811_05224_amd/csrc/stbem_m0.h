@@ -30,21 +30,29 @@ struct Mesh2 {
     const int *v2t_ptr, *v2t;              // vertex -> triangles
 };
 
+// For k >= 1, with z = a/t, E1(a/t_{k+1}) - E1(a/t_k) = ln(t_{k+1}/t_k)
+// + Ein(a/t_{k+1}) - Ein(a/t_k) is a power series in a; when a/t_k stays
+// <= 4 (a <= amax[k]) it is evaluated from precomputed coefficients
+// (row-wise table, Horner); farther pairs use E1 directly.  DERIV adds -(e^{-a/t_{k+1}} - e^{-a/t_k}).
+constexpr int kPolyMax = 40;
+// Per time element k >= 1: coefficients of the series in a (c[k][0] = cd[k][0]
+// = ln(t_{k+1}/t_k)), their count, the range a <= amax[k]; it[k] = 1/t_k.
+struct M0Poly { const double* c; const double* cd; const int* n; const double* amax; const double* it; };   // [nt][kPolyMax], [nt], [nt], [nt+1]
+
 // G_k (or its alpha-derivative) at r^2
 template <bool DERIV>
-SDEV double m0_kernel(const Geom& g, int k, double r2)
+SDEV double m0_kernel(const Geom& g, const M0Poly& PP, int k, double r2)
 {
     double a = 0.25 * g.alpha * r2;
-    double t1 = g.t[k + 1], t0 = g.t[k];
-    double z1 = a / t1;
+    double z1 = a * PP.it[k + 1];
     double x1, x0;
     if (k == 0) {
         double E = e1t<DERIV>(z1, x1);
         return DERIV ? (E - x1) * kInv4Pi : g.alpha * kInv4Pi * E;
     }
-    double z0 = a / t0, dE;
+    double z0 = a * PP.it[k], dE;
     if (z0 <= 2.0) {
-        dE = log(t1 / t0) + ein(z1) - ein(z0);    // no ln a cancellation
+        dE = PP.c[(long long)k * kPolyMax] + ein(z1) - ein(z0);    // ln(t1/t0): no ln a cancellation
         if (DERIV) { x1 = exp(-z1); x0 = exp(-z0); }
     } else {
         dE = e1t<DERIV>(z1, x1) - e1t<DERIV>(z0, x0);
@@ -102,13 +110,6 @@ SDEV double seg_tri_dist(const Piece& S, const Tri& tr)
 }
 
 struct M0Orders { int qs_near, qt_near; double near_ratio, omax, q_tol, z_floor; };
-
-// For k >= 1, with z = a/t, E1(a/t_{k+1}) - E1(a/t_k) = ln(t_{k+1}/t_k)
-// + Ein(a/t_{k+1}) - Ein(a/t_k) is a power series in a; when a/t_k stays
-// <= 4 (a <= amax[k]) it is evaluated from precomputed coefficients
-// (row-wise table, Horner); farther pairs use E1 directly.  DERIV adds -(e^{-a/t_{k+1}} - e^{-a/t_k}).
-constexpr int kPolyMax = 40;
-struct M0Poly { const double* c; const double* cd; const int* n; const double* amax; };   // [nt][kPolyMax], [nt], [nt]
 
 // Horner over the full zero-padded coefficient row (leading zeros leave it
 // unchanged), unrolled so that the coefficient loads are issued ahead
@@ -249,13 +250,12 @@ SDEV void m0_row_values(const Geom& g, const M0Poly& PP, int k0, int nr, double 
             have = 0;
             continue;
         }
-        const double t1 = g.t[k + 1], t0 = g.t[k];
-        const double z1 = a / t1, z0 = a / t0;
+        const double z1 = a * PP.it[k + 1], z0 = a * PP.it[k];
         double dE, x1 = 0.0, x0 = 0.0;
         if (z0 <= 2.0) {
             const double e0 = have == 2 ? einprev : ein(z0);
             const double e1v = ein(z1);
-            dE = log(t1 / t0) + e1v - e0;            // no ln a cancellation
+            dE = PP.c[(long long)k * kPolyMax] + e1v - e0;    // ln(t1/t0): no ln a cancellation
             if (DERIV) { x1 = exp(-z1); x0 = have == 2 ? xprev : exp(-z0); }
             einprev = e1v; xprev = x1; have = 2;
         } else {
@@ -351,7 +351,7 @@ SDEV void m0_tri_moments(const Tables& T, const M0Tables& D, const M0Orders& MO,
             for (int v = 0; v < 3; ++v) out[v] = sm[v] - B * lg[v];
             return;
         }
-        if (PART != 2 && q0 > 0) m0_regular3(T, S, tr, q0, q0, [&](double r2) { return m0_kernel<DERIV>(g, 0, r2); }, out);
+        if (PART != 2 && q0 > 0) m0_regular3(T, S, tr, q0, q0, [&](double r2) { return m0_kernel<DERIV>(g, PP, 0, r2); }, out);
         return;
     }
     const int n = PP.n[k];
@@ -360,11 +360,11 @@ SDEV void m0_tri_moments(const Tables& T, const M0Tables& D, const M0Orders& MO,
         const double amax = PP.amax[k], q4 = 0.25 * g.alpha, sc = (DERIV ? 1.0 : g.alpha) * kInv4Pi;
         m0_regular3(T, S, tr, qs, qs, [&](double r2) {
             double a = q4 * r2;
-            return a <= amax ? sc * m0_poly(c, n, a) : m0_kernel<DERIV>(g, k, r2);
+            return a <= amax ? sc * m0_poly(c, n, a) : m0_kernel<DERIV>(g, PP, k, r2);
         }, out);
         return;
     }
-    m0_regular3(T, S, tr, qs, qs, [&](double r2) { return m0_kernel<DERIV>(g, k, r2); }, out);
+    m0_regular3(T, S, tr, qs, qs, [&](double r2) { return m0_kernel<DERIV>(g, PP, k, r2); }, out);
 }
 
 // ------------------------------------------------ representation formula

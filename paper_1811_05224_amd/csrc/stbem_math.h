@@ -31,7 +31,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
-#include "e1_cheb_table.h"
+#include "e1_poly_table.h"
 
 #define SDEV __host__ __device__ __forceinline__
 
@@ -83,23 +83,35 @@ struct Orders {
 
 // ------------------------------------------------------------------ E1
 // Ein(z) = sum_{n>=1} (-1)^{n+1} z^n/(n n!), entire; used for 0 <= z <= 2,
-// where 24 terms leave a tail below 1e-18 of the sum.
+// where 24 terms leave a tail below 1e-18 of the sum.  Evaluated in Horner
+// form, z (c_1 + z (c_2 + ...)), c_n = (-1)^{n+1}/(n n!): one FMA per term.
+struct EinCoef { double c[24]; };
+constexpr EinCoef ein_coef()
+{
+    EinCoef e{};
+    double f = 1.0;
+    for (int n = 1; n <= 24; ++n) {
+        f *= n;
+        e.c[n - 1] = ((n & 1) ? 1.0 : -1.0) / (n * f);
+    }
+    return e;
+}
+constexpr EinCoef kEin = ein_coef();
+
 SDEV double ein(double z)
 {
-    double term = z, sum = z;
+    double p = kEin.c[23];
 #pragma unroll
-    for (int n = 2; n <= 24; ++n) {
-        term *= z * (-1.0 / n);
-        sum += term * (1.0 / n);
-    }
-    return sum;
+    for (int n = 22; n >= 0; --n) p = fma(p, z, kEin.c[n]);
+    return p * z;
 }
 
 // E1(z) for z > 0 (and, with EX, ex = e^{-z}): -gamma - ln z + Ein(z) for
-// z <= 2; on [2, 64) e^{-z} times a Chebyshev expansion of e^z E1(z) per
-// octave (generated with mpmath, relative error < 2.5e-16); beyond, the
-// continued fraction e^{-z}/(z+1 - 1^2/(z+3 - 2^2/(z+5 - ...))) evaluated
-// from the tail.  The exponential is shared with the caller.
+// z <= 2; on [2, 64) e^{-z} times a polynomial for e^z E1(z) per
+// half-octave (fitted with mpmath, relative error < 2.1e-16, Horner in the
+// local variable); beyond, the continued fraction
+// e^{-z}/(z+1 - 1^2/(z+3 - 2^2/(z+5 - ...))) evaluated from the tail.  The
+// exponential is shared with the caller.
 template <bool EX>
 SDEV double e1t(double z, double& ex)
 {
@@ -110,24 +122,29 @@ SDEV double e1t(double z, double& ex)
     if (z > 740.0) { ex = 0.0; return 0.0; }
     ex = exp(-z);
     if (z < 64.0) {
-        int o = z < 4.0 ? 0 : z < 8.0 ? 1 : z < 16.0 ? 2 : z < 32.0 ? 3 : 4;
-        double lo = (double)(2 << o), x = (z - 1.5 * lo) / (0.5 * lo);
-        const double* co = kE1Cheb[o];
-        // fixed length (shorter octaves are zero-padded, which leaves the
-        // recurrence unchanged), unrolled so that the coefficient loads of
-        // the lane's octave are issued ahead of the recurrence
-        double b1 = 0.0, b2 = 0.0;
-        const double x2 = 2.0 * x;
+        // octave [lo, 2 lo), lo = 2^(o+1), halves [lo, 1.5 lo) and [1.5 lo, 2 lo)
+        const int o = z < 4.0 ? 0 : z < 8.0 ? 1 : z < 16.0 ? 2 : z < 32.0 ? 3 : 4;
+        const double lo = (double)(2 << o);
+        const int hh = z >= 1.5 * lo ? 1 : 0;
+        const double x = (z - lo * (1.0 + 0.5 * hh)) * (4.0 / lo) - 1.0;   // z - a exact
+        const double* co = kE1Poly[2 * o + hh];
+        // fixed length (shorter rows are zero-padded), unrolled so that the
+        // coefficient loads of the lane's interval issue ahead of the sum
+        double p = co[kE1PolyN - 1];
 #pragma unroll
-        for (int n = kE1ChebMax - 1; n >= 1; --n) {
-            double t = x2 * b1 - b2 + co[n];
-            b2 = b1; b1 = t;
-        }
-        return ex * (x * b1 - b2 + co[0]);
+        for (int n = kE1PolyN - 2; n >= 0; --n) p = fma(p, x, co[n]);
+        return ex * p;
     }
-    double tail = 0.0;
-    for (int n = 6; n >= 1; --n) tail = (double)n * n / (z + 2.0 * n + 1.0 - tail);
-    return ex / (z + 1.0 - tail);
+    // the fraction's tail n^2/(z + 2n + 1 - ...) for n = 6 .. 1 carried as
+    // a ratio nu/de (all terms positive), so that one division remains
+    double nu = 36.0, de = z + 13.0;
+#pragma unroll
+    for (int n = 5; n >= 1; --n) {
+        const double d2 = fma(z + (2.0 * n + 1.0), de, -nu);
+        nu = (double)(n * n) * de;
+        de = d2;
+    }
+    return ex * de / fma(z + 1.0, de, -nu);
 }
 
 SDEV double e1x(double z, double& ex) { return e1t<true>(z, ex); }
@@ -156,6 +173,7 @@ struct TimeBlock {
     double del[4];        // positive lags of the closed form: d=0 {h_k};
     double sgn[4];        //   d=1 {h_k + h_m, h_k, h_m}; d>=2 all four
     double lnd[4];
+    double idel[4];       // 1 / del
     int ndel;
     double dc, inv_dc;    // centre distance (separated)
     double w2;            // alpha / (4 smallest lag): z = w2 r^2 bounds a / delta
@@ -202,7 +220,7 @@ SDEV void time_block(const Geom& g, int k, int m, TimeBlock& tb)
             tb.del[1] = g.t[k + 1] - g.t[m + 1]; tb.sgn[1] = -1.0;
             tb.del[2] = g.t[k] - g.t[m];         tb.sgn[2] = -1.0;
             tb.del[3] = g.t[k] - g.t[m + 1];     tb.sgn[3] = 1.0;
-            for (int s = 0; s < 4; ++s) tb.lnd[s] = log(tb.del[s]);
+            for (int s = 0; s < 4; ++s) { tb.lnd[s] = log(tb.del[s]); tb.idel[s] = 1.0 / tb.del[s]; }
             return;
         }
         tb.ser = 1;
@@ -239,7 +257,7 @@ SDEV void time_block(const Geom& g, int k, int m, TimeBlock& tb)
             }
         }
     }
-    for (int s = 0; s < tb.ndel; ++s) tb.lnd[s] = log(tb.del[s]);
+    for (int s = 0; s < tb.ndel; ++s) { tb.lnd[s] = log(tb.del[s]); tb.idel[s] = 1.0 / tb.del[s]; }
 }
 
 // Separated time elements: the series at z = a/dc.
@@ -284,7 +302,7 @@ SDEV TouchVals touch(const TimeBlock& tb, double a, double alpha)
 {
     TouchVals r = {0, 0, 0, 0, 0};
     for (int s = 0; s < tb.ndel; ++s) {
-        double d = tb.del[s], z = a / d, x;
+        double d = tb.del[s], z = a * tb.idel[s], x;
         double E = e1x(z, x), sg = tb.sgn[s];
         if (NEED_V) r.v += sg * ((d + a) * E - d * x);
         if (NEED_K) r.k += sg * (d * x - a * E);
@@ -306,7 +324,7 @@ SDEV TouchH touch_h(const TimeBlock& tb, double a)
     TouchH r = {0, 0, 0, 0};
     double ia = 1.0 / a;
     for (int s = 0; s < tb.ndel; ++s) {
-        double d = tb.del[s], z = a / d, sg = tb.sgn[s];
+        double d = tb.del[s], z = a * tb.idel[s], sg = tb.sgn[s];
         double ez, E = e1x(z, ez), x = d * ez * ia;
         r.dd += sg * E;
         r.va += sg * (E - x);
@@ -329,7 +347,7 @@ SDEV SplitVals touch_split(const TimeBlock& tb, double a, double lnr, double alp
     SplitVals r = {{0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}};
     double ssum = 0.0;                          // sum of signs: 1 (d=0) or -1 (d=1)
     for (int s = 0; s < tb.ndel; ++s) {
-        double d = tb.del[s], z = a / d, sg = tb.sgn[s];
+        double d = tb.del[s], z = a * tb.idel[s], sg = tb.sgn[s];
         double x, Ez = ez_part(z, c0, tb.lnd[s], lnr, x);
         ssum += sg;
         if (NEED_V) r.v.a += sg * ((d + a) * Ez - d * x);
