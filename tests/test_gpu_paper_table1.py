@@ -1,11 +1,17 @@
 """The paper's preconditioning experiment (Sec. 4, Table 1) on the GPU path.
 
-The paper does not state its GMRES variant (restart, orthogonalisation,
-which residual is measured), so exact iteration counts are not expected to
-coincide.  What is checked is what Table 1 shows: with the opposite-order
-preconditioner the count stays bounded as the mesh is refined, without it
-the count grows; and our counts are compared with the printed ones within a
-band.  L = 2..7 (N = 64 .. 65536) fit one GPU comfortably."""
+Checked:
+- what Table 1 shows: with the opposite-order preconditioner the count stays
+  bounded as the mesh is refined, without it the count grows;
+- the unpreconditioned counts equal the printed ones within one iteration;
+- the preconditioned counts lie 0 to 4 iterations below the printed ones.
+  The paper does not state its GMRES variant; left or right
+  preconditioning, stopping on the true or the preconditioned residual, row
+  or column lumping and the full mass matrix all give counts at or below
+  ours on the oracle's matrices (L = 2, 3), none the printed 17, 18;
+- at L = 2 and 3 both counts equal the oracle's own GMRES counts
+  (tests/golden/table1_oracle_counts.txt, written from oracle/ alone).
+L = 2..7 (N = 64 .. 65536) fit one GPU comfortably."""
 import os
 
 import numpy as np
@@ -15,10 +21,11 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "table1_iterations.txt")
+ORACLE_COUNTS = os.path.join(os.path.dirname(__file__), "golden", "table1_oracle_counts.txt")
 
 
-def table1():
-    rows = [list(map(int, l.split())) for l in open(GOLD) if l.strip() and not l.startswith("#")]
+def table1(path=GOLD):
+    rows = [list(map(int, l.split())) for l in open(path) if l.strip() and not l.startswith("#")]
     return {r[0]: (r[1], r[2], r[3]) for r in rows}
 
 
@@ -47,7 +54,11 @@ def test_table1_iteration_counts():
     assert plain[-1] >= 2 * plain[0]                         # grows without preconditioner
     assert all(p < q for p, q in zip(prec[3:], plain[3:]))   # preconditioner wins on fine meshes
     for lev in range(2, 8):
-        assert abs(got[lev][1] - ref[lev][2]) <= 0.5 * ref[lev][2]
+        assert abs(got[lev][0] - ref[lev][1]) <= 1, (lev, got[lev][0], ref[lev][1])
+        assert 0 <= ref[lev][2] - got[lev][1] <= 4, (lev, got[lev][1], ref[lev][2])
+    if os.path.exists(ORACLE_COUNTS):
+        for lev, (n, plain_o, prec_o) in table1(ORACLE_COUNTS).items():
+            assert (got[lev][0], got[lev][1]) == (plain_o, prec_o), (lev, got[lev][:2], plain_o, prec_o)
     errs = [got[l][2] for l in range(2, 8)]
     assert all(b < a for a, b in zip(errs, errs[1:]))        # the flux converges under refinement
 
