@@ -1352,10 +1352,12 @@ struct VecLd {
 
 // partial[b][i] = sum_j A_b[i][j] x_m[j]: 4 waves x kRowsPerWave rows per
 // workgroup, VW-wide loads (FP64 pair, hi+lo float pair, or FP32), ACC
-// accumulation; the rows of a wave keep kRowsPerWave loads per lane in flight.
-// The matrix is streamed once per product, so its loads are non-temporal.
+// accumulation; the rows of a wave keep kRowsPerWave x CU loads per lane in
+// flight (CU column chunks per step; each row still adds its chunks in
+// column order).  The matrix is streamed once per product, so its loads are
+// non-temporal.
 constexpr int kRowsPerWave = 8;
-template <class T, int VW, class ACC, bool HILO>
+template <class T, int VW, class ACC, bool HILO, int CU = 1>
 __global__ __launch_bounds__(kWG) void k_gemv_n_vec(const T* __restrict__ A, const T* __restrict__ A2,
                                                     const double* __restrict__ x, double* __restrict__ part,
                                                     int ng, int rowchunks, long long b0)
@@ -1369,26 +1371,43 @@ __global__ __launch_bounds__(kWG) void k_gemv_n_vec(const T* __restrict__ A, con
     const long long base = b * (long long)ng * ng;
     const double* xm = x + (long long)m * ng;
     const int span = 64 * VW;
+    const int i0 = (rc * 4 + wave) * kRowsPerWave;
     ACC s[kRowsPerWave];
 #pragma unroll
     for (int rr = 0; rr < kRowsPerWave; ++rr) s[rr] = 0;
-    for (int c = lane * VW; c < ng; c += span) {
-        ACC xv[VW];
+    for (int c0 = lane * VW; c0 < ng; c0 += span * CU) {
+        VT a[CU][kRowsPerWave], a2[HILO ? CU : 1][HILO ? kRowsPerWave : 1];
+        ACC xv[CU][VW];
 #pragma unroll
-        for (int q = 0; q < VW; ++q) xv[q] = (ACC)xm[c + q];
+        for (int u = 0; u < CU; ++u) {
+            const int c = c0 + u * span;
+            if (c < ng) {
 #pragma unroll
-        for (int rr = 0; rr < kRowsPerWave; ++rr) {
-            const int i = (rc * 4 + wave) * kRowsPerWave + rr;
-            if (i < ng) {
-                const long long o = base + (long long)i * ng + c;
-                VT a = __builtin_nontemporal_load(reinterpret_cast<const VT*>(A + o));
-                if (HILO) {
-                    VT a2 = __builtin_nontemporal_load(reinterpret_cast<const VT*>(A2 + o));
+                for (int q = 0; q < VW; ++q) xv[u][q] = (ACC)xm[c + q];
 #pragma unroll
-                    for (int q = 0; q < VW; ++q) s[rr] += ((ACC)a[q] + (ACC)a2[q]) * xv[q];
-                } else {
+                for (int rr = 0; rr < kRowsPerWave; ++rr) {
+                    if (i0 + rr < ng) {
+                        const long long o = base + (long long)(i0 + rr) * ng + c;
+                        a[u][rr] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(A + o));
+                        if (HILO) a2[HILO ? u : 0][HILO ? rr : 0] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(A2 + o));
+                    }
+                }
+            }
+        }
 #pragma unroll
-                    for (int q = 0; q < VW; ++q) s[rr] += (ACC)a[q] * xv[q];
+        for (int u = 0; u < CU; ++u) {
+            if (c0 + u * span < ng) {
+#pragma unroll
+                for (int rr = 0; rr < kRowsPerWave; ++rr) {
+                    if (i0 + rr < ng) {
+                        if (HILO) {
+#pragma unroll
+                            for (int q = 0; q < VW; ++q) s[rr] += ((ACC)a[u][rr][q] + (ACC)a2[HILO ? u : 0][HILO ? rr : 0][q]) * xv[u][q];
+                        } else {
+#pragma unroll
+                            for (int q = 0; q < VW; ++q) s[rr] += (ACC)a[u][rr][q] * xv[u][q];
+                        }
+                    }
                 }
             }
         }
@@ -1398,7 +1417,7 @@ __global__ __launch_bounds__(kWG) void k_gemv_n_vec(const T* __restrict__ A, con
         ACC v = s[rr];
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-        const int i = (rc * 4 + wave) * kRowsPerWave + rr;
+        const int i = i0 + rr;
         if (lane == 0 && i < ng) part[(b - b0) * ng + i] = (double)v;
     }
 }
@@ -1766,6 +1785,7 @@ struct stbem_ctx {
     double *d_t = nullptr, *d_vx = nullptr, *d_vy = nullptr, *d_ex = nullptr, *d_ey = nullptr, *d_len = nullptr;
     double *d_ox = nullptr, *d_oy = nullptr, *d_mt = nullptr;
     double *d_m0c = nullptr, *d_m0cd = nullptr, *d_m0amax = nullptr, *d_m0it = nullptr;
+    double *d_m0ce = nullptr, *d_m0cde = nullptr, *d_m0es = nullptr;
     int m0_ksplit = 0, m0_npow = 0;   // M0 rows k >= m0_ksplit by moments of powers (none if == nt)
     int *d_m0n = nullptr, *d_v2t_loc = nullptr;
     int *d_tri = nullptr, *d_v2t_ptr = nullptr, *d_v2t = nullptr;
@@ -1889,6 +1909,7 @@ M0Poly m0poly(const stbem_ctx* c)
 {
     M0Poly p;
     p.c = c->d_m0c; p.cd = c->d_m0cd; p.n = c->d_m0n; p.amax = c->d_m0amax; p.it = c->d_m0it;
+    p.ce = c->d_m0ce; p.cde = c->d_m0cde; p.es = c->d_m0es;
     return p;
 }
 
@@ -2501,7 +2522,7 @@ int gemv_partials(stbem_ctx* c, const double* A, const float* hi, const float* l
         int rowchunks = (ng + 4 * kRowsPerWave - 1) / (4 * kRowsPerWave);
         dim3 gr((unsigned)(nb * rowchunks)), bl(kWG);
         if (A) {
-            if (vw64 == 2) hipLaunchKernelGGL((k_gemv_n_vec<double, 2, double, false>), gr, bl, 0, s, A, (const double*)nullptr, x, part, ng, rowchunks, b0);
+            if (vw64 == 2) hipLaunchKernelGGL((k_gemv_n_vec<double, 2, double, false, 2>), gr, bl, 0, s, A, (const double*)nullptr, x, part, ng, rowchunks, b0);
             else hipLaunchKernelGGL((k_gemv_n_vec<double, 1, double, false>), gr, bl, 0, s, A, (const double*)nullptr, x, part, ng, rowchunks, b0);
         } else if (hi) {
             if (vw32 == 4) hipLaunchKernelGGL((k_gemv_n_vec<float, 4, double, true>), gr, bl, 0, s, hi, lo, x, part, ng, rowchunks, b0);
@@ -2764,6 +2785,61 @@ extern "C" {
 
 const char* stbem_last_error(const stbem_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+// Chebyshev economisation of sum_{j<n} c_j a^j on [0, A] (long double):
+// rewritten in y = 2a/A - 1, expanded in Chebyshev polynomials of y,
+// truncated where the dropped coefficients sum below tol |c_0|, and written
+// back in powers of y.  Returns the number of coefficients kept, 0 if more
+// than nmax would be needed.
+static int econ_poly(const long double* c, int n, long double A, int nmax, long double tol, double* out)
+{
+    constexpr int N = kPolyMax;
+    long double d[N + 1] = {}, B[N + 1] = {}, t[N + 1];
+    const long double h = A / 2;
+    long double hp = 1;
+    for (int j = 0; j < n; ++j) {                  // a^j = h^j (y + 1)^j
+        const long double cj = c[j] * hp;
+        long double bin = 1;
+        for (int i = 0; i <= j; ++i) {
+            d[i] += cj * bin;
+            bin = bin * (j - i) / (i + 1);
+        }
+        hp *= h;
+    }
+    for (int i = n - 1; i >= 0; --i) {             // Horner in the Chebyshev basis
+        for (int k = 0; k <= N; ++k) t[k] = 0;
+        for (int k = 0; k < N; ++k) {              // y T_0 = T_1, y T_k = (T_{k+1} + T_{k-1}) / 2
+            if (k == 0) t[1] += B[0];
+            else { t[k + 1] += 0.5L * B[k]; t[k - 1] += 0.5L * B[k]; }
+        }
+        t[0] += d[i];
+        for (int k = 0; k <= N; ++k) B[k] = t[k];
+    }
+    int K = n;
+    long double drop = 0;
+    while (K > 1 && drop + fabsl(B[K - 1]) < tol * fabsl(c[0])) { drop += fabsl(B[K - 1]); --K; }
+    if (K > nmax) return 0;
+    long double P[N + 1] = {}, Tm[N + 1] = {}, Tc[N + 1] = {}, Tn[N + 1];
+    Tm[0] = 1; Tc[1] = 1;
+    for (int i = 0; i <= N; ++i) P[i] = B[0] * Tm[i] + (K > 1 ? B[1] * Tc[i] : 0.0L);
+    for (int k = 2; k < K; ++k) {                  // T_{k} = 2 y T_{k-1} - T_{k-2}
+        for (int i = 0; i <= N; ++i) Tn[i] = (i > 0 ? 2 * Tc[i - 1] : 0.0L) - Tm[i];
+        for (int i = 0; i <= N; ++i) { P[i] += B[k] * Tn[i]; Tm[i] = Tc[i]; Tc[i] = Tn[i]; }
+    }
+    for (int i = 0; i < nmax; ++i) out[i] = i < K ? (double)P[i] : 0.0;
+    // the double polynomial against the series, at 65 points of [0, A]
+    const double es = (double)(2.0L / A);
+    for (int q = 0; q <= 64; ++q) {
+        const long double a = A * q / 64;
+        long double ref = 0;
+        for (int j = n - 1; j >= 0; --j) ref = ref * a + c[j];
+        const double y = std::fma((double)a, es, -1.0);
+        double got = out[nmax - 1];
+        for (int i = nmax - 2; i >= 0; --i) got = std::fma(got, y, out[i]);
+        if (fabsl((long double)got - ref) > 1e-15L * fabsl(c[0])) return 0;
+    }
+    return K;
+}
+
 int stbem_create(const stbem_problem* p, stbem_ctx** out)
 {
     if (!p || !out) return STBEM_EINVAL;
@@ -2896,7 +2972,8 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
         double amax = 0.25 * c->alpha * R2;
         std::vector<double> cf((size_t)c->nt * kPolyMax, 0.0), cfd((size_t)c->nt * kPolyMax, 0.0);
         std::vector<int> nn(c->nt, 0);
-        std::vector<double> am(c->nt, 0.0), it(c->nt + 1, 0.0);
+        std::vector<double> am(c->nt, 0.0), it(c->nt + 1, 0.0), es(c->nt, 0.0);
+        std::vector<double> ce((size_t)c->nt * kEconMax, 0.0), cde((size_t)c->nt * kEconMax, 0.0);
         for (int k = 1; k <= c->nt; ++k) it[k] = 1.0 / c->t[k];
         for (int k = 1; k < c->nt; ++k) {
             long double t0 = c->t[k], t1 = c->t[k + 1], h = (long double)c->t[k + 1] - (long double)c->t[k];
@@ -2904,7 +2981,9 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
             am[k] = amk;
             double* co = &cf[(size_t)k * kPolyMax];
             double* cd = &cfd[(size_t)k * kPolyMax];
-            co[0] = cd[0] = (double)logl(t1 / t0);
+            long double cl[kPolyMax], cdl[kPolyMax];
+            cl[0] = cdl[0] = logl(t1 / t0);
+            co[0] = cd[0] = (double)cl[0];
             long double fact = 1, sum = 0, pw1 = 1, pw0 = 1;   // sum = sum_j t1^j t0^(n-1-j)
             int n = 1;
             bool conv = false;
@@ -2915,12 +2994,20 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
                 fact *= n;
                 long double en = -h * sum / (pw1 * pw0) / fact;  // (t1^-n - t0^-n)/n!
                 long double sg = (n & 1) ? 1.0L : -1.0L;       // (-1)^{n+1}
-                co[n] = (double)(sg * en / n);
-                cd[n] = (double)(sg * en * (1.0L / n + 1.0L));
+                cl[n] = sg * en / n;
+                cdl[n] = sg * en * (1.0L / n + 1.0L);
+                co[n] = (double)cl[n];
+                cd[n] = (double)cdl[n];
                 long double tail = powl(amk / t0, n) / fact;
                 if (tail < 1e-18L * fabsl((long double)co[0]) && n > 2) { ++n; conv = true; break; }
             }
             nn[k] = conv ? n : 0;      // not converged: the E1 path is used
+            if (nn[k] > 0) {
+                es[k] = (double)(2.0L / amk);
+                if (!econ_poly(cl, n, amk, kEconMax, 1e-18L, &ce[(size_t)k * kEconMax]) ||
+                    !econ_poly(cdl, n, amk, kEconMax, 1e-18L, &cde[(size_t)k * kEconMax]))
+                    nn[k] = 0;
+            }
         }
         // rows whose series covers every pair (amax reached) from ksplit on
         c->m0_ksplit = c->nt;
@@ -2929,7 +3016,8 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
         for (int k = c->m0_ksplit; k < c->nt; ++k) c->m0_npow = std::max(c->m0_npow, nn[k]);
         int rc2 = 0;
         if ((rc2 = upload(c, &c->d_m0c, cf)) || (rc2 = upload(c, &c->d_m0cd, cfd)) || (rc2 = upload(c, &c->d_m0n, nn)) ||
-            (rc2 = upload(c, &c->d_m0amax, am)) || (rc2 = upload(c, &c->d_m0it, it))) {
+            (rc2 = upload(c, &c->d_m0amax, am)) || (rc2 = upload(c, &c->d_m0it, it)) ||
+            (rc2 = upload(c, &c->d_m0ce, ce)) || (rc2 = upload(c, &c->d_m0cde, cde)) || (rc2 = upload(c, &c->d_m0es, es))) {
             stbem_destroy(c);
             return rc2;
         }
@@ -2943,7 +3031,7 @@ int stbem_destroy(stbem_ctx* c)
     if (!c) return STBEM_OK;
     for (int s = 0; s < 7; ++s) dev_free(c, c->mat[s]);
     free_f32(c, true, true);
-    void* own[] = {c->d_t, c->d_vx, c->d_vy, c->d_ex, c->d_ey, c->d_len, c->d_ox, c->d_oy, c->d_mt, c->d_m0c, c->d_m0cd, c->d_m0n, c->d_m0amax, c->d_m0it, c->d_v2t_loc,
+    void* own[] = {c->d_t, c->d_vx, c->d_vy, c->d_ex, c->d_ey, c->d_len, c->d_ox, c->d_oy, c->d_mt, c->d_m0c, c->d_m0cd, c->d_m0n, c->d_m0amax, c->d_m0it, c->d_m0ce, c->d_m0cde, c->d_m0es, c->d_v2t_loc,
                    c->d_tri, c->d_v2t_ptr, c->d_v2t, c->d_tab, c->d_m0tab, c->part, c->d_tbs, c->d_tbs32, c->wvec,
                    c->gm_q, c->gm_part, c->gm_h, c->gm_v};
     for (void* p : own) if (p) (void)hipFree(p);

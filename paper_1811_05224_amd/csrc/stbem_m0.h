@@ -37,7 +37,14 @@ struct Mesh2 {
 constexpr int kPolyMax = 40;
 // Per time element k >= 1: coefficients of the series in a (c[k][0] = cd[k][0]
 // = ln(t_{k+1}/t_k)), their count, the range a <= amax[k]; it[k] = 1/t_k.
-struct M0Poly { const double* c; const double* cd; const int* n; const double* amax; const double* it; };   // [nt][kPolyMax], [nt], [nt], [nt+1]
+// ce, cde: the same polynomials economised on [0, amax[k]] (Chebyshev
+// truncation, written in powers of y = a es[k] - 1, es[k] = 2/amax[k]),
+// evaluated per pair; c, cd stay for the moment form of the late rows.
+constexpr int kEconMax = 24;
+struct M0Poly {
+    const double* c; const double* cd; const int* n; const double* amax; const double* it;   // [nt][kPolyMax], [nt], [nt], [nt+1]
+    const double* ce; const double* cde; const double* es;                                  // [nt][kEconMax], [nt]
+};
 
 // G_k (or its alpha-derivative) at r^2
 template <bool DERIV>
@@ -111,14 +118,14 @@ SDEV double seg_tri_dist(const Piece& S, const Tri& tr)
 
 struct M0Orders { int qs_near, qt_near; double near_ratio, omax, q_tol, z_floor; };
 
-// Horner over the full zero-padded coefficient row (leading zeros leave it
-// unchanged), unrolled so that the coefficient loads are issued ahead
-SDEV double m0_poly(const double* c, int, double a)
+// Horner in y over the full zero-padded economised row (leading zeros leave
+// it unchanged), unrolled so that the coefficient loads are issued ahead
+SDEV double m0_econ(const double* p, double y)
 {
-    double p = c[kPolyMax - 1];
+    double s = p[kEconMax - 1];
 #pragma unroll
-    for (int q = kPolyMax - 2; q >= 0; --q) p = p * a + c[q];
-    return p;
+    for (int q = kEconMax - 2; q >= 0; --q) s = fma(s, y, p[q]);
+    return s;
 }
 
 // ------------------------------------------------ per-triangle moments
@@ -246,7 +253,7 @@ SDEV void m0_row_values(const Geom& g, const M0Poly& PP, int k0, int nr, double 
         if (r >= nr) continue;
         const int k = k0 + r;
         if (PP.n[k] > 0 && a <= PP.amax[k]) {
-            val[r] = sc * m0_poly((DERIV ? PP.cd : PP.c) + (long long)k * kPolyMax, PP.n[k], a);
+            val[r] = sc * m0_econ((DERIV ? PP.cde : PP.ce) + (long long)k * kEconMax, fma(a, PP.es[k], -1.0));
             have = 0;
             continue;
         }
@@ -356,11 +363,11 @@ SDEV void m0_tri_moments(const Tables& T, const M0Tables& D, const M0Orders& MO,
     }
     const int n = PP.n[k];
     if (n > 0) {
-        const double* c = (DERIV ? PP.cd : PP.c) + (long long)k * kPolyMax;
-        const double amax = PP.amax[k], q4 = 0.25 * g.alpha, sc = (DERIV ? 1.0 : g.alpha) * kInv4Pi;
+        const double* c = (DERIV ? PP.cde : PP.ce) + (long long)k * kEconMax;
+        const double amax = PP.amax[k], es = PP.es[k], q4 = 0.25 * g.alpha, sc = (DERIV ? 1.0 : g.alpha) * kInv4Pi;
         m0_regular3(T, S, tr, qs, qs, [&](double r2) {
             double a = q4 * r2;
-            return a <= amax ? sc * m0_poly(c, n, a) : m0_kernel<DERIV>(g, PP, k, r2);
+            return a <= amax ? sc * m0_econ(c, fma(a, es, -1.0)) : m0_kernel<DERIV>(g, PP, k, r2);
         }, out);
         return;
     }
