@@ -298,7 +298,7 @@ __device__ __forceinline__ void far_pair(const Tables& T, const TimeBlock& tb, d
         const double wP = P[4] * T.gl_w[Q][a];
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
-            const double e = exp(-z[c]);
+            const double e = exp_neg(z[c], T.ex2);
             const double wq = wP * Qs[4] * T.gl_w[Q][c];
             if (OP == OP_V) {
                 m0 += wq * e * acc[c];
@@ -469,7 +469,7 @@ __device__ __forceinline__ void far_dpair(const Tables& T, const TimeBlock& tb, 
         double r0 = 0, r1s = 0, rv = 0, ra0 = 0, ra1 = 0, rb = 0;
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
-            const double e = exp(-z[c]);
+            const double e = exp_neg(z[c], T.ex2);
             const double kap = e * fma(zt[c], s2[c], fma(fk, sk[c], fd * sd[c]));
             const double xc = T.gl_x[Q][c], wq = Qs[4] * T.gl_w[Q][c];
             const double w = wq * kap;
@@ -535,7 +535,7 @@ __device__ __forceinline__ double far_kpair(const Tables& T, const TimeBlock& tb
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
             const double xc = T.gl_x[Q][c], wq = Qs[4] * T.gl_w[Q][c];
-            const double g = wq * exp(-z[c]) * sk[c] * dn[c];
+            const double g = wq * exp_neg(z[c], T.ex2) * sk[c] * dn[c];
             r = fma(g, ORI == 0 ? 0.5 * (hq + xc) : 1.0, r);
         }
         acc = fma(ORI == 0 ? wP : wP * 0.5 * (hp + xa), r, acc);
@@ -2069,20 +2069,21 @@ void launch_knear(stbem_ctx* c, int slot, double* o, hipStream_t s)
 }
 
 // Algorithmic operation counts of the far-field (series) kernels, FMA = 2,
-// an FP64 exponential = 29 (range reduction, degree-11 polynomial, scaling),
-// counted from the kernels' arithmetic for the lanes that do work:
+// an FP64 exponential (exp_neg) = 19 (argument reduction 7, degree-5
+// polynomial 10, table factor and scaling 2), counted from the kernels'
+// arithmetic for the lanes that do work:
 //   far_pair (V_h, K_h, dV_h, dK_h; one segment pair per lane): per row of
-//     Q nodes 5; per node pair V 13 + 35 after the series, dV 14 + 38,
-//     K 18 + 39, dK 17 + 39; per series term and node pair V and dK 12, K and
+//     Q nodes 5; per node pair V 13 + 25 after the series, dV 14 + 28,
+//     K 18 + 29, dK 17 + 29; per series term and node pair V and dK 12, K and
 //     dV 14 (two recurrence steps of 5, sums 2 or 4)
 //   far_dpair (D_h; one half-piece pair): 21 per pair; per row 19 (WV) or
-//     17; per node pair 25 + 45 (WV) or 42 after the series; per term 22 (WV)
+//     17; per node pair 25 + 35 (WV) or 32 after the series; per term 22 (WV)
 //     or 20; per stored D_h entry of a tile 196 to combine 16 pairs (+3 V_h)
 // sum_nterm is the sum of the series terms of the launched blocks.
 double flops_vkfar(int op, int Q, long long nblk, long long sum_nterm, long long lanes_per_block)
 {
     const double q2 = (double)Q * Q;
-    const double node = op == OP_V ? 48.0 : op == OP_DV ? 52.0 : op == OP_K ? 57.0 : 56.0;
+    const double node = op == OP_V ? 38.0 : op == OP_DV ? 42.0 : op == OP_K ? 47.0 : 46.0;
     const double term = op == OP_V || op == OP_DK ? 12.0 : 14.0;
     return (double)lanes_per_block * ((double)nblk * (5.0 * Q + q2 * (node - term) + 5.0) + term * q2 * (double)sum_nterm);
 }
@@ -2092,7 +2093,7 @@ double flops_dfar(int Q, bool wv, long long nblk, long long sum_nterm, long long
 {
     const double q2 = (double)Q * Q;
     const double pw = wv ? 1024.0 : 0.0, pp = wv ? 132.0 : 1156.0;       // pairs per tile with / without V_h
-    double per_pair_wv = 21.0 + 19.0 * Q + q2 * (70.0 - 22.0), per_pair = 21.0 + 17.0 * Q + q2 * (67.0 - 20.0);
+    double per_pair_wv = 21.0 + 19.0 * Q + q2 * (60.0 - 22.0), per_pair = 21.0 + 17.0 * Q + q2 * (57.0 - 20.0);
     const double tiles = (double)tiles_per_blk;
     double kborder = 0.0;
     if (wk) {

@@ -53,7 +53,27 @@ struct Tables {
     double gl_w[kMaxGL + 1][kMaxGL];
     double lg_x[kMaxLog + 1][kMaxLog];
     double lg_w[kMaxLog + 1][kMaxLog];
+    double ex2[64];                       // 2^(-j/64), j = 0..63 (exp_neg)
 };
+
+// e^{-z} for z >= 0 by the table-driven method of Tang (1989): with
+// z = (64 m + j) ln2/64 + r, |r| <= ln2/128, e^{-z} = 2^{-m} 2^{-j/64} e^{-r},
+// e^{-r} from its degree-5 Taylor polynomial (remainder < 4e-17).  ln2/64 is
+// split in a 36-bit head and a tail so that k ln2/64 is subtracted exactly.
+// Arguments beyond 2^24 ln2/64 (where e^{-z} is 0 in double) are clamped
+// before the integer conversion; the scaling by 2^{-m} then underflows to 0.
+constexpr double kLn2o64Hi = 0x1.62e42fefa0000p-7;
+constexpr double kLn2o64Lo = 2.572804622327669e-14;
+constexpr double k64oLn2 = 92.33248261689366;
+SDEV double exp_neg(double z, const double* ex2)
+{
+    const double k = fmin(rint(z * k64oLn2), 16777216.0);
+    double r = fma(-k, kLn2o64Hi, z);
+    r = fma(-k, kLn2o64Lo, r);
+    const double p = fma(fma(fma(fma(fma(-1.0 / 120.0, r, 1.0 / 24.0), r, -1.0 / 6.0), r, 0.5), r, -1.0), r, 1.0);
+    const int ki = (int)k;
+    return ldexp(ex2[ki & 63] * p, -(ki >> 6));
+}
 
 // Geometry of Gamma_h (closed CCW polygon) and the time grid.
 struct Geom {
