@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc", "stbem.hip")
 LIB = os.path.join(HERE, "libstbem.so")
-HEADERS = ["stbem_math.h", "stbem_m0.h", "stbem_tables.h", "loggauss_table.h", "e1_poly_table.h"]
+HEADERS = ["stbem_math.h", "stbem_m0.h", "stbem_tables.h", "loggauss_table.h", "e1_poly_table.h", "exp2_table.h"]
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

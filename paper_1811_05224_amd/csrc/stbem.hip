@@ -369,7 +369,7 @@ __global__ __launch_bounds__(kWG) void k_assemble_vkfar(Geom g, const Tables* __
 // takes the rising moment of segment j-1 from the lane to its left.  Per hat
 // this is one segment pair instead of two.
 template <int OP>
-__global__ __launch_bounds__(kWG) void k_assemble_knear(Geom g, const Tables* __restrict__ Tg, Orders O,
+__global__ __launch_bounds__(kWG, 3) void k_assemble_knear(Geom g, const Tables* __restrict__ Tg, Orders O,
                                                         const int* __restrict__ blist, int tiles_i, int tiles_j,
                                                         double* __restrict__ out64)
 {

@@ -240,7 +240,7 @@ SDEV void seg_log_potential3(const M0Tables& D, const Piece& S, const Tri3& tr, 
 // computed once instead of twice; rows inside their power-series range take
 // the series.  Row r's three moments go to out[3r .. 3r+2].  Every row gets
 // the same operations, in the same order, as with the per-row kernel.
-constexpr int kM0Group = 4;
+constexpr int kM0Group = 2;     // of 2, 3, 4 and 8 rows, 2 was fastest (no VGPR spills)
 
 template <bool DERIV>
 SDEV void m0_row_values(const Geom& g, const M0Poly& PP, int k0, int nr, double r2, double* val)

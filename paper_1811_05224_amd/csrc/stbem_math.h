@@ -32,6 +32,7 @@
 #include <math.h>
 
 #include "e1_poly_table.h"
+#include "exp2_table.h"
 
 #define SDEV __host__ __device__ __forceinline__
 

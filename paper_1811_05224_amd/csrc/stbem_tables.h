@@ -32,7 +32,7 @@ inline void build_tables(Tables& T)
     }
     for (int n = 0; n <= kMaxLog; ++n)
         for (int i = 0; i < kMaxLog; ++i) { T.lg_x[n][i] = kLogGaussX[n][i]; T.lg_w[n][i] = kLogGaussW[n][i]; }
-    for (int j = 0; j < 64; ++j) T.ex2[j] = (double)exp2l(-j / 64.0L);
+    for (int j = 0; j < 64; ++j) T.ex2[j] = kEx2[j];
 }
 
 }  // namespace stbem
