@@ -2321,19 +2321,22 @@ int launch_dfar32(stbem_ctx* c, const int* bl, OutBuf od, hipStream_t s)
     const int t1 = (c->ng + kTile - 1) / kTile;
     const long long tiles = tiles_per_block(t1, true);
     const int step = blocks_per_launch(tiles);
+    // The blocks of the FP64 rule q take q - 1 points per direction: the FP32
+    // entries need about 1e-7 of the block maximum, which the shorter rule
+    // still meets (the FP64 orders are set for 1e-15).
     for (int q = 3; q <= 8; ++q) {
         for (int off = 0; off < c->nlist_far[2][q]; off += step) {
             const int n = std::min(step, c->nlist_far[2][q] - off);
             dim3 gr((unsigned)(n * tiles)), blk(kWG);
             const int* b2 = bl + off;
-            KTimer kt(c, (std::string("k_assemble_dfar32<") + std::to_string(q) + ">").c_str(), (double)n * c->ng * c->ng, s);
+            KTimer kt(c, (std::string("k_assemble_dfar32<") + std::to_string(q - 1) + ">").c_str(), (double)n * c->ng * c->ng, s);
             switch (q) {
-            case 3: hipLaunchKernelGGL((k_assemble_dfar32<3>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
-            case 4: hipLaunchKernelGGL((k_assemble_dfar32<4>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
-            case 5: hipLaunchKernelGGL((k_assemble_dfar32<5>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
-            case 6: hipLaunchKernelGGL((k_assemble_dfar32<6>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
-            case 7: hipLaunchKernelGGL((k_assemble_dfar32<7>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
-            default: hipLaunchKernelGGL((k_assemble_dfar32<8>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
+            case 3: hipLaunchKernelGGL((k_assemble_dfar32<2>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
+            case 4: hipLaunchKernelGGL((k_assemble_dfar32<3>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
+            case 5: hipLaunchKernelGGL((k_assemble_dfar32<4>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
+            case 6: hipLaunchKernelGGL((k_assemble_dfar32<5>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
+            case 7: hipLaunchKernelGGL((k_assemble_dfar32<6>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
+            default: hipLaunchKernelGGL((k_assemble_dfar32<7>), gr, blk, 0, s, geom(c), c->d_tab, b2, t1, od, c->d_tbs32); break;
             }
         }
         bl += c->nlist_far[2][q];
