@@ -242,6 +242,9 @@ SDEV void seg_log_potential3(const M0Tables& D, const Piece& S, const Tri3& tr, 
 // the same operations, in the same order, as with the per-row kernel.
 constexpr int kM0Group = 2;     // of 2, 3, 4 and 8 rows, 2 was fastest (no VGPR spills)
 
+// Ein out of line for the rows' rare small-argument branch (see e1t_large)
+__host__ __device__ __attribute__((noinline)) inline double ein_cold(double z) { return ein(z); }
+
 template <bool DERIV>
 SDEV void m0_row_values(const Geom& g, const M0Poly& PP, int k0, int nr, double r2, double* val)
 {
@@ -260,16 +263,16 @@ SDEV void m0_row_values(const Geom& g, const M0Poly& PP, int k0, int nr, double 
         const double z1 = a * PP.it[k + 1], z0 = a * PP.it[k];
         double dE, x1 = 0.0, x0 = 0.0;
         if (z0 <= 2.0) {
-            const double e0 = have == 2 ? einprev : ein(z0);
-            const double e1v = ein(z1);
+            const double e0 = have == 2 ? einprev : ein_cold(z0);
+            const double e1v = ein_cold(z1);
             dE = PP.c[(long long)k * kPolyMax] + e1v - e0;    // ln(t1/t0): no ln a cancellation
             if (DERIV) { x1 = exp(-z1); x0 = have == 2 ? xprev : exp(-z0); }
             einprev = e1v; xprev = x1; have = 2;
         } else {
             double E0;
             if (have == 1) { E0 = Eprev; x0 = xprev; }
-            else E0 = e1t<DERIV>(z0, x0);
-            const double E1v = e1t<DERIV>(z1, x1);
+            else E0 = e1t_large<DERIV>(z0, x0);
+            const double E1v = e1t_large<DERIV>(z1, x1);
             dE = E1v - E0;
             Eprev = E1v; xprev = x1; have = 1;
         }

@@ -169,6 +169,22 @@ SDEV double e1t(double z, double& ex)
 }
 
 SDEV double e1x(double z, double& ex) { return e1t<true>(z, ex); }
+
+// E1 for callers whose arguments are nearly always > 2: the branch z <= 2
+// (its 24 series constants) is kept out of line, so that it holds no
+// registers in the caller's loops.
+template <bool EX>
+__host__ __device__ __attribute__((noinline)) double e1_small(double z, double& ex)
+{
+    if (EX) ex = exp(-z);
+    return -kEuler - log(z) + ein(z);
+}
+template <bool EX>
+SDEV double e1t_large(double z, double& ex)
+{
+    if (z <= 2.0) return e1_small<EX>(z, ex);
+    return e1t<EX>(z, ex);
+}
 SDEV double e1(double z)
 {
     double ex;
