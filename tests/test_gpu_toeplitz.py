@@ -126,8 +126,9 @@ def test_rhs_with_chunked_m0_equals_stored():
 def test_table1_level8_block_toeplitz():
     """Table 1, L = 8 (1024 segments x 256 steps, N = 262144, alpha = 10):
     the paper reports 91 GMRES iterations without and 19 with the
-    preconditioner (relative precision 1e-8).  As for L = 2..7 the counts
-    are compared within a band; the flux error keeps falling."""
+    preconditioner (relative precision 1e-8).  As for L = 2..7: the
+    unpreconditioned count within one of the paper's, the preconditioned one
+    0 to 4 below it; the flux error keeps falling."""
     import paper_1811_05224_amd as P
     from paper_1811_05224_amd import _lib as L
     wl = W.paper_level(8)
@@ -141,8 +142,8 @@ def test_table1_level8_block_toeplitz():
     w, i12 = c.solve(f, tol=1e-12, max_it=400)
     err = np.linalg.norm(w.cpu().numpy() - wl.w_ref) / np.linalg.norm(wl.w_ref)
     print(f"L=8 N={c.n}: GMRES {inp.iters} (paper 91), preconditioned {ip.iters} (paper 19), flux error {err:.3e}")
-    assert abs(ip.iters - 19) <= 0.5 * 19
+    assert 0 <= 19 - ip.iters <= 4
     assert ip.iters < inp.iters
-    assert abs(inp.iters - 91) <= 0.25 * 91
+    assert abs(inp.iters - 91) <= 1
     assert err < 1.4e-4      # below the L = 7 error (1.4e-4)
     c.close()
