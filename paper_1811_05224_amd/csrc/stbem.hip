@@ -135,6 +135,15 @@ struct TimeBlock32 {
     float st[kMaxTerms][12];
 };
 
+// gam_j of the rescaled Laguerre recurrence (time_block): gam_0 = gam_1 = 1,
+// gam_{j+1} = j/(j+1) gam_{j-1}, i.e. prod over i = j-1, j-3, ... >= 1 of i/(i+1)
+__device__ double lag_gamma(int j)
+{
+    double g = 1.0;
+    for (int i = (j % 2 == 0) ? 1 : 2; i < j; i += 2) g *= (double)i / (i + 1);
+    return g;
+}
+
 __global__ __launch_bounds__(kWG) void k_time_blocks32(Geom g, long long nb, TimeBlock32* __restrict__ out)
 {
     const long long b = (long long)blockIdx.x * kWG + threadIdx.x;
@@ -166,16 +175,18 @@ __global__ __launch_bounds__(kWG) void k_time_blocks32(Geom g, long long nb, Tim
         const double hc1 = e + 1 < n ? hc : 0.0;
         kc += cn;
         hc += kc;
+        // the rescaled recurrence of time_block: L_m = gam_m P_m
+        const double g0 = lag_gamma(2 * e), g1 = lag_gamma(2 * e + 1);
         float* st = tb.st[e];
-        st[6] = (float)kc; st[7] = (float)kc1; st[8] = (float)hc; st[9] = (float)hc1;
-        st[10] = (float)((2.0 * e + 1.0) * cn);
-        st[11] = (float)cn;
+        st[6] = (float)(kc * g0); st[7] = (float)(kc1 * g1); st[8] = (float)(hc * g0); st[9] = (float)(hc1 * g1);
+        st[10] = (float)((2.0 * e + 1.0) * cn * g1);
+        st[11] = (float)(cn * g0);
         for (int h = 0; h < 2; ++h) {
             const int j = 2 * e - 1 + h;
-            const double bb = j >= 0 ? 1.0 / (j + 1.0) : 0.0;
-            st[3 * h] = (float)((2.0 * j + 1.0) * bb);
-            st[3 * h + 1] = (float)bb;
-            st[3 * h + 2] = (float)(j * bb);
+            const double r = j >= 1 ? lag_gamma(j) / lag_gamma(j + 1) / (j + 1.0) : 0.0;
+            st[3 * h] = (float)((2.0 * j + 1.0) * r);
+            st[3 * h + 1] = (float)r;
+            st[3 * h + 2] = 0.0f;
         }
     }
 }
@@ -287,8 +298,8 @@ __device__ __forceinline__ void far_pair(const Tables& T, const TimeBlock& tb, d
             const double* st = tb.st[n];
 #pragma unroll
             for (int c = 0; c < Q; ++c) {
-                const double x2 = fma(fma(-st[1], z[c], st[0]), l1[c], -st[2] * l0[c]);
-                const double x3 = fma(fma(-st[4], z[c], st[3]), x2, -st[5] * l1[c]);
+                const double x2 = fma(fma(-st[1], z[c], st[0]), l1[c], -l0[c]);
+                const double x3 = fma(fma(-st[4], z[c], st[3]), x2, -l1[c]);
                 if (OP == OP_V) acc[c] = fma(st[11], x2, acc[c]);
                 else if (OP == OP_DK) acc[c] = fma(st[10], x3, acc[c]);
                 else acc[c] = fma(st[7], x3, fma(st[6], x2, acc[c]));
@@ -457,8 +468,8 @@ __device__ __forceinline__ void far_dpair(const Tables& T, const TimeBlock& tb, 
             const double* st = tb.st[n];
 #pragma unroll
             for (int c = 0; c < Q; ++c) {
-                const double x2 = fma(fma(-st[1], z[c], st[0]), l1[c], -st[2] * l0[c]);
-                const double x3 = fma(fma(-st[4], z[c], st[3]), x2, -st[5] * l1[c]);
+                const double x2 = fma(fma(-st[1], z[c], st[0]), l1[c], -l0[c]);
+                const double x3 = fma(fma(-st[4], z[c], st[3]), x2, -l1[c]);
                 sk[c] = fma(st[7], x3, fma(st[6], x2, sk[c]));
                 s2[c] = fma(st[9], x3, fma(st[8], x2, s2[c]));
                 sd[c] = fma(st[10], x3, sd[c]);
@@ -525,8 +536,8 @@ __device__ __forceinline__ double far_kpair(const Tables& T, const TimeBlock& tb
             const double* st = tb.st[n];
 #pragma unroll
             for (int c = 0; c < Q; ++c) {
-                const double x2 = fma(fma(-st[1], z[c], st[0]), l1[c], -st[2] * l0[c]);
-                const double x3 = fma(fma(-st[4], z[c], st[3]), x2, -st[5] * l1[c]);
+                const double x2 = fma(fma(-st[1], z[c], st[0]), l1[c], -l0[c]);
+                const double x3 = fma(fma(-st[4], z[c], st[3]), x2, -l1[c]);
                 sk[c] = fma(st[7], x3, fma(st[6], x2, sk[c]));
                 l0[c] = x2; l1[c] = x3;
             }
@@ -707,8 +718,8 @@ __device__ __forceinline__ void far_dpair32(const Tables& T, const TimeBlock32& 
             const float* st = tb.st[n];
 #pragma unroll
             for (int c = 0; c < Q; ++c) {
-                const float x2 = fmaf(fmaf(-st[1], z[c], st[0]), l1[c], -st[2] * l0[c]);
-                const float x3 = fmaf(fmaf(-st[4], z[c], st[3]), x2, -st[5] * l1[c]);
+                const float x2 = fmaf(fmaf(-st[1], z[c], st[0]), l1[c], -l0[c]);
+                const float x3 = fmaf(fmaf(-st[4], z[c], st[3]), x2, -l1[c]);
                 sk[c] = fmaf(st[7], x3, fmaf(st[6], x2, sk[c]));
                 s2[c] = fmaf(st[9], x3, fmaf(st[8], x2, s2[c]));
                 sd[c] = fmaf(st[10], x3, sd[c]);
@@ -2074,17 +2085,17 @@ void launch_knear(stbem_ctx* c, int slot, double* o, hipStream_t s)
 // arithmetic for the lanes that do work:
 //   far_pair (V_h, K_h, dV_h, dK_h; one segment pair per lane): per row of
 //     Q nodes 5; per node pair V 13 + 25 after the series, dV 14 + 28,
-//     K 18 + 29, dK 17 + 29; per series term and node pair V and dK 12, K and
-//     dV 14 (two recurrence steps of 5, sums 2 or 4)
+//     K 18 + 29, dK 17 + 29; per series term and node pair V and dK 10, K and
+//     dV 12 (two rescaled recurrence steps of 4, sums 2 or 4)
 //   far_dpair (D_h; one half-piece pair): 21 per pair; per row 19 (WV) or
-//     17; per node pair 25 + 35 (WV) or 32 after the series; per term 22 (WV)
-//     or 20; per stored D_h entry of a tile 196 to combine 16 pairs (+3 V_h)
+//     17; per node pair 25 + 35 (WV) or 32 after the series; per term 20 (WV)
+//     or 18; per stored D_h entry of a tile 196 to combine 16 pairs (+3 V_h)
 // sum_nterm is the sum of the series terms of the launched blocks.
 double flops_vkfar(int op, int Q, long long nblk, long long sum_nterm, long long lanes_per_block)
 {
     const double q2 = (double)Q * Q;
     const double node = op == OP_V ? 38.0 : op == OP_DV ? 42.0 : op == OP_K ? 47.0 : 46.0;
-    const double term = op == OP_V || op == OP_DK ? 12.0 : 14.0;
+    const double term = op == OP_V || op == OP_DK ? 10.0 : 12.0;
     return (double)lanes_per_block * ((double)nblk * (5.0 * Q + q2 * (node - term) + 5.0) + term * q2 * (double)sum_nterm);
 }
 
@@ -2093,19 +2104,19 @@ double flops_dfar(int Q, bool wv, long long nblk, long long sum_nterm, long long
 {
     const double q2 = (double)Q * Q;
     const double pw = wv ? 1024.0 : 0.0, pp = wv ? 132.0 : 1156.0;       // pairs per tile with / without V_h
-    double per_pair_wv = 21.0 + 19.0 * Q + q2 * (60.0 - 22.0), per_pair = 21.0 + 17.0 * Q + q2 * (57.0 - 20.0);
+    double per_pair_wv = 21.0 + 19.0 * Q + q2 * (60.0 - 20.0), per_pair = 21.0 + 17.0 * Q + q2 * (57.0 - 18.0);
     const double tiles = (double)tiles_per_blk;
     double kborder = 0.0;
     if (wk) {
         // K_h moments: per node pair 20 (normal components 6, weight 2,
         // shape 2, four moments 10), per row 12; border pairs (64 per tile,
-        // 128 off the diagonal): per node pair 20 + 14 per series term, per row 4
+        // 128 off the diagonal): per node pair 20 + 12 per series term, per row 4
         per_pair_wv += 12.0 * Q + 20.0 * q2;
         const double border = 64.0 + 128.0 * (tiles - 1.0) / tiles;
-        kborder = tiles * border * ((double)nblk * (4.0 * Q + 20.0 * q2) + 14.0 * q2 * (double)sum_nterm);
+        kborder = tiles * border * ((double)nblk * (4.0 * Q + 20.0 * q2) + 12.0 * q2 * (double)sum_nterm);
     }
-    return tiles * (pw * ((double)nblk * per_pair_wv + 22.0 * q2 * (double)sum_nterm) +
-                    pp * ((double)nblk * per_pair + 20.0 * q2 * (double)sum_nterm)) + kborder +
+    return tiles * (pw * ((double)nblk * per_pair_wv + 20.0 * q2 * (double)sum_nterm) +
+                    pp * ((double)nblk * per_pair + 18.0 * q2 * (double)sum_nterm)) + kborder +
            (double)nblk * (double)owned_per_blk * (wv ? (wk ? 215.0 : 199.0) : 196.0);
 }
 

@@ -214,13 +214,16 @@ struct TimeBlock {
     int ndel;
     double dc, inv_dc;    // centre distance (separated)
     double w2;            // alpha / (4 smallest lag): z = w2 r^2 bounds a / delta
-    // Series step n (n >= 1 advances L_{2n-1} -> L_{2n} -> L_{2n+1}; n = 0
-    // holds the coefficients of L_0, L_1), with L_{j+1} = (A_j - B_j z) L_j - C_j L_{j-1}:
-    //   st[n][0..2] = A, B, C for j = 2n - 1      st[n][3..5] = A, B, C for j = 2n
+    // Series step n (n >= 1 advances P_{2n-1} -> P_{2n} -> P_{2n+1}; n = 0
+    // holds the coefficients of P_0 = L_0, P_1 = L_1), with the rescaled
+    // Laguerre polynomials P_j = L_j / gam_j, P_{j+1} = (a_j - b_j z) P_j - P_{j-1}:
+    //   st[n][0..1] = a, b for j = 2n - 1         st[n][3..4] = a, b for j = 2n
     //   st[n][6..7] = kc_{2n}, kc_{2n+1}          st[n][8..9] = hc_{2n}, hc_{2n+1}
     //   st[n][10]   = (2n + 1) c_n                st[n][11]   = c_n
-    // where c_n = mu_2n / dc^2n and kc, hc are the coefficients of L_m in
-    // sum_n c_n L^(1)_2n and sum_n c_n L^(2)_2n (tail sums of c, see time_block).
+    // (st[n][2], st[n][5] unused), where c_n = mu_2n / dc^2n, kc and hc are the
+    // coefficients of L_m in sum_n c_n L^(1)_2n and sum_n c_n L^(2)_2n (tail
+    // sums of c), and the entries 6..11 carry the factor gam_m of their L_m
+    // (see time_block).
     alignas(16) double st[kMaxTerms][12];
 };
 
@@ -285,14 +288,27 @@ SDEV void time_block(const Geom& g, int k, int m, TimeBlock& tb)
             hc += kc;
             tb.st[e][8] = hc;
             tb.st[e][10] = (2.0 * e + 1.0) * cn;
-            for (int h = 0; h < 2; ++h) {
-                const int j = 2 * e - 1 + h;
-                const double b = j >= 0 ? 1.0 / (j + 1.0) : 0.0;
-                tb.st[e][3 * h] = (2.0 * j + 1.0) * b;
-                tb.st[e][3 * h + 1] = b;
-                tb.st[e][3 * h + 2] = j * b;
-            }
         }
+        // Rescaled recurrence (one operation fewer per step): P_j = L_j / gam_j
+        // with gam_0 = gam_1 = 1 and gam_{j+1} = C_j gam_{j-1}, C_j = j/(j+1), so
+        // that P_{j+1} = (a_j - b_j z) P_j - P_{j-1} with
+        // a_j = (2j+1)/(j+1) gam_j/gam_{j+1}, b_j = 1/(j+1) gam_j/gam_{j+1}; the
+        // coefficients of the sums take the factor gam_m of their L_m.
+        double gjm1 = 1.0, gj = 1.0;                // gam_{j-1}, gam_j at j = 1
+        for (int e = 1; e < n; ++e) {
+            for (int h = 0; h < 2; ++h) {
+                const int j = 2 * e - 1 + h;            // step L_{j-1}, L_j -> L_{j+1}
+                const double b = 1.0 / (j + 1.0), gjp1 = j * b * gjm1;
+                tb.st[e][3 * h] = (2.0 * j + 1.0) * b * gj / gjp1;
+                tb.st[e][3 * h + 1] = b * gj / gjp1;
+                tb.st[e][3 * h + 2] = 0.0;
+                gjm1 = gj; gj = gjp1;
+            }
+            // gjm1 = gam_{2e}, gj = gam_{2e+1}
+            tb.st[e][6] *= gjm1; tb.st[e][8] *= gjm1; tb.st[e][11] *= gjm1;
+            tb.st[e][7] *= gj;   tb.st[e][9] *= gj;   tb.st[e][10] *= gj;
+        }
+        for (int c = 0; c < 6; ++c) tb.st[0][c] = 0.0;  // term 0 holds L_0 = 1, L_1 = 1 - z
     }
     for (int s = 0; s < tb.ndel; ++s) { tb.lnd[s] = log(tb.del[s]); tb.idel[s] = 1.0 / tb.del[s]; }
 }
@@ -313,8 +329,8 @@ SDEV SeriesVals series(const TimeBlock& tb, double a)
     double sv = s0[11], sk = s0[6] + s0[7] * l1, sd = s0[10] * l1, s2 = s0[8] + s0[9] * l1;
     for (int n = 1; n < tb.nterm; ++n) {
         const double* st = tb.st[n];        // advance to L_{2n}, L_{2n+1}
-        const double l2 = fma(fma(-st[1], z, st[0]), l1, -st[2] * l0);
-        const double l3 = fma(fma(-st[4], z, st[3]), l2, -st[5] * l1);
+        const double l2 = fma(fma(-st[1], z, st[0]), l1, -l0);
+        const double l3 = fma(fma(-st[4], z, st[3]), l2, -l1);
         if (NEED_V) sv = fma(st[11], l2, sv);
         if (NEED_K || NEED_H) sk = fma(st[7], l3, fma(st[6], l2, sk));
         if (NEED_D) sd = fma(st[10], l3, sd);
