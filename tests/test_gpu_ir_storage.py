@@ -3,10 +3,11 @@
 Assembled with precision STBEM_FP32_IR, V_h is stored as the float pair
 hi = fl32(V), lo = fl32(V - hi) and D_h as float; no FP64 copy of either is
 kept.  V_h is computed in FP64 everywhere; D_h in FP64 on touching time
-blocks and in FP32 arithmetic (float Laguerre series) on separated ones.  The
-pair must reproduce the oracle's V_h to the FP64 bar (it carries about 48
-bits), D_h's touching blocks to FP32 rounding and its separated blocks to
-1e-5 of the block maximum, and the refinement solve with only this
+blocks and in FP32 arithmetic (float Laguerre series, one Gauss point fewer
+per direction than the FP64 rule) on separated ones.  The pair must
+reproduce the oracle's V_h to the FP64 bar (it carries about 48 bits), D_h's
+touching blocks to FP32 rounding and its separated blocks to 1e-6 of the
+block maximum (measured 2.4e-7), and the refinement solve with only this
 storage must reach the oracle's solution within 1e-10.  Assembling V_h or D_h
 again in FP64 drops FP32 copies made from the old FP64 storage.
 """
@@ -59,7 +60,7 @@ def test_fp32_storage_entries(small_ir):
     assert e_pair <= 1e-12
     assert e_hi <= 1e-7
     assert e_d_near <= 2e-6
-    assert e_d_far <= 1e-5
+    assert e_d_far <= 1e-6
     # stored blocks stay exactly symmetric
     h = hi.cpu().numpy()
     assert np.array_equal(h, np.transpose(h, (0, 2, 1)))
