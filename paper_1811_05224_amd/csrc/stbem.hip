@@ -2804,8 +2804,9 @@ const char* stbem_last_error(const stbem_ctx* c) { return c ? c->err.c_str() : "
 // rewritten in y = 2a/A - 1, expanded in Chebyshev polynomials of y,
 // truncated where the dropped coefficients sum below tol |c_0|, and written
 // back in powers of y.  Returns the number of coefficients kept, 0 if more
-// than nmax would be needed.
-static int econ_poly(const long double* c, int n, long double A, int nmax, long double tol, double* out)
+// than kEconMax would be needed or the double polynomial, evaluated as the
+// kernels do, misses the series by more than 1e-15 of its leading term.
+static int econ_poly(const long double* c, int n, long double A, long double tol, double* out)
 {
     constexpr int N = kPolyMax;
     long double d[N + 1] = {}, B[N + 1] = {}, t[N + 1];
@@ -2832,7 +2833,7 @@ static int econ_poly(const long double* c, int n, long double A, int nmax, long 
     int K = n;
     long double drop = 0;
     while (K > 1 && drop + fabsl(B[K - 1]) < tol * fabsl(c[0])) { drop += fabsl(B[K - 1]); --K; }
-    if (K > nmax) return 0;
+    if (K > kEconMax) return 0;
     long double P[N + 1] = {}, Tm[N + 1] = {}, Tc[N + 1] = {}, Tn[N + 1];
     Tm[0] = 1; Tc[1] = 1;
     for (int i = 0; i <= N; ++i) P[i] = B[0] * Tm[i] + (K > 1 ? B[1] * Tc[i] : 0.0L);
@@ -2840,16 +2841,14 @@ static int econ_poly(const long double* c, int n, long double A, int nmax, long 
         for (int i = 0; i <= N; ++i) Tn[i] = (i > 0 ? 2 * Tc[i - 1] : 0.0L) - Tm[i];
         for (int i = 0; i <= N; ++i) { P[i] += B[k] * Tn[i]; Tm[i] = Tc[i]; Tc[i] = Tn[i]; }
     }
-    for (int i = 0; i < nmax; ++i) out[i] = i < K ? (double)P[i] : 0.0;
+    for (int i = 0; i < kEconMax; ++i) out[i] = i < K ? (double)P[i] : 0.0;
     // the double polynomial against the series, at 65 points of [0, A]
     const double es = (double)(2.0L / A);
     for (int q = 0; q <= 64; ++q) {
         const long double a = A * q / 64;
         long double ref = 0;
         for (int j = n - 1; j >= 0; --j) ref = ref * a + c[j];
-        const double y = std::fma((double)a, es, -1.0);
-        double got = out[nmax - 1];
-        for (int i = nmax - 2; i >= 0; --i) got = std::fma(got, y, out[i]);
+        const double got = m0_econ(out, std::fma((double)a, es, -1.0));    // as the kernels evaluate it
         if (fabsl((long double)got - ref) > 1e-15L * fabsl(c[0])) return 0;
     }
     return K;
@@ -3019,8 +3018,8 @@ int stbem_create(const stbem_problem* p, stbem_ctx** out)
             nn[k] = conv ? n : 0;      // not converged: the E1 path is used
             if (nn[k] > 0) {
                 es[k] = (double)(2.0L / amk);
-                if (!econ_poly(cl, n, amk, kEconMax, 1e-18L, &ce[(size_t)k * kEconMax]) ||
-                    !econ_poly(cdl, n, amk, kEconMax, 1e-18L, &cde[(size_t)k * kEconMax]))
+                if (!econ_poly(cl, n, amk, 1e-18L, &ce[(size_t)k * kEconMax]) ||
+                    !econ_poly(cdl, n, amk, 1e-18L, &cde[(size_t)k * kEconMax]))
                     nn[k] = 0;
             }
         }

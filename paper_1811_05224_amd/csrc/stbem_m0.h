@@ -118,13 +118,24 @@ SDEV double seg_tri_dist(const Piece& S, const Tri& tr)
 
 struct M0Orders { int qs_near, qt_near; double near_ratio, omax, q_tol, z_floor; };
 
-// Horner in y over the full zero-padded economised row (leading zeros leave
-// it unchanged), unrolled so that the coefficient loads are issued ahead
+// The economised row polynomial at y: Horner in y^8 over chunks of eight
+// coefficients, each chunk summed against the powers y^0 .. y^7 with the
+// coefficient as a factor of one FMA, so that the coefficients (the same for
+// all lanes) are used straight from their scalar loads.  Padding zeros at
+// the top leave the value unchanged.
+static_assert(kEconMax % 8 == 0, "economised rows come in chunks of eight");
 SDEV double m0_econ(const double* p, double y)
 {
-    double s = p[kEconMax - 1];
+    const double y2 = y * y, y3 = y2 * y, y4 = y2 * y2, y5 = y4 * y, y6 = y4 * y2, y7 = y4 * y3, y8 = y4 * y4;
+    double s = 0.0;
 #pragma unroll
-    for (int q = kEconMax - 2; q >= 0; --q) s = fma(s, y, p[q]);
+    for (int k = kEconMax / 8 - 1; k >= 0; --k) {
+        const double* c = p + 8 * k;
+        double t = c[7] * y7;
+        t = fma(c[6], y6, t); t = fma(c[5], y5, t); t = fma(c[4], y4, t);
+        t = fma(c[3], y3, t); t = fma(c[2], y2, t); t = fma(c[1], y, t);
+        s = fma(s, y8, t + c[0]);
+    }
     return s;
 }
 
