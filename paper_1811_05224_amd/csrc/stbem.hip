@@ -1009,7 +1009,7 @@ __global__ __launch_bounds__(kWG) void k_entries(Geom g, const Tables* __restric
 // M_h^0, pass 1: the three barycentric moments of every (row, triangle) pair
 // of a chunk of rows into scratch[row - row0][t][v].
 template <bool DERIV, bool FIRST, int PART = 0>
-__global__ __launch_bounds__(kWG) void k_m0_tri(Geom g, Mesh2 mesh, const Tables* __restrict__ Tg,
+__global__ __launch_bounds__(kWG, PART == 2 ? 3 : 1) void k_m0_tri(Geom g, Mesh2 mesh, const Tables* __restrict__ Tg,
                                                 const M0Tables* __restrict__ Dg, M0Orders MO, M0Poly PP,
                                                 long long row0, long long lrow0, int nchunk,
                                                 double* __restrict__ scratch)
