@@ -109,8 +109,10 @@ int stbem_sizes(const stbem_ctx* ctx, long long* n, int* n_bnd, int* n_t, int* n
  * precision = STBEM_FP32_IR: only STBEM_V and STBEM_D may be in `mask` (else
  *   STBEM_EINVAL; also refused in block-Toeplitz mode).  V_h is stored as the
  *   float pair hi = fl32(V), lo = fl32(V - hi) (about 48 bits together), D_h
- *   as float (D_h only shapes the preconditioner); 12 bytes per entry pair
- *   instead of 16.  The FP64 storage of these operators is freed, and
+ *   as float (D_h only shapes the preconditioner; its separated time blocks
+ *   are computed in FP32 arithmetic with one Gauss point fewer per direction
+ *   than in FP64, within about 3e-7 of the block maximum); 12 bytes per entry
+ *   pair instead of 16.  The FP64 storage of these operators is freed, and
  *   operators that need FP64 V_h or D_h (FP64 solves) are unavailable until
  *   they are assembled again in FP64.
  * Re-assembling an operator replaces its storage; assembling V_h or D_h in
