@@ -124,10 +124,12 @@ __global__ __launch_bounds__(kWG) void k_time_blocks(Geom g, long long nb, TimeB
 
 // The series data of separated time blocks for FP32 arithmetic (D_h's
 // far field in the FP32-storage mode): the same coefficients as the FP64
-// table (see TimeBlock), computed in FP64, truncated where p^(2n+2) < 1e-9
-// (ample for FP32 sums; the FP64 table runs to 1e-19) and stored as float.
-// nterm = 0 for blocks that are not series blocks.
-constexpr double kSeriesTol32 = 1e-9;
+// table (see TimeBlock), computed in FP64, truncated where p^(2n+2) < 1e-8
+// (by the bound at kSeriesTol, the tail stays below 1.7e-8 of the leading
+// coefficient: under FP32 rounding, 6e-8, and the FP32 far field's Gauss
+// rule, about 3e-7) and stored as float.  nterm = 0 for blocks that are not
+// series blocks.
+constexpr double kSeriesTol32 = 1e-8;
 struct TimeBlock32 {
     int nterm;
     float inv_dc;

@@ -46,6 +46,13 @@ constexpr double kInv2Pi = 0.15915494309189533577;    // 1/(2 pi)
 constexpr int kMaxGL = 16;       // largest Gauss-Legendre order in the tables
 constexpr int kMaxLog = 8;       // largest order of the -ln u rule
 constexpr int kMaxTerms = 40;    // series terms for separated time elements
+// Truncation of that series: terms n = 0..N are kept, N the first n >= 1 with
+// p^(2n+2) < kSeriesTol (p = sum of the half-lengths / centre lag).  As
+// |e^{-z} L^(b)_m(z)| <= C(m+b, m) e^{-z/2} and c_n <= 2 c_0 p^(2n) /
+// ((2n+1)(2n+2)) (equal steps), each omitted term of the b = 0, 1, 2 sums is
+// at most c_0 p^(2n) e^{-z/2}; the whole tail stays below 1.7 kSeriesTol of
+// the leading coefficient (p <= 0.62), under the FP64 rounding of the sums.
+constexpr double kSeriesTol = 1e-17;
 
 // Quadrature tables on [0,1]: gl_x[n][i], gl_w[n][i] for n = 1..kMaxGL,
 // and the n-point rule for int_0^1 f(u) (-ln u) du.
@@ -269,7 +276,7 @@ SDEV void time_block(const Geom& g, int k, int m, TimeBlock& tb)
         int n = 0;
         for (; n < kMaxTerms; ++n) {
             tb.st[n][11] = 2.0 * dc * dc * (pp - qq) / ((2.0 * n + 1.0) * (2.0 * n + 2.0));
-            if (n > 0 && pp < 1e-19) { ++n; break; }
+            if (n > 0 && pp < kSeriesTol) { ++n; break; }
             pp *= p2; qq *= q2;
         }
         tb.nterm = n;

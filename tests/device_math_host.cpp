@@ -1,12 +1,31 @@
 // Host build of the kernels' special functions (stbem_math.h is written
-// __host__ __device__ so that its arithmetic can be exercised on the CPU):
-// reads z values from stdin, writes z, E1(z), e^{-z} (from E1's path),
-// Ein(z) and exp_neg(z) with 17 significant digits.
+// __host__ __device__ so that its arithmetic can be exercised on the CPU).
+// Default mode: reads z values from stdin, writes z, E1(z), e^{-z} (from E1's
+// path), Ein(z) and exp_neg(z) with 17 significant digits.
+// "series" mode: reads lines t0 t1 t2 t3 a (time elements [t0, t1] and
+// [t2, t3], separated) and writes the series values of the block
+// (Delta F_V, Delta F_K, Delta F_D, d/da and d2/da2 of Delta F_V) and the
+// number of terms, or nan when the block is not a series block.
 #include "stbem_tables.h"
+#include <cmath>
 #include <cstdio>
+#include <cstring>
 
-int main()
+int main(int argc, char** argv)
 {
+    if (argc > 1 && std::strcmp(argv[1], "series") == 0) {
+        double t[4], a;
+        while (std::scanf("%lf %lf %lf %lf %lf", &t[0], &t[1], &t[2], &t[3], &a) == 5) {
+            stbem::Geom g = {};
+            g.nt = 3; g.alpha = 1.0; g.t = t;
+            static stbem::TimeBlock tb;
+            stbem::time_block(g, 2, 0, tb);
+            if (!tb.ser) { std::printf("nan nan nan nan nan 0\n"); continue; }
+            const stbem::SeriesVals r = stbem::series<true, true, true, true>(tb, a);
+            std::printf("%.17e %.17e %.17e %.17e %.17e %d\n", r.v, r.k, r.dd, r.va, r.vaa, tb.nterm);
+        }
+        return 0;
+    }
     static stbem::Tables T;
     stbem::build_tables(T);
     double z;

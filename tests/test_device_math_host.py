@@ -63,3 +63,57 @@ def test_ein_and_table_exponential(prog):
     big = ref < 1e-300
     assert np.all(e[big] < 1e-300)
     assert (np.abs(e[~big] - ref[~big]) / ref[~big]).max() < 4e-16
+
+
+def _lag_integral(kern, t, a):
+    """int over s of w(s) kern(s, a), w the overlap length of [t2, t3] and
+    [t0, t1] + s (the two time elements at lag s), by mpmath."""
+    import mpmath as mp
+    t0, t1, t2, t3 = (mp.mpf(float(v)) for v in t)
+    w = lambda s: max(mp.mpf(0), min(t3, t1 + s) - max(t2, t0 + s))
+    br = sorted({t2 - t1, t2 - t0, t3 - t1, t3 - t0})
+    return mp.quad(lambda s: w(s) * kern(s, mp.mpf(float(a))), br)
+
+
+def test_separated_block_series(prog):
+    """The series of separated time elements (Laguerre expansion about the
+    centre lag, truncated at kSeriesTol) against mpmath quadrature of the
+    five lag kernels with the trapezoid weight: equal steps at lags 2, 3, 5,
+    12 and 60, and unequal steps, for z = a / dc from 0 to 40.  Bar: 2e-15 of
+    the integral of |kernel| times e^{z/2} (the bound of e^{-z} L_n(z) that
+    also bounds the truncated tail).  Rounding sets the worst case (8.8e-16,
+    the same with the series cut at 1e-19); cut at 1e-13 it fails."""
+    import mpmath as mp
+    mp.mp.dps = 30
+    pi4 = 4 * mp.pi
+    kern = [lambda s, a: mp.exp(-a / s) / (pi4 * s),                  # Delta F_V
+            lambda s, a: a * mp.exp(-a / s) / s ** 2,                  # Delta F_K
+            lambda s, a: mp.exp(-a / s) * (a - s) / (pi4 * s ** 3),    # Delta F_D
+            lambda s, a: -mp.exp(-a / s) / (pi4 * s ** 2),             # d/da Delta F_V
+            lambda s, a: mp.exp(-a / s) / (pi4 * s ** 3)]              # d2/da2 Delta F_V
+    h = 1.0 / 256
+    blocks = [(0.0, h, d * h, (d + 1) * h) for d in (2, 3, 5, 12, 60)]
+    blocks += [(0.1, 0.14, 0.22, 0.24), (0.1, 0.11, 0.15, 0.17), (0.0, 0.02, 0.5, 0.53)]
+    cases = []
+    for t in blocks:
+        dc = 0.5 * (t[2] + t[3]) - 0.5 * (t[0] + t[1])
+        for z in (0.0, 1e-6, 0.3, 1.0, 2.5, 6.0, 15.0, 40.0):
+            cases.append((t, z * dc))
+    inp = "\n".join(" ".join(repr(float(v)) for v in (*t, a)) for t, a in cases)
+    out = subprocess.run([prog, "series"], input=inp, capture_output=True, text=True, check=True).stdout.split()
+    got = np.array(out, dtype=np.float64).reshape(-1, 6)
+    assert np.all(np.isfinite(got[:, :5])) and np.all(got[:, 5] >= 2)
+    worst = 0.0
+    for (t, a), row in zip(cases, got):
+        dc = 0.5 * (t[2] + t[3]) - 0.5 * (t[0] + t[1])
+        grow = float(mp.exp(a / dc / 2))
+        for q in range(5):
+            ref = _lag_integral(kern[q], t, a)
+            scale = _lag_integral(lambda s, aa: abs(kern[q](s, aa)), t, a) * grow
+            if scale == 0:
+                assert row[q] == 0.0
+                continue
+            err = float(abs(mp.mpf(row[q]) - ref) / scale)
+            worst = max(worst, err)
+            assert err <= 2e-15, (t, a, q, err)
+    print("worst scaled error", worst)
