@@ -43,9 +43,9 @@ FP32_PEAK_TFLOPS = 157.3
 # kernel changed after its counters were taken has no entry here.
 HBM_BYTES_PER_UNIT = {
     # precision workload, profiles/dfar_q3_precision_counters.md: FETCH_SIZE
-    # 165,303 KiB (x 2) and WRITE_SIZE 198,122,961 KiB per dispatch of
+    # 165,364 KiB (x 2) and WRITE_SIZE 196,418,614 KiB per dispatch of
     # 8.2248e9 D entries (the D, V and K entries written, FP64)
-    "k_assemble_dfar<3, true, true>": 24.71,
+    "k_assemble_dfar<3, true, true>": 24.50,
 }
 # bytes streamed per stored entry by the matrix-vector kernels
 GEMV_BYTES = {"k_gemv_n_vec<double>": 8, "k_gemv_t_vec<double>": 8, "k_gemv_n_vec<float hi+lo>": 8,

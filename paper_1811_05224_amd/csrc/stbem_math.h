@@ -111,8 +111,8 @@ struct Orders {
 
 // ------------------------------------------------------------------ E1
 // Ein(z) = sum_{n>=1} (-1)^{n+1} z^n/(n n!), entire; used for 0 <= z <= 2,
-// where 24 terms leave a tail below 1e-18 of the sum.  Evaluated in Horner
-// form, z (c_1 + z (c_2 + ...)), c_n = (-1)^{n+1}/(n n!): one FMA per term.
+// where 24 terms leave a tail below 1e-18 of the sum: z (c_1 + c_2 z + ...),
+// c_n = (-1)^{n+1}/(n n!).
 struct EinCoef { double c[24]; };
 constexpr EinCoef ein_coef()
 {
@@ -126,20 +126,29 @@ constexpr EinCoef ein_coef()
 }
 constexpr EinCoef kEin = ein_coef();
 
+// The terms from c_5 on are evaluated in chunks of four coefficients,
+// c0 + c1 z + (c2 + c3 z) z^2 each, joined by Horner in z^4, and the first
+// four by Horner on top of them: a dependent chain of about 12 operations
+// instead of 24, with the rounding of Horner's last steps.
 SDEV double ein(double z)
 {
-    double p = kEin.c[23];
+    const double z2 = z * z, z4 = z2 * z2;
+    const double* c = kEin.c;
+    double p = 0.0;
 #pragma unroll
-    for (int n = 22; n >= 0; --n) p = fma(p, z, kEin.c[n]);
+    for (int k = 5; k >= 1; --k)
+        p = fma(p, z4, fma(fma(c[4 * k + 3], z, c[4 * k + 2]), z2, fma(c[4 * k + 1], z, c[4 * k])));
+    p = fma(fma(fma(fma(p, z, c[3]), z, c[2]), z, c[1]), z, c[0]);
     return p * z;
 }
 
 // E1(z) for z > 0 (and, with EX, ex = e^{-z}): -gamma - ln z + Ein(z) for
 // z <= 2; on [2, 64) e^{-z} times a polynomial for e^z E1(z) per
-// half-octave (fitted with mpmath, relative error < 2.1e-16, Horner in the
-// local variable); beyond, the continued fraction
+// half-octave (fitted with mpmath, relative error < 2.1e-16, in the local
+// variable); beyond, the continued fraction
 // e^{-z}/(z+1 - 1^2/(z+3 - 2^2/(z+5 - ...))) evaluated from the tail.  The
 // exponential is shared with the caller.
+static_assert(kE1PolyN == 19, "e1t evaluates 4 chunks of 4 and one of 3 coefficients");
 template <bool EX>
 SDEV double e1t(double z, double& ex)
 {
@@ -157,10 +166,15 @@ SDEV double e1t(double z, double& ex)
         const double x = (z - lo * (1.0 + 0.5 * hh)) * (4.0 / lo) - 1.0;   // z - a exact
         const double* co = kE1Poly[2 * o + hh];
         // fixed length (shorter rows are zero-padded), unrolled so that the
-        // coefficient loads of the lane's interval issue ahead of the sum
-        double p = co[kE1PolyN - 1];
+        // coefficient loads of the lane's interval issue ahead of the sum;
+        // from co[4] on chunks of four joined by Horner in x^4, the first
+        // four by Horner on top (as in ein)
+        const double x2 = x * x, x4 = x2 * x2;
+        double p = fma(co[18], x2, fma(co[17], x, co[16]));
 #pragma unroll
-        for (int n = kE1PolyN - 2; n >= 0; --n) p = fma(p, x, co[n]);
+        for (int k = 3; k >= 1; --k)
+            p = fma(p, x4, fma(fma(co[4 * k + 3], x, co[4 * k + 2]), x2, fma(co[4 * k + 1], x, co[4 * k])));
+        p = fma(fma(fma(fma(p, x, co[3]), x, co[2]), x, co[1]), x, co[0]);
         return ex * p;
     }
     // the fraction's tail n^2/(z + 2n + 1 - ...) for n = 6 .. 1 carried as
