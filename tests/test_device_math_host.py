@@ -2,7 +2,8 @@
 (csrc/stbem_math.h is __host__ __device__), against SciPy and NumPy:
 E1 on its three branches (Ein series for z <= 2, half-octave polynomials on
 [2, 64), continued fraction beyond), Ein, and the table-driven exponential
-of the separated-block tiles.  The bound 4e-15 on z <= 2 comes from
+of the separated-block tiles; and the time integrals of separated (series)
+and touching (closed forms) blocks against mpmath quadrature.  The bound 4e-15 on z <= 2 comes from
 -gamma - ln z + Ein(z) near its smallest value; elsewhere a few ulp."""
 import os
 import shutil
@@ -116,4 +117,52 @@ def test_separated_block_series(prog):
             err = float(abs(mp.mpf(row[q]) - ref) / scale)
             worst = max(worst, err)
             assert err <= 2e-15, (t, a, q, err)
+    print("worst scaled error", worst)
+
+
+def test_touching_block_closed_forms(prog):
+    """The closed forms of touching time elements (four-point differences of
+    the antiderivatives, E1 on its three branches) against mpmath quadrature
+    of the lag kernels with the trapezoid weight: an element with itself and
+    two adjacent elements of equal and unequal length, z = a / h from 1e-3 to
+    60.  Bar: 1e-13 of the integral of |kernel|, with the floor of the
+    parity tests (1e-8 of the largest such integral over the block's z):
+    the differences cancel by about z^2 where e^{-z} is far below that floor
+    (2.4e-13 of the value at z = 60)."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    pi4 = 4 * mp.pi
+    kern = [lambda s, a: mp.exp(-a / s) / (pi4 * s),                  # Delta F_V
+            lambda s, a: a * mp.exp(-a / s) / s ** 2,                  # Delta F_K
+            lambda s, a: mp.exp(-a / s) * (a - s) / (pi4 * s ** 3),    # Delta F_D
+            lambda s, a: -a * mp.exp(-a / s) / (pi4 * s ** 2),         # d/dalpha Delta F_V, alpha = 1
+            lambda s, a: mp.exp(-a / s) * (a - s) / s ** 3]            # four-point sum of E1
+    blocks = [(0, 0.3, 0.32, 0.0), (1, 0.3, 0.32, 0.34), (1, 0.3, 0.31, 0.34)]
+    zs = (1e-3, 0.05, 0.5, 1.0, 2.5, 8.0, 30.0, 60.0)
+    cases = [(d, t0, t1, t2, z * (t1 - t0)) for d, t0, t1, t2 in blocks for z in zs]
+    inp = "\n".join("%d %r %r %r %r" % c for c in cases)
+    out = subprocess.run([prog, "touch"], input=inp, capture_output=True, text=True, check=True).stdout.split()
+    got = np.array(out, dtype=np.float64).reshape(-1, 5)
+    res = []
+    for (d, t0, t1, t2, a), row in zip(cases, got):
+        m0, m1 = mp.mpf(t0), mp.mpf(t1)
+        k0, k1 = (m0, m1) if d == 0 else (mp.mpf(t1), mp.mpf(t2))
+        am = mp.mpf(a)
+        w = lambda s: max(mp.mpf(0), min(k1, m1 + s) - max(k0, m0 + s))
+        corners = [v for v in (k0 - m1, k0 - m0, k1 - m1, k1 - m0) if v > 0]
+        # e^{-a/s} piles the integrand up against the largest lags when a is
+        # large: points graded toward every corner keep the quadrature exact
+        br = sorted({mp.mpf(0), am, 4 * am, *corners, *(c * (1 - mp.mpf(2) ** -j) for c in corners for j in range(1, 12))})
+        for q in range(5):
+            ref = mp.quad(lambda s: w(s) * kern[q](s, am), br)
+            scale = mp.quad(lambda s: w(s) * abs(kern[q](s, am)), br)
+            res.append(((d, t0, t1, t2), q, a, float(abs(mp.mpf(row[q]) - ref)), float(scale)))
+    top = {}
+    for blk, q, a, err, scale in res:
+        top[blk, q] = max(top.get((blk, q), 0.0), scale)
+    worst = 0.0
+    for blk, q, a, err, scale in res:
+        rel = err / max(scale, 1e-8 * top[blk, q])
+        worst = max(worst, rel)
+        assert rel <= 1e-13, (blk, q, a, rel)
     print("worst scaled error", worst)
