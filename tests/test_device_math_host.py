@@ -3,8 +3,9 @@
 E1 on its three branches (Ein series for z <= 2, half-octave polynomials on
 [2, 64), continued fraction beyond), Ein, and the table-driven exponential
 of the separated-block tiles; and the time integrals of separated (series)
-and touching (closed forms) blocks against mpmath quadrature.  The bound 4e-15 on z <= 2 comes from
--gamma - ln z + Ein(z) near its smallest value; elsewhere a few ulp."""
+and touching (closed forms) blocks against mpmath quadrature.  The E1
+bound 4e-15 on z <= 2 comes from -gamma - ln z + Ein(z) near its smallest
+value; elsewhere a few ulp."""
 import os
 import shutil
 import subprocess
